@@ -1,0 +1,373 @@
+/*
+ * hgoracle.c -- plain, single-threaded CPU oracle for the km1 label-propagation
+ * refinement core of "Scalable Shared-Memory Hypergraph Partitioning"
+ * (Gottesbueren, Heuer, Sanders, Schlag; arXiv 2010.10272).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path (the HIP library and
+ * its Python binding) may link, import or call this file.  Only the tests, the
+ * smoke check and the CPU-baseline leg of the benchmark use it.
+ *
+ * Every function below is the textbook definition written out, or the
+ * synchronous LP round taken step by step, with no blocking, fusion or
+ * incremental bookkeeping.  Pin counts, connectivity and block weights are
+ * recomputed from scratch from the partition whenever they are needed.  All
+ * arithmetic is integer (int32 ids and weights, int64 sums); the only floating
+ * point is the one double product that turns epsilon into L_max.
+ *
+ * Notation follows the paper (section "Preliminaries"):
+ *   H = (V, E, c, w): n vertices, m nets, vertex weights c, net weights w.
+ *   Net e is a set of pins; I(v) is the set of nets incident to v.
+ *   Pi: V -> {0..k-1} (blocks are 0-based here; the paper counts from 1).
+ *   Phi(e,i) = |e intersect V_i|, Lambda(e) = {i : Phi(e,i) > 0},
+ *   lambda(e) = |Lambda(e)|, km1 = sum_e (lambda(e)-1) w(e).
+ *
+ * Readings of points the paper leaves open (tie-break, approval order, ...)
+ * are listed where they are used and collected in the design notes.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_ERR_INVALID (-1)
+#define OR_ERR_UNSUPPORTED (-2)
+
+typedef struct {
+  int64_t eligible;       /* |E_r|: vertices eligible at round start          */
+  int64_t boundary;       /* |A_r|: eligible vertices that are boundary       */
+  int64_t candidates;     /* vertices whose best move passes the move rule    */
+  int64_t approved;       /* moves approved against L_max (= moves applied)   */
+  int64_t moved_pins;     /* sum of d(u) over moved u                         */
+  int64_t touched_nets;   /* nets holding at least one moved vertex           */
+  int64_t km1_delta;      /* km1(before) - km1(after), both recomputed        */
+  int64_t km1_after;      /* km1 after the round                              */
+  int64_t max_block_weight; /* max_i c(V_i) after the round                   */
+} or_round_stats;
+
+/* ------------------------------------------------------------------------ */
+/* Input checks (section "Preliminaries": nets are non-empty vertex subsets, */
+/* weights are positive).                                                    */
+/* ------------------------------------------------------------------------ */
+
+static int cmp_i32(const void* a, const void* b) {
+  int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+  return (x > y) - (x < y);
+}
+
+/* Returns OR_OK if (eptr, pins, c, w) is a valid weighted hypergraph:
+ * eptr[0] = 0, eptr[m] = P, every net non-empty, pins in [0,n), no vertex twice
+ * in one net (a net is a set), all weights > 0.  c or w may be NULL (unit). */
+int or_check_hypergraph(int32_t n, int32_t m, int64_t P, const int64_t* eptr,
+                        const int32_t* pins, const int32_t* c, const int32_t* w) {
+  if (n < 1 || m < 1 || P < m) return OR_ERR_INVALID;
+  if (eptr[0] != 0 || eptr[m] != P) return OR_ERR_INVALID;
+  int64_t maxlen = 0;
+  for (int32_t e = 0; e < m; ++e) {
+    if (eptr[e + 1] <= eptr[e]) return OR_ERR_INVALID; /* empty net */
+    if (eptr[e + 1] - eptr[e] > maxlen) maxlen = eptr[e + 1] - eptr[e];
+  }
+  for (int64_t p = 0; p < P; ++p)
+    if (pins[p] < 0 || pins[p] >= n) return OR_ERR_INVALID;
+  int32_t* tmp = (int32_t*)malloc(sizeof(int32_t) * (size_t)maxlen);
+  if (!tmp) return OR_ERR_INVALID;
+  int bad = 0;
+  for (int32_t e = 0; e < m && !bad; ++e) {
+    int64_t len = eptr[e + 1] - eptr[e];
+    memcpy(tmp, pins + eptr[e], sizeof(int32_t) * (size_t)len);
+    qsort(tmp, (size_t)len, sizeof(int32_t), cmp_i32);
+    for (int64_t j = 1; j < len; ++j)
+      if (tmp[j] == tmp[j - 1]) { bad = 1; break; }
+  }
+  free(tmp);
+  if (bad) return OR_ERR_INVALID;
+  if (c) for (int32_t v = 0; v < n; ++v) if (c[v] <= 0) return OR_ERR_INVALID;
+  if (w) for (int32_t e = 0; e < m; ++e) if (w[e] <= 0) return OR_ERR_INVALID;
+  return OR_OK;
+}
+
+int or_check_partition(int32_t n, const int32_t* part, int32_t k) {
+  if (k < 2) return OR_ERR_INVALID;
+  for (int32_t v = 0; v < n; ++v)
+    if (part[v] < 0 || part[v] >= k) return OR_ERR_INVALID;
+  return OR_OK;
+}
+
+static inline int64_t cw(const int32_t* c, int32_t v) { return c ? (int64_t)c[v] : 1; }
+static inline int64_t ww(const int32_t* w, int32_t e) { return w ? (int64_t)w[e] : 1; }
+
+/* ------------------------------------------------------------------------ */
+/* Incident nets I(v), listed in increasing net id.                          */
+/* ------------------------------------------------------------------------ */
+void or_incidence(int32_t n, int32_t m, const int64_t* eptr, const int32_t* pins,
+                  int64_t* vptr, int32_t* vnets) {
+  for (int32_t v = 0; v <= n; ++v) vptr[v] = 0;
+  for (int32_t e = 0; e < m; ++e)
+    for (int64_t p = eptr[e]; p < eptr[e + 1]; ++p) vptr[pins[p] + 1] += 1;
+  for (int32_t v = 0; v < n; ++v) vptr[v + 1] += vptr[v];
+  int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  for (int32_t v = 0; v < n; ++v) fill[v] = vptr[v];
+  for (int32_t e = 0; e < m; ++e) /* nets in increasing id => rows sorted */
+    for (int64_t p = eptr[e]; p < eptr[e + 1]; ++p) vnets[fill[pins[p]]++] = e;
+  free(fill);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pin counts Phi(e,i) = |{v in e : Pi(v) = i}|   (section "Preliminaries")  */
+/* ------------------------------------------------------------------------ */
+void or_pin_counts(int32_t m, const int64_t* eptr, const int32_t* pins,
+                   const int32_t* part, int32_t k, int32_t* phi) {
+  memset(phi, 0, sizeof(int32_t) * (size_t)m * (size_t)k);
+  for (int32_t e = 0; e < m; ++e)
+    for (int64_t p = eptr[e]; p < eptr[e + 1]; ++p)
+      phi[(int64_t)e * k + part[pins[p]]] += 1;
+}
+
+/* Connectivity set Lambda(e) = {i : Phi(e,i) > 0} as a bitset of ceil(k/32)
+ * words (bit i%32 of word i/32), and connectivity lambda(e) = |Lambda(e)|. */
+void or_connectivity(int32_t m, int32_t k, const int32_t* phi, int32_t* lambda,
+                     uint32_t* conn) {
+  int32_t wk = (k + 31) / 32;
+  for (int32_t e = 0; e < m; ++e) {
+    int32_t l = 0;
+    for (int32_t j = 0; j < wk; ++j) conn[(int64_t)e * wk + j] = 0;
+    for (int32_t i = 0; i < k; ++i) {
+      if (phi[(int64_t)e * k + i] > 0) {
+        l += 1;
+        conn[(int64_t)e * wk + i / 32] |= (uint32_t)1 << (i % 32);
+      }
+    }
+    lambda[e] = l;
+  }
+}
+
+/* Block weights c(V_i) = sum of c(v) over v with Pi(v) = i. */
+void or_block_weights(int32_t n, const int32_t* c, const int32_t* part, int32_t k,
+                      int64_t* W) {
+  for (int32_t i = 0; i < k; ++i) W[i] = 0;
+  for (int32_t v = 0; v < n; ++v) W[part[v]] += cw(c, v);
+}
+
+/* Connectivity metric (lambda - 1)(Pi) = sum_e (lambda(e) - 1) w(e). */
+int64_t or_km1(int32_t m, const int32_t* w, const int32_t* lambda) {
+  int64_t s = 0;
+  for (int32_t e = 0; e < m; ++e) s += (int64_t)(lambda[e] - 1) * ww(w, e);
+  return s;
+}
+
+/* L_max = (1 + eps) * ceil(c(V) / k) (section "Preliminaries").  Block weights
+ * are integers, so c(V_i) <= L_max is the same as c(V_i) <= floor(L_max). */
+int64_t or_lmax(int64_t total_weight, int32_t k, double eps) {
+  int64_t avg = (total_weight + k - 1) / k;
+  return (int64_t)floor((1.0 + eps) * (double)avg);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Gains (section "Parallel Gain Calculation"):                              */
+/*   b(u)   = w({e in I(u) : Phi(e, Pi(u)) = 1})                             */
+/*   p_i(u) = w({e in I(u) : Phi(e, V_i)  = 0})                              */
+/*   g_i(u) = b(u) - p_i(u)  for i != Pi(u);  g_{Pi(u)}(u) = 0 (moving a     */
+/*   vertex into its own block changes nothing).                             */
+/* gains: n*k row-major; benefit: n entries or NULL.                         */
+/* ------------------------------------------------------------------------ */
+void or_gains(int32_t n, const int64_t* vptr, const int32_t* vnets, const int32_t* w,
+              const int32_t* part, int32_t k, const int32_t* phi, int64_t* gains,
+              int64_t* benefit) {
+  int64_t* p = (int64_t*)malloc(sizeof(int64_t) * (size_t)k);
+  for (int32_t u = 0; u < n; ++u) {
+    int32_t a = part[u];
+    int64_t b = 0;
+    for (int32_t i = 0; i < k; ++i) p[i] = 0;
+    for (int64_t j = vptr[u]; j < vptr[u + 1]; ++j) {
+      int32_t e = vnets[j];
+      if (phi[(int64_t)e * k + a] == 1) b += ww(w, e);
+      for (int32_t i = 0; i < k; ++i)
+        if (phi[(int64_t)e * k + i] == 0) p[i] += ww(w, e);
+    }
+    for (int32_t i = 0; i < k; ++i)
+      gains[(int64_t)u * k + i] = (i == a) ? 0 : b - p[i];
+    if (benefit) benefit[u] = b;
+  }
+  free(p);
+}
+
+/* ------------------------------------------------------------------------ */
+/* One synchronous label-propagation round (section "Label Propagation"),   */
+/* re-specified for synchronous execution:                                   */
+/*  1. eligible set E (given), active set A = eligible boundary vertices;    */
+/*  2. for u in A: neighbouring blocks T(u) = union of Lambda(e) over I(u)   */
+/*     minus Pi(u); feasible F(u) = {i in T(u): c(V_i) + c(u) <= L_max};     */
+/*     best target by (gain desc, c(V_i) asc, i asc);                         */
+/*  3. u is a candidate if that gain is > 0, or = 0 and the move makes the    */
+/*     heavier side lighter: c(V_t) + c(u) < c(V_Pi(u));                      */
+/*  4. approval per target block t: candidates sorted by (gain desc, id asc),*/
+/*     the longest prefix whose weight fits c(V_t) + prefix <= L_max;         */
+/*  5. all approved moves are applied at once; Phi/lambda/c(V_i) are then    */
+/*     recomputed from scratch; the next eligible set is every pin of every  */
+/*     net that holds a moved vertex.                                         */
+/* All decisions read the round-start state only.                            */
+/* ------------------------------------------------------------------------ */
+
+typedef struct { int64_t gain; int32_t u; int32_t t; } or_cand;
+
+static int cmp_cand(const void* x, const void* y) {
+  const or_cand* a = (const or_cand*)x;
+  const or_cand* b = (const or_cand*)y;
+  if (a->t != b->t) return (a->t > b->t) - (a->t < b->t);
+  if (a->gain != b->gain) return (a->gain < b->gain) - (a->gain > b->gain); /* desc */
+  return (a->u > b->u) - (a->u < b->u);
+}
+
+int or_lp_round(int32_t n, int32_t m, const int64_t* eptr, const int32_t* pins,
+                const int64_t* vptr, const int32_t* vnets, const int32_t* c,
+                const int32_t* w, int32_t k, int64_t lmax, int32_t* part,
+                uint8_t* eligible, uint8_t* moved, or_round_stats* st) {
+  int32_t* phi = (int32_t*)malloc(sizeof(int32_t) * (size_t)m * (size_t)k);
+  int32_t* lambda = (int32_t*)malloc(sizeof(int32_t) * (size_t)m);
+  int64_t* W = (int64_t*)malloc(sizeof(int64_t) * (size_t)k);
+  int64_t* conn = (int64_t*)malloc(sizeof(int64_t) * (size_t)k);
+  int32_t* target = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  or_cand* cand = (or_cand*)malloc(sizeof(or_cand) * (size_t)n);
+  uint8_t* touched = (uint8_t*)malloc((size_t)m);
+  if (!phi || !lambda || !W || !conn || !target || !cand || !touched) return OR_ERR_INVALID;
+  memset(st, 0, sizeof(*st));
+
+  /* round-start state S_r */
+  or_pin_counts(m, eptr, pins, part, k, phi);
+  int32_t wk = (k + 31) / 32;
+  uint32_t* conn_bits = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)m * (size_t)wk);
+  or_connectivity(m, k, phi, lambda, conn_bits);
+  free(conn_bits);
+  or_block_weights(n, c, part, k, W);
+  int64_t km1_before = or_km1(m, w, lambda);
+
+  /* steps 1-3: select */
+  int64_t ncand = 0;
+  for (int32_t u = 0; u < n; ++u) {
+    target[u] = -1;
+    if (!eligible[u]) continue;
+    st->eligible += 1;
+    int boundary = 0;
+    for (int64_t j = vptr[u]; j < vptr[u + 1]; ++j)
+      if (lambda[vnets[j]] > 1) boundary = 1;
+    if (!boundary) continue;
+    st->boundary += 1;
+
+    int32_t a = part[u];
+    /* b(u) and, for every block, the weight of incident nets that already
+     * touch that block: p_i(u) = w(I(u)) - conn_i.  A block i is a
+     * neighbouring block iff some incident net has a pin in it. */
+    int64_t b = 0, wsum = 0;
+    for (int32_t i = 0; i < k; ++i) conn[i] = 0;
+    for (int64_t j = vptr[u]; j < vptr[u + 1]; ++j) {
+      int32_t e = vnets[j];
+      wsum += ww(w, e);
+      if (phi[(int64_t)e * k + a] == 1) b += ww(w, e);
+      for (int32_t i = 0; i < k; ++i)
+        if (phi[(int64_t)e * k + i] > 0) conn[i] += ww(w, e);
+    }
+    int32_t best = -1;
+    int64_t best_gain = 0;
+    for (int32_t i = 0; i < k; ++i) {
+      if (i == a || conn[i] == 0) continue;         /* not a neighbouring block */
+      if (W[i] + cw(c, u) > lmax) continue;         /* infeasible               */
+      int64_t g = b - (wsum - conn[i]);             /* b(u) - p_i(u)            */
+      if (best < 0 || g > best_gain || (g == best_gain && W[i] < W[best])) {
+        best = i;                                   /* ties on (g, W): lower i  */
+        best_gain = g;                              /* wins since i ascends     */
+      }
+    }
+    if (best < 0) continue;
+    int is_cand = best_gain > 0 || (best_gain == 0 && W[best] + cw(c, u) < W[a]);
+    if (!is_cand) continue;
+    cand[ncand].gain = best_gain;
+    cand[ncand].u = u;
+    cand[ncand].t = best;
+    ncand += 1;
+  }
+  st->candidates = ncand;
+
+  /* step 4: approval per target block, in (gain desc, id asc) order */
+  qsort(cand, (size_t)ncand, sizeof(or_cand), cmp_cand);
+  int64_t i0 = 0;
+  while (i0 < ncand) {
+    int32_t t = cand[i0].t;
+    int64_t i1 = i0;
+    while (i1 < ncand && cand[i1].t == t) ++i1;
+    int64_t load = W[t];
+    for (int64_t i = i0; i < i1; ++i) {
+      if (load + cw(c, cand[i].u) > lmax) break;   /* longest feasible prefix */
+      load += cw(c, cand[i].u);
+      target[cand[i].u] = t;
+    }
+    i0 = i1;
+  }
+
+  /* step 5: apply all approved moves at once */
+  memset(touched, 0, (size_t)m);
+  for (int32_t u = 0; u < n; ++u) {
+    moved[u] = 0;
+  }
+  for (int32_t u = 0; u < n; ++u) {
+    if (target[u] < 0) continue;
+    part[u] = target[u];
+    moved[u] = 1;
+    st->approved += 1;
+    st->moved_pins += vptr[u + 1] - vptr[u];
+    for (int64_t j = vptr[u]; j < vptr[u + 1]; ++j) touched[vnets[j]] = 1;
+  }
+  memset(eligible, 0, (size_t)n);
+  for (int32_t e = 0; e < m; ++e) {
+    if (!touched[e]) continue;
+    st->touched_nets += 1;
+    for (int64_t p = eptr[e]; p < eptr[e + 1]; ++p) eligible[pins[p]] = 1;
+  }
+
+  /* new state, recomputed from scratch */
+  or_pin_counts(m, eptr, pins, part, k, phi);
+  conn_bits = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)m * (size_t)wk);
+  or_connectivity(m, k, phi, lambda, conn_bits);
+  free(conn_bits);
+  or_block_weights(n, c, part, k, W);
+  st->km1_after = or_km1(m, w, lambda);
+  st->km1_delta = km1_before - st->km1_after;
+  st->max_block_weight = W[0];
+  for (int32_t i = 1; i < k; ++i) if (W[i] > st->max_block_weight) st->max_block_weight = W[i];
+
+  free(phi); free(lambda); free(W); free(conn); free(target); free(cand); free(touched);
+  return OR_OK;
+}
+
+/* Refinement driver: R synchronous rounds from the given partition, every
+ * vertex eligible in round 1 (section "Label Propagation": in the first round
+ * every boundary vertex may move; afterwards the movers and their neighbours).
+ * stats holds R records; rounds after convergence are recorded as empty.
+ * Returns the final km1 through *km1_out. */
+int or_refine(int32_t n, int32_t m, const int64_t* eptr, const int32_t* pins,
+              const int32_t* c, const int32_t* w, int32_t k, int64_t lmax,
+              int32_t rounds, int32_t* part, or_round_stats* stats, int64_t* km1_out) {
+  int64_t* vptr = (int64_t*)malloc(sizeof(int64_t) * ((size_t)n + 1));
+  int64_t P = eptr[m];
+  int32_t* vnets = (int32_t*)malloc(sizeof(int32_t) * (size_t)P);
+  uint8_t* eligible = (uint8_t*)malloc((size_t)n);
+  uint8_t* moved = (uint8_t*)malloc((size_t)n);
+  if (!vptr || !vnets || !eligible || !moved) return OR_ERR_INVALID;
+  or_incidence(n, m, eptr, pins, vptr, vnets);
+  memset(eligible, 1, (size_t)n);
+  int rc = OR_OK;
+  for (int32_t r = 0; r < rounds && rc == OR_OK; ++r)
+    rc = or_lp_round(n, m, eptr, pins, vptr, vnets, c, w, k, lmax, part, eligible,
+                     moved, &stats[r]);
+  if (rc == OR_OK) {
+    int32_t* phi = (int32_t*)malloc(sizeof(int32_t) * (size_t)m * (size_t)k);
+    int32_t* lambda = (int32_t*)malloc(sizeof(int32_t) * (size_t)m);
+    uint32_t* conn_bits =
+        (uint32_t*)malloc(sizeof(uint32_t) * (size_t)m * (size_t)((k + 31) / 32));
+    or_pin_counts(m, eptr, pins, part, k, phi);
+    or_connectivity(m, k, phi, lambda, conn_bits);
+    *km1_out = or_km1(m, w, lambda);
+    free(phi); free(lambda); free(conn_bits);
+  }
+  free(vptr); free(vnets); free(eligible); free(moved);
+  return rc;
+}
