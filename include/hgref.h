@@ -1,0 +1,224 @@
+/*
+ * hgref.h -- C ABI of the MI355X (gfx950) km1 label-propagation refinement
+ * core: pin counts, connectivity, km1, k-way move gains and synchronous,
+ * deterministic label-propagation rounds on a hypergraph.
+ *
+ * Paper: Gottesbueren, Heuer, Sanders, Schlag, "Scalable Shared-Memory
+ * Hypergraph Partitioning" (arXiv 2010.10272).  The operations follow its
+ * problem statement (section "Preliminaries"), its gain definitions (section
+ * "Parallel Gain Calculation", subsections "Data Structures for Gain
+ * Calculation" and "Attributed Gains") and its label-propagation refinement
+ * (section "Label Propagation"), re-specified as synchronous rounds.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All arrays are DEVICE memory owned by the caller (for example PyTorch
+ *   tensors).  The library never allocates or frees device memory; scratch
+ *   space comes from the caller's workspace (hg_workspace_size).  Buffers
+ *   must stay alive until the work queued on `stream` has completed and, for
+ *   the arrays a graph handle borrows, until hg_free.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Calls
+ *   only enqueue work and return, except hg_load_csr and hg_sync_status,
+ *   which synchronize the stream.
+ * - Integers only.  Vertex ids, net ids, block ids, vertex and net weights and
+ *   pin counts are int32; offsets, block weights, gains and km1 are int64.
+ *   Blocks are numbered 0..k-1 (the paper numbers them 1..k).
+ * - Supported sizes: 1 <= n, m < 2^31; m <= P < 2^31 pins; 2 <= k <= 256;
+ *   positive weights; total net weight sum_e w(e) < 2^31 and total vertex
+ *   weight < 2^62.  Larger values return HG_ERR_UNSUPPORTED.
+ * - Errors: every call returns an hg_status.  Host-side argument checks run
+ *   before anything is enqueued; on failure nothing is enqueued and
+ *   hg_last_error() describes the problem.  Values read from device arrays
+ *   (partition ids) are checked on the device: an out-of-range value is
+ *   skipped, never used as an index, and raises a flag that hg_sync_status
+ *   reports.  A device fault surfaces as HG_ERR_DEVICE at the next call that
+ *   synchronizes.
+ * - Results are deterministic: the same inputs give bit-identical outputs,
+ *   whatever the order in which the GPU runs its work items.
+ */
+#ifndef HGREF_H
+#define HGREF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hg_status;
+#define HG_OK 0
+#define HG_ERR_INVALID (-1)      /* malformed input (null pointer, bad CSR, ...) */
+#define HG_ERR_UNSUPPORTED (-2)  /* valid but outside the supported sizes        */
+#define HG_ERR_DEVICE (-3)       /* a HIP runtime call failed                    */
+#define HG_ERR_WORKSPACE (-4)    /* workspace too small for this n, m, P or k    */
+
+#define HG_MAX_K 256
+
+/* Opaque host object describing one loaded hypergraph.  It borrows the
+ * caller's device arrays (net CSR, weights, incidence CSR, workspace) and
+ * holds a few host-side facts about them (sizes, total weights, degree
+ * classes).  Not thread-safe: one handle is used by one host thread. */
+typedef struct hg_graph_s* hg_graph;
+
+/* One record per label-propagation round, written to DEVICE memory.
+ * Counts refer to the round-start state S_r (section "Label Propagation"). */
+typedef struct {
+  int64_t eligible;              /* vertices eligible in this round                 */
+  int64_t boundary;              /* eligible vertices incident to a cut net         */
+  int64_t candidates;            /* vertices whose best move passes the move rule   */
+  int64_t approved;              /* moves approved against L_max and applied        */
+  int64_t moved_pins;            /* sum of d(u) over moved vertices                 */
+  int64_t touched_nets;          /* nets holding at least one moved vertex          */
+  int64_t km1_delta;             /* attributed km1 reduction of the round           */
+  int64_t km1_after;             /* km1 after the round                             */
+  int64_t max_block_weight;      /* max_i c(V_i) after the round                    */
+  int64_t km1_delta_recomputed;  /* sum over touched nets of (lambda_old -
+                                    lambda_new) * w(e); equals km1_delta           */
+} hg_round_stats;
+
+/* Static facts about a loaded hypergraph (host memory). */
+typedef struct {
+  int32_t n, m;
+  int64_t P;
+  int64_t total_vertex_weight;   /* c(V)                                            */
+  int64_t total_net_weight;      /* w(E)                                            */
+  int32_t max_degree;            /* max_v d(v)                                      */
+  int32_t max_net_size;          /* max_e |e|                                       */
+  int32_t max_incident_weight;   /* max_v w(I(v)), an upper bound of every gain     */
+  int32_t heavy_vertices;        /* vertices with w(I(v)) > 255 (wavefront path)    */
+} hg_graph_info;
+
+/* Number of 32-bit words per net in the net-state array for a given k:
+ * 2 + 2*ceil(k/32) rounded up to a power of two (4, 8, 16 or 32).  Returns 0
+ * for an unsupported k.
+ *
+ * Net-state layout (uint32 netstate[m * hg_net_words(k)], row e):
+ *   word 0                 w(e), the net weight (copied at pin-count time)
+ *   word 1                 lambda(e) = |Lambda(e)|
+ *   words 2 .. 2+W-1       Lambda(e) as a bitset: bit i%32 of word 2+i/32 is
+ *                          set iff Phi(e,i) > 0          (W = ceil(k/32))
+ *   words 2+W .. 2+2W-1    S(e): bit i set iff Phi(e,i) == 1 (blocks holding
+ *                          exactly one pin of e; b(u) needs only this)
+ *   remaining words        zero
+ * The paper keeps Phi(e,i) and Lambda(e) per net in its partition data
+ * structure (subsection "Data Structures for Gain Calculation"); this packs
+ * what a gain computation reads for one net into one aligned record. */
+int32_t hg_net_words(int32_t k);
+
+/* Bytes of device workspace needed for a hypergraph with n vertices, m nets
+ * and P pins, refined with any k <= k_max.  0 if the sizes are unsupported. */
+size_t hg_workspace_size(int32_t n, int32_t m, int64_t P, int32_t k_max);
+
+/* Load a hypergraph given as net CSR and build its incidence CSR
+ * (section "Preliminaries": nets are vertex sets, I(v) the incident nets).
+ *   eptr   int64[m+1]   offsets into pins; eptr[0] = 0, eptr[m] = P
+ *   pins   int32[P]     pins of net e at pins[eptr[e] .. eptr[e+1])
+ *   vwgt   int32[n]     vertex weights c(v) > 0, or NULL for unit weights
+ *   ewgt   int32[m]     net weights w(e) > 0, or NULL for unit weights
+ *   vptr   int64[n+1]   OUT: incidence offsets
+ *   vnets  int32[P]     OUT: I(v) at vnets[vptr[v] .. vptr[v+1]), increasing
+ *   workspace, ws_bytes caller scratch of at least
+ *                       hg_workspace_size(n, m, P, k_max) bytes
+ *   k_max               largest k later calls will use (2..256)
+ * Checks (on the device, always): eptr increasing with eptr[0] = 0 and
+ * eptr[m] = P (no empty net), pins in [0,n), no vertex twice in a net,
+ * weights > 0, total net weight < 2^31.  Single-pin nets are allowed.
+ * Synchronizes `stream` (twice) and returns HG_ERR_INVALID or
+ * HG_ERR_UNSUPPORTED on bad input, with *out left NULL.  The handle borrows
+ * eptr, pins, vwgt, ewgt, vptr, vnets and workspace. */
+hg_status hg_load_csr(int32_t n, int32_t m, int64_t P, const int64_t* eptr,
+                      const int32_t* pins, const int32_t* vwgt, const int32_t* ewgt,
+                      int64_t* vptr, int32_t* vnets, void* workspace, size_t ws_bytes,
+                      int32_t k_max, void* stream, hg_graph* out);
+
+/* Release the host handle (device arrays stay with the caller). */
+void hg_free(hg_graph g);
+
+/* Copy the static facts gathered by hg_load_csr into *info. */
+hg_status hg_get_info(hg_graph g, hg_graph_info* info);
+
+/* L_max = (1 + eps) * ceil(c(V) / k) (section "Preliminaries"), as the
+ * integer floor((1 + eps) * ceil(c(V)/k)) computed in IEEE double; block
+ * weights are integers, so c(V_i) <= L_max is the same test.  Requires
+ * 0 < eps < 1.  Returns -1 on bad arguments. */
+int64_t hg_max_block_weight(hg_graph g, int32_t k, double eps);
+
+/* Pin counts Phi(e,i), connectivity sets and block weights from a partition
+ * (section "Preliminaries").
+ *   part      int32[n]        block of every vertex, in [0,k)
+ *   phi       int32[m*k]      OUT: Phi(e,i) at phi[e*k + i]
+ *   netstate  uint32[m*hg_net_words(k)]  OUT: per-net record (see above)
+ *   block_w   int64[k]        OUT: c(V_i)
+ *   km1_out   int64[1] or NULL OUT: sum_e (lambda(e) - 1) w(e)
+ * Each net is counted by one group of lanes, so no atomics touch Phi. */
+hg_status hg_compute_pincounts(hg_graph g, int32_t k, const int32_t* part, int32_t* phi,
+                               uint32_t* netstate, int64_t* block_w, int64_t* km1_out,
+                               void* stream);
+
+/* Connectivity metric km1 = sum_e (lambda(e) - 1) w(e) (section
+ * "Preliminaries") from a net-state array; int64 result in km1_out[0]. */
+hg_status hg_km1(hg_graph g, int32_t k, const uint32_t* netstate, int64_t* km1_out,
+                 void* stream);
+
+/* All k-way move gains (section "Parallel Gain Calculation"):
+ *   b(u)   = w({e in I(u) : Phi(e, Pi(u)) = 1})
+ *   p_i(u) = w({e in I(u) : Phi(e, i) = 0})
+ *   gains[u*k + i] = b(u) - p_i(u) for i != Pi(u), and 0 for i = Pi(u)
+ *   benefit[u] = b(u) (int64[n], may be NULL)
+ * part and netstate must describe the same partition (hg_compute_pincounts
+ * or a sequence of hg_lp_round calls establishes that). */
+hg_status hg_gains(hg_graph g, int32_t k, const int32_t* part, const uint32_t* netstate,
+                   int64_t* gains, int64_t* benefit, void* stream);
+
+/* One synchronous label-propagation round (section "Label Propagation",
+ * re-specified as select / approve / apply on the round-start state):
+ *  1. eligible vertices (eligible[v] != 0) that touch a cut net are active;
+ *  2. each active u picks, among neighbouring blocks i (some net of I(u) has
+ *     a pin in i) with c(V_i) + c(u) <= max_block_w, the best by (gain desc,
+ *     c(V_i) asc, i asc); it is a candidate if that gain is > 0, or 0 with
+ *     c(V_t) + c(u) < c(V_Pi(u));
+ *  3. per target block t, candidates in (gain desc, vertex id asc) order are
+ *     approved as the longest prefix with c(V_t) + prefix weight <= L_max;
+ *  4. approved moves are applied at once: part, phi (integer atomics),
+ *     netstate of every touched net and block_w are updated, *km1 drops by
+ *     the attributed gain (subsection "Attributed Gains");
+ *  5. eligible is rewritten to mark every pin of every net holding a moved
+ *     vertex (the movers and their neighbours), and moved[v] = 1 for movers.
+ *   part, phi, netstate, block_w  in/out state of one partition (consistent)
+ *   eligible uint8[n]     in/out; set all to 1 before the first round
+ *   moved    uint8[n]     OUT, or NULL
+ *   km1      int64[1]     in/out: km1 of the state before/after the round
+ *   stats    hg_round_stats[1]  OUT (device)
+ * max_block_w is L_max (hg_max_block_weight). */
+hg_status hg_lp_round(hg_graph g, int32_t k, int64_t max_block_w, int32_t* part,
+                      int32_t* phi, uint32_t* netstate, int64_t* block_w,
+                      uint8_t* eligible, uint8_t* moved, int64_t* km1,
+                      hg_round_stats* stats, void* stream);
+
+/* Refinement driver: hg_compute_pincounts from `part`, every vertex
+ * eligible, then `rounds` label-propagation rounds with
+ * L_max = hg_max_block_weight(g, k, eps).  Rounds after convergence record
+ * zero moves.  part is refined in place; phi, netstate, block_w and eligible
+ * are caller buffers used as state and hold the final state on return;
+ * stats[rounds] (device) receives one record per round; km1_out[0] (device)
+ * the final km1.  use_graph != 0 records the rounds once into a hipGraph and
+ * replays it (the record is kept in the handle and reused while the same
+ * buffers, k and round count are passed). */
+hg_status hg_refine(hg_graph g, int32_t k, double eps, int32_t rounds, int32_t* part,
+                    int32_t* phi, uint32_t* netstate, int64_t* block_w, uint8_t* eligible,
+                    hg_round_stats* stats, int64_t* km1_out, int32_t use_graph,
+                    void* stream);
+
+/* Synchronize `stream`, then report HG_ERR_INVALID if a device-side check
+ * (a partition id outside [0,k)) fired since the last call, HG_ERR_DEVICE
+ * if the stream reported an error, HG_OK otherwise.  Clears the flag. */
+hg_status hg_sync_status(hg_graph g, void* stream);
+
+/* Message for the last non-OK status returned on this host thread. */
+const char* hg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HGREF_H */

@@ -1,0 +1,350 @@
+// hg_api.hip -- the C ABI declared in include/hgref.h: argument checks,
+// workspace carving, launch sequencing and the recorded refinement graph.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "hg_internal.h"
+
+namespace hg {
+hipError_t load_sort_big(hg_graph_s* g, int big_rows, hipStream_t s);
+}
+
+namespace {
+
+thread_local char g_msg[512] = "";
+
+hg_status fail(hg_status code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_msg, sizeof(g_msg), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+hg_status hip_fail(hipError_t e, const char* what) {
+  return fail(HG_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HG_TRY(expr, what)                       \
+  do {                                           \
+    hipError_t _e = (expr);                      \
+    if (_e != hipSuccess) return hip_fail(_e, what); \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+constexpr long long kMaxPins = 0x7fffffffLL;
+
+const char* describe_err(int err) {
+  if (err & hg::kErrCsr) return "net offsets must increase strictly from 0 to P (no empty net)";
+  if (err & hg::kErrPin) return "a pin lies outside [0, n)";
+  if (err & hg::kErrWeight) return "vertex and net weights must be positive";
+  if (err & hg::kErrDuplicate) return "a vertex appears twice in one net (nets are sets)";
+  if (err & hg::kErrPart) return "a partition id lies outside [0, k)";
+  return "invalid input";
+}
+
+hg_status check_k(hg_graph g, int k) {
+  if (!g) return fail(HG_ERR_INVALID, "graph handle is NULL");
+  if (k < 2) return fail(HG_ERR_INVALID, "k must be at least 2 (got %d)", k);
+  if (k > HG_MAX_K) return fail(HG_ERR_UNSUPPORTED, "k must be at most %d (got %d)", HG_MAX_K, k);
+  if (k > g->k_max)
+    return fail(HG_ERR_WORKSPACE, "k = %d exceeds the k_max = %d the workspace was sized for", k,
+                g->k_max);
+  return HG_OK;
+}
+
+hg_status read_info(hg_graph_s* g, hipStream_t s) {
+  HG_TRY(hipMemcpyAsync(&g->info, g->ws + g->lay.info, sizeof(hg::LoadInfo),
+                        hipMemcpyDeviceToHost, s),
+         "hipMemcpyAsync");
+  HG_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  return HG_OK;
+}
+
+}  // namespace
+
+namespace hg {
+
+WsLayout ws_layout(int n, int m, long long P, int k_max) {
+  (void)P;
+  WsLayout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off = align256(off + bytes);
+    return at;
+  };
+  L.num_tiles = (int)(((long long)n + kTile - 1) / kTile);
+  L.scan_blocks = (int)(((long long)n + kBlock * 8 - 1) / (kBlock * 8));
+  L.cand = take(sizeof(long long) * (size_t)n);
+  L.touched = take(sizeof(unsigned) * (((size_t)m + 31) / 32));
+  L.tlist = take(sizeof(int) * 2 * (size_t)m);
+  L.heavy = take(sizeof(int) * (size_t)n);
+  L.big = take(sizeof(int) * (size_t)n);
+  L.hist = take(sizeof(unsigned long long) * (size_t)k_max * kBuckets);
+  L.overflow = take(sizeof(int) * (size_t)k_max);
+  L.thr = take(sizeof(Threshold) * (size_t)k_max);
+  L.tilesum = take(sizeof(long long) * (size_t)k_max * (size_t)L.num_tiles);
+  L.ctr = take(sizeof(RoundCounters));
+  L.info = take(sizeof(LoadInfo));
+  L.scan = take(sizeof(long long) * (size_t)L.scan_blocks);
+  L.flags = take(256);
+  L.total = off;
+  return L;
+}
+
+}  // namespace hg
+
+extern "C" {
+
+int32_t hg_net_words(int32_t k) { return hg::net_words(k); }
+
+size_t hg_workspace_size(int32_t n, int32_t m, int64_t P, int32_t k_max) {
+  if (n < 1 || m < 1 || P < m || P > kMaxPins || k_max < 2 || k_max > HG_MAX_K) return 0;
+  return hg::ws_layout(n, m, P, k_max).total;
+}
+
+const char* hg_last_error(void) { return g_msg; }
+
+hg_status hg_load_csr(int32_t n, int32_t m, int64_t P, const int64_t* eptr, const int32_t* pins,
+                      const int32_t* vwgt, const int32_t* ewgt, int64_t* vptr, int32_t* vnets,
+                      void* workspace, size_t ws_bytes, int32_t k_max, void* stream,
+                      hg_graph* out) {
+  if (!out) return fail(HG_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (n < 1 || m < 1) return fail(HG_ERR_INVALID, "need n >= 1 and m >= 1 (got %d, %d)", n, m);
+  if (P < m) return fail(HG_ERR_INVALID, "P = %lld pins cannot fill m = %d non-empty nets",
+                         (long long)P, m);
+  if (P > kMaxPins) return fail(HG_ERR_UNSUPPORTED, "P = %lld exceeds 2^31 - 1", (long long)P);
+  if (k_max < 2 || k_max > HG_MAX_K)
+    return fail(HG_ERR_UNSUPPORTED, "k_max must lie in [2, %d] (got %d)", HG_MAX_K, k_max);
+  if (!eptr || !pins || !vptr || !vnets || !workspace)
+    return fail(HG_ERR_INVALID, "eptr, pins, vptr, vnets and workspace must be non-NULL");
+  hg::WsLayout lay = hg::ws_layout(n, m, P, k_max);
+  if (ws_bytes < lay.total)
+    return fail(HG_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu needed",
+                ws_bytes, lay.total);
+  hipStream_t s = (hipStream_t)stream;
+  hg_graph_s* g = new (std::nothrow) hg_graph_s();
+  if (!g) return fail(HG_ERR_INVALID, "out of host memory");
+  g->n = n;
+  g->m = m;
+  g->P = P;
+  g->eptr = (const long long*)eptr;
+  g->pins = pins;
+  g->vwgt = vwgt;
+  g->ewgt = ewgt;
+  g->vptr = (long long*)vptr;
+  g->vnets = vnets;
+  g->ws = (char*)workspace;
+  g->ws_bytes = ws_bytes;
+  g->k_max = k_max;
+  g->lay = lay;
+  g->graph_exec = nullptr;
+  g->cap_stream = nullptr;
+  auto bail = [&](hg_status st) {
+    delete g;
+    return st;
+  };
+  hipError_t e = hg::load_check(g, s);
+  if (e != hipSuccess) return bail(hip_fail(e, "load checks"));
+  hg_status st = read_info(g, s);
+  if (st != HG_OK) return bail(st);
+  if (g->info.err) return bail(fail(HG_ERR_INVALID, "%s", describe_err(g->info.err)));
+  if (g->info.total_net_weight > 0x7fffffffULL)
+    return bail(fail(HG_ERR_UNSUPPORTED, "total net weight %llu exceeds 2^31 - 1",
+                     g->info.total_net_weight));
+  if (g->info.total_vertex_weight > (1ULL << 62))
+    return bail(fail(HG_ERR_UNSUPPORTED, "total vertex weight exceeds 2^62"));
+  e = hg::load_build(g, s);
+  if (e != hipSuccess) return bail(hip_fail(e, "incidence build"));
+  st = read_info(g, s);
+  if (st != HG_OK) return bail(st);
+  e = hg::load_sort_big(g, g->info.big_rows, s);
+  if (e != hipSuccess) return bail(hip_fail(e, "incidence sort"));
+  // zero the round state kept in the workspace
+  char* ws = g->ws;
+  e = hg::fill_i32((int*)(ws + lay.touched), 0, ((long long)m + 31) / 32, s);
+  if (e == hipSuccess)
+    e = hg::fill_i64((long long*)(ws + lay.hist), 0, (long long)k_max * hg::kBuckets, s);
+  if (e == hipSuccess) e = hg::fill_i32((int*)(ws + lay.overflow), 0, k_max, s);
+  if (e == hipSuccess)
+    e = hg::fill_i32((int*)(ws + lay.ctr), 0, sizeof(hg::RoundCounters) / sizeof(int), s);
+  if (e == hipSuccess) e = hg::fill_i32((int*)(ws + lay.flags), 0, 64, s);
+  if (e != hipSuccess) return bail(hip_fail(e, "workspace init"));
+  st = read_info(g, s);
+  if (st != HG_OK) return bail(st);
+  if (g->info.err) return bail(fail(HG_ERR_INVALID, "%s", describe_err(g->info.err)));
+  *out = g;
+  return HG_OK;
+}
+
+void hg_free(hg_graph g) {
+  if (!g) return;
+  if (g->graph_exec) (void)hipGraphExecDestroy((hipGraphExec_t)g->graph_exec);
+  if (g->cap_stream) (void)hipStreamDestroy((hipStream_t)g->cap_stream);
+  delete g;
+}
+
+hg_status hg_get_info(hg_graph g, hg_graph_info* info) {
+  if (!g || !info) return fail(HG_ERR_INVALID, "graph handle or info is NULL");
+  info->n = g->n;
+  info->m = g->m;
+  info->P = g->P;
+  info->total_vertex_weight = (int64_t)g->info.total_vertex_weight;
+  info->total_net_weight = (int64_t)g->info.total_net_weight;
+  info->max_degree = g->info.max_degree;
+  info->max_net_size = g->info.max_net_size;
+  info->max_incident_weight = g->info.max_incident_weight;
+  info->heavy_vertices = g->info.heavy_count;
+  return HG_OK;
+}
+
+int64_t hg_max_block_weight(hg_graph g, int32_t k, double eps) {
+  if (!g || k < 2 || !(eps > 0.0 && eps < 1.0)) return -1;
+  const long long W = (long long)g->info.total_vertex_weight;
+  const long long avg = (W + k - 1) / k;
+  return (int64_t)floor((1.0 + eps) * (double)avg);
+}
+
+hg_status hg_compute_pincounts(hg_graph g, int32_t k, const int32_t* part, int32_t* phi,
+                               uint32_t* netstate, int64_t* block_w, int64_t* km1_out,
+                               void* stream) {
+  hg_status st = check_k(g, k);
+  if (st != HG_OK) return st;
+  if (!part || !phi || !netstate || !block_w)
+    return fail(HG_ERR_INVALID, "part, phi, netstate and block_w must be non-NULL");
+  HG_TRY(hg::launch_pincounts(g, k, part, phi, netstate, (long long*)block_w, (long long*)km1_out,
+                              (hipStream_t)stream),
+         "pin counts");
+  return HG_OK;
+}
+
+hg_status hg_km1(hg_graph g, int32_t k, const uint32_t* netstate, int64_t* km1_out,
+                 void* stream) {
+  hg_status st = check_k(g, k);
+  if (st != HG_OK) return st;
+  if (!netstate || !km1_out) return fail(HG_ERR_INVALID, "netstate and km1_out must be non-NULL");
+  HG_TRY(hg::launch_km1(g, k, netstate, (long long*)km1_out, (hipStream_t)stream), "km1");
+  return HG_OK;
+}
+
+hg_status hg_gains(hg_graph g, int32_t k, const int32_t* part, const uint32_t* netstate,
+                   int64_t* gains, int64_t* benefit, void* stream) {
+  hg_status st = check_k(g, k);
+  if (st != HG_OK) return st;
+  if (!part || !netstate || !gains)
+    return fail(HG_ERR_INVALID, "part, netstate and gains must be non-NULL");
+  HG_TRY(hg::launch_gains(g, k, part, netstate, (long long*)gains, (long long*)benefit,
+                          (hipStream_t)stream),
+         "gains");
+  return HG_OK;
+}
+
+hg_status hg_lp_round(hg_graph g, int32_t k, int64_t max_block_w, int32_t* part, int32_t* phi,
+                      uint32_t* netstate, int64_t* block_w, uint8_t* eligible, uint8_t* moved,
+                      int64_t* km1, hg_round_stats* stats, void* stream) {
+  hg_status st = check_k(g, k);
+  if (st != HG_OK) return st;
+  if (!part || !phi || !netstate || !block_w || !eligible || !km1 || !stats)
+    return fail(HG_ERR_INVALID,
+                "part, phi, netstate, block_w, eligible, km1 and stats must be non-NULL");
+  if (max_block_w < 0) return fail(HG_ERR_INVALID, "max_block_w must be >= 0");
+  HG_TRY(hg::launch_lp_round(g, k, max_block_w, part, phi, netstate, (long long*)block_w,
+                             eligible, moved, (long long*)km1, stats, (hipStream_t)stream),
+         "label-propagation round");
+  return HG_OK;
+}
+
+static hipError_t enqueue_refine(hg_graph g, int k, long long lmax, int rounds, int32_t* part,
+                                 int32_t* phi, uint32_t* netstate, int64_t* block_w,
+                                 uint8_t* eligible, hg_round_stats* stats, int64_t* km1,
+                                 hipStream_t s) {
+  hipError_t e = hg::launch_pincounts(g, k, part, phi, netstate, (long long*)block_w,
+                                      (long long*)km1, s);
+  if (e != hipSuccess) return e;
+  e = hg::fill_u8(eligible, 1, g->n, s);
+  for (int r = 0; r < rounds && e == hipSuccess; ++r)
+    e = hg::launch_lp_round(g, k, lmax, part, phi, netstate, (long long*)block_w, eligible,
+                            nullptr, (long long*)km1, stats + r, s);
+  return e;
+}
+
+hg_status hg_refine(hg_graph g, int32_t k, double eps, int32_t rounds, int32_t* part,
+                    int32_t* phi, uint32_t* netstate, int64_t* block_w, uint8_t* eligible,
+                    hg_round_stats* stats, int64_t* km1_out, int32_t use_graph, void* stream) {
+  hg_status st = check_k(g, k);
+  if (st != HG_OK) return st;
+  if (!(eps > 0.0 && eps < 1.0)) return fail(HG_ERR_INVALID, "eps must lie in (0, 1)");
+  if (rounds < 0) return fail(HG_ERR_INVALID, "rounds must be >= 0");
+  if (!part || !phi || !netstate || !block_w || !eligible || !km1_out || (rounds > 0 && !stats))
+    return fail(HG_ERR_INVALID, "part, phi, netstate, block_w, eligible, stats and km1_out must "
+                                "be non-NULL");
+  const long long lmax = hg_max_block_weight(g, k, eps);
+  hipStream_t s = (hipStream_t)stream;
+  if (!use_graph) {
+    HG_TRY(enqueue_refine(g, k, lmax, rounds, part, phi, netstate, block_w, eligible, stats,
+                          km1_out, s),
+           "refine");
+    return HG_OK;
+  }
+  unsigned long long key[12] = {(unsigned long long)k,        (unsigned long long)rounds,
+                                (unsigned long long)lmax,     (unsigned long long)part,
+                                (unsigned long long)phi,      (unsigned long long)netstate,
+                                (unsigned long long)block_w,  (unsigned long long)eligible,
+                                (unsigned long long)stats,    (unsigned long long)km1_out,
+                                1ull,                         0ull};
+  if (!g->graph_exec || memcmp(key, g->graph_key, sizeof(key)) != 0) {
+    if (g->graph_exec) {
+      (void)hipGraphExecDestroy((hipGraphExec_t)g->graph_exec);
+      g->graph_exec = nullptr;
+    }
+    if (!g->cap_stream) {
+      hipStream_t cs;
+      HG_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
+      g->cap_stream = cs;
+    }
+    hipStream_t cs = (hipStream_t)g->cap_stream;
+    HG_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    hipError_t e = enqueue_refine(g, k, lmax, rounds, part, phi, netstate, block_w, eligible,
+                                  stats, km1_out, cs);
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    if (e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return hip_fail(e, "refine capture");
+    }
+    if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    g->graph_exec = exec;
+    memcpy(g->graph_key, key, sizeof(key));
+  }
+  HG_TRY(hipGraphLaunch((hipGraphExec_t)g->graph_exec, s), "hipGraphLaunch");
+  return HG_OK;
+}
+
+hg_status hg_sync_status(hg_graph g, void* stream) {
+  if (!g) return fail(HG_ERR_INVALID, "graph handle is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  HG_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  int flags = 0;
+  HG_TRY(hipMemcpyAsync(&flags, g->ws + g->lay.flags, sizeof(int), hipMemcpyDeviceToHost, s),
+         "hipMemcpyAsync");
+  HG_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  if (flags) {
+    HG_TRY(hg::fill_i32((int*)(g->ws + g->lay.flags), 0, 1, s), "flag reset");
+    HG_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+    return fail(HG_ERR_INVALID, "%s", describe_err(flags));
+  }
+  return HG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,141 @@
+// hg_internal.h -- shared definitions of the HIP implementation behind hgref.h.
+//
+// Data layout in device memory (all caller-owned):
+//   net CSR          eptr int64[m+1], pins int32[P]
+//   incidence CSR    vptr int64[n+1], vnets int32[P] (rows sorted by net id)
+//   partition state  part int32[n], phi int32[m*k] (row-major by net),
+//                    netstate uint32[m*RW] (RW = hg_net_words(k)), block_w int64[k]
+//   workspace        carved by WsLayout below
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/hgref.h"
+
+namespace hg {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;            // threads per workgroup in every kernel
+constexpr int kTile = 4096;            // vertices per approval tile (256 threads x 16)
+constexpr int kPerThreadTile = kTile / kBlock;
+constexpr int kBuckets = 256;          // gain buckets per target block (0..254 exact, 255 = ">=255")
+constexpr int kLightLimit = 255;       // w(I(v)) <= 255: bit-sliced register path
+constexpr int kPlanes = 8;             // bit planes for counters <= 255
+constexpr int kSmallRow = 64;          // incidence rows up to this length sort in-thread
+constexpr int kNumXcd = 8;             // MI355X: 8 XCDs, each with its own L2
+
+// Validation bits raised on the device.
+enum : int {
+  kErrCsr = 1,         // eptr not increasing / wrong ends
+  kErrPin = 2,         // pin outside [0,n)
+  kErrWeight = 4,      // non-positive weight
+  kErrDuplicate = 8,   // a vertex twice in one net
+  kErrPart = 16,       // partition id outside [0,k)
+  kErrNetWeight = 32,  // total net weight >= 2^31
+};
+
+// Per-round counters kept in the workspace.  Zero between rounds.
+struct RoundCounters {
+  unsigned long long eligible, boundary, candidates, approved, moved_pins, touched;
+  unsigned long long delta_attr;   // two's complement int64 sums
+  unsigned long long delta_check;
+  unsigned int done_final;         // workgroups of the finalize kernel that have finished
+  unsigned int any_overflow;       // some block's threshold fell into the ">=255" bucket
+  unsigned int pad[14];
+};
+
+// Approval threshold of one target block.
+struct Threshold {
+  int gstar;          // gains > gstar approved; == gstar decided by vertex order; -1: all approved
+  int tau;            // tile holding the last approved vertex of gain gstar (numTiles: none)
+  long long rem;      // budget left for gain-gstar candidates after all higher gains
+  long long rem_tile; // budget left inside tile tau
+};
+
+// Facts gathered at load time (device side, copied to the host once).
+struct LoadInfo {
+  int err;
+  int max_degree;
+  int max_net_size;
+  int max_incident_weight;
+  int max_vertex_weight;
+  int heavy_count;
+  unsigned long long total_vertex_weight;
+  unsigned long long total_net_weight;
+  int big_rows;       // incidence rows longer than kSmallRow
+  int pad[5];
+};
+
+struct WsLayout {
+  size_t cand, touched, tlist, heavy, big, hist, overflow, thr, tilesum, ctr, info, scan, flags;
+  size_t total;
+  int num_tiles;
+  int scan_blocks;
+};
+
+WsLayout ws_layout(int n, int m, long long P, int k_max);
+
+// 32-bit words per block bitset in a net record: ceil(k/32) rounded up to a
+// power of two (1, 2, 4 or 8), so that word offsets are compile-time friendly.
+__host__ __device__ inline int bit_words(int k) {
+  int w = 1;
+  while (w * 32 < k) w *= 2;
+  return w;
+}
+
+// Words per net record: 2 + 2 * bit_words(k) rounded up to a power of two.
+__host__ __device__ inline int net_words(int k) {
+  if (k < 2 || k > HG_MAX_K) return 0;
+  int need = 2 + 2 * bit_words(k);
+  int rw = 4;
+  while (rw < need) rw *= 2;
+  return rw;
+}
+
+}  // namespace hg
+
+struct hg_graph_s {
+  int n, m;
+  long long P;
+  const long long* eptr;
+  const int* pins;
+  const int* vwgt;   // may be null (unit)
+  const int* ewgt;   // may be null (unit)
+  long long* vptr;
+  int* vnets;
+  char* ws;
+  size_t ws_bytes;
+  int k_max;
+  hg::WsLayout lay;
+  hg::LoadInfo info;
+  // recorded refinement graph (hipGraphExec_t) and the private stream it is
+  // captured on (the caller's stream may be the legacy null stream)
+  void* graph_exec;
+  void* cap_stream;
+  unsigned long long graph_key[12];
+};
+
+namespace hg {
+
+// ---- launch helpers implemented in the .hip files (return hipError_t) ----
+hipError_t fill_i64(long long* p, long long v, long long count, hipStream_t s);
+hipError_t fill_u8(unsigned char* p, unsigned char v, long long count, hipStream_t s);
+hipError_t fill_i32(int* p, int v, long long count, hipStream_t s);
+
+hipError_t load_check(hg_graph_s* g, hipStream_t s);
+hipError_t load_build(hg_graph_s* g, hipStream_t s);
+
+hipError_t launch_pincounts(hg_graph_s* g, int k, const int* part, int* phi,
+                            unsigned* netstate, long long* block_w, long long* km1,
+                            hipStream_t s);
+hipError_t launch_km1(hg_graph_s* g, int k, const unsigned* netstate, long long* km1,
+                      hipStream_t s);
+hipError_t launch_gains(hg_graph_s* g, int k, const int* part, const unsigned* netstate,
+                        long long* gains, long long* benefit, hipStream_t s);
+hipError_t launch_lp_round(hg_graph_s* g, int k, long long lmax, int* part, int* phi,
+                           unsigned* netstate, long long* block_w, unsigned char* eligible,
+                           unsigned char* moved, long long* km1, hg_round_stats* stats,
+                           hipStream_t s);
+
+}  // namespace hg

@@ -1,0 +1,77 @@
+// hg_netrec.h -- building one net's record (w, lambda, Lambda bits, S bits)
+// from its pin counts with a group of G lanes (G in {4,8,16,32,64}).
+//
+// Lane gl of the group handles blocks gl, gl+G, ...; the bitsets come from
+// two wave ballots per chunk of G blocks (Phi > 0 and Phi == 1).  Every lane
+// ends up holding the record word with index gl, so the record is written
+// with one coalesced store per lane.
+#pragma once
+
+#include "hg_device.h"
+
+namespace hg {
+
+struct NetBits {
+  int lambda;
+  unsigned word;   // record word with index = lane-in-group (valid for 1 <= gl < 2+2W)
+};
+
+// get(i) -> Phi(e,i); put(i, v) stores it (or does nothing).
+template <int G, typename Get, typename Put>
+__device__ __forceinline__ NetBits net_bits(int k, int gl, Get get, Put put) {
+  const int wk = bit_words(k);
+  const int shift = (G == kWave) ? 0 : (lane_id() / G) * G;
+  const unsigned long long gmask = (G == kWave) ? ~0ull : ((1ull << (G % kWave)) - 1);
+  NetBits r;
+  r.lambda = 0;
+  r.word = 0;
+  const int nchunks = (k + G - 1) / G;
+  for (int c = 0; c < nchunks; ++c) {
+    int i = c * G + gl;
+    int cv = 0;
+    if (i < k) {
+      cv = get(i);
+      put(i, cv);
+    }
+    unsigned long long nz = (__ballot(cv > 0) >> shift) & gmask;
+    unsigned long long one = (__ballot(cv == 1) >> shift) & gmask;
+    r.lambda += __popcll(nz);
+    if (G <= 32) {                    // then k <= G: one word per bitset
+      if (gl == 2) r.word = (unsigned)nz;
+      if (gl == 3) r.word = (unsigned)one;
+    } else {
+      int j0 = 2 * c;
+      if (gl == 2 + j0) r.word = (unsigned)nz;
+      if (gl == 3 + j0) r.word = (unsigned)(nz >> 32);
+      if (gl == 2 + wk + j0) r.word = (unsigned)one;
+      if (gl == 3 + wk + j0) r.word = (unsigned)(one >> 32);
+    }
+  }
+  if (gl == 1) r.word = (unsigned)r.lambda;
+  return r;
+}
+
+// Pin counts of one net already in LDS (cnt[0..k)); writes the Phi row.
+template <int G>
+__device__ __forceinline__ void netbits_from_counts(const int* cnt, int k, int gl, NetBits& b,
+                                                    int* phi_row) {
+  b = net_bits<G>(k, gl, [&](int i) { return cnt[i]; },
+                  [&](int i, int v) { phi_row[i] = v; });
+}
+
+// Write a whole record (w in word 0, zero padding); needs G >= record words,
+// which holds for the group sizes chosen per k (G >= 4 = words for k <= 32,
+// G = 64 >= 32 words otherwise).
+__device__ __forceinline__ void write_netrec(unsigned* rec, int gl, int w, const NetBits& b,
+                                             int k) {
+  const int wk = bit_words(k);
+  const int rw = net_words(k);
+  if (gl < rw) {
+    unsigned val = 0;
+    if (gl == 0) val = (unsigned)w;
+    else if (gl < 2 + 2 * wk) val = b.word;
+    rec[gl] = val;
+  }
+}
+
+}  // namespace hg

@@ -1,0 +1,153 @@
+// hg_state.hip -- pin counts Phi(e,i), connectivity sets Lambda(e), the
+// singleton sets S(e) = {i : Phi(e,i) = 1}, block weights c(V_i) and km1.
+//
+// Section "Preliminaries" defines Phi, Lambda, lambda and km1; subsection
+// "Data Structures for Gain Calculation" keeps Phi and a bitset Lambda per
+// net.  Here one group of G lanes owns one net at a time: it counts the net's
+// pins per block in LDS, writes the Phi row with coalesced stores and builds
+// the bitsets with wave ballots.  No global atomics touch Phi, so the result
+// is deterministic by construction.
+#include "hg_device.h"
+#include "hg_internal.h"
+#include "hg_netrec.h"
+
+namespace hg {
+
+// G lanes per net (G divides 64); LDS counters: (kBlock/G) groups x k ints.
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_pincounts(int m, int k, int rw,
+                                                      const long long* eptr, const int* pins,
+                                                      const int* ewgt, const int* part,
+                                                      int* phi, unsigned* netstate,
+                                                      unsigned long long* km1_acc,
+                                                      int* err_flags, int n) {
+  extern __shared__ int s_cnt[];   // [kBlock/G][k]
+  __shared__ long long s_tmp[kBlock / kWave];
+  const int grp_in_block = threadIdx.x / G;
+  const int gl = threadIdx.x % G;                      // lane within group
+  int* cnt = s_cnt + grp_in_block * k;
+  const long long groups = (long long)gridDim.x * (kBlock / G);
+  const unsigned lb = xcd_remap(blockIdx.x, gridDim.x);
+  long long km1_local = 0;
+  int err = 0;
+  for (long long e = (long long)lb * (kBlock / G) + grp_in_block; e < m; e += groups) {
+    for (int i = gl; i < k; i += G) cnt[i] = 0;
+    wave_lds_sync();
+    long long b = eptr[e], t = eptr[e + 1];
+    for (long long p = b + gl; p < t; p += G) {
+      int v = pins[p];
+      int blk = part[v];
+      if ((unsigned)blk < (unsigned)k) atomicAdd(&cnt[blk], 1);
+      else err = kErrPart;
+    }
+    wave_lds_sync();
+    NetBits bits;
+    netbits_from_counts<G>(cnt, k, gl, bits, phi + e * (long long)k);
+    int w = ewgt ? ewgt[e] : 1;
+    write_netrec(netstate + e * (long long)rw, gl, w, bits, k);
+    if (gl == 0) km1_local += (long long)(bits.lambda - 1) * w;
+    wave_lds_sync();
+  }
+  if (err) atomicOr(err_flags, err);
+  long long tot = block_sum64(km1_local, s_tmp);
+  if (threadIdx.x == 0 && km1_acc) atomicAdd(km1_acc, (unsigned long long)tot);
+}
+
+// Block weights: LDS partial sums per workgroup, then one atomic per block.
+__global__ __launch_bounds__(kBlock) void k_block_weights(int n, int k, const int* part,
+                                                          const int* vwgt,
+                                                          unsigned long long* block_w,
+                                                          int* err_flags) {
+  __shared__ unsigned long long s_w[HG_MAX_K];
+  for (int i = threadIdx.x; i < k; i += kBlock) s_w[i] = 0;
+  __syncthreads();
+  long long stride = (long long)gridDim.x * kBlock;
+  int err = 0;
+  for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < n; v += stride) {
+    int blk = part[v];
+    if ((unsigned)blk < (unsigned)k)
+      atomicAdd(&s_w[blk], (unsigned long long)(vwgt ? vwgt[v] : 1));
+    else
+      err = kErrPart;
+  }
+  if (err) atomicOr(err_flags, err);
+  __syncthreads();
+  for (int i = threadIdx.x; i < k; i += kBlock)
+    if (s_w[i]) atomicAdd(&block_w[i], s_w[i]);
+}
+
+// km1 = sum_e (lambda(e) - 1) w(e) from the net-state records.
+__global__ __launch_bounds__(kBlock) void k_km1(int m, int rw, const unsigned* netstate,
+                                                unsigned long long* km1_acc) {
+  __shared__ long long s_tmp[kBlock / kWave];
+  long long stride = (long long)gridDim.x * kBlock;
+  long long acc = 0;
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < m; e += stride) {
+    const unsigned* r = netstate + e * rw;
+    acc += (long long)((int)r[1] - 1) * (int)r[0];
+  }
+  acc = block_sum64(acc, s_tmp);
+  if (threadIdx.x == 0) atomicAdd(km1_acc, (unsigned long long)acc);
+}
+
+static unsigned persistent_grid(long long items, int per_block) {
+  long long b = (items + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > 32768) b = 32768;
+  return (unsigned)b;
+}
+
+template <int G>
+static void launch_pincounts_g(hg_graph_s* g, int k, const int* part, int* phi,
+                               unsigned* netstate, unsigned long long* km1, int* err,
+                               hipStream_t s) {
+  unsigned grid = persistent_grid(g->m, kBlock / G);
+  size_t lds = sizeof(int) * (size_t)(kBlock / G) * k;
+  hipLaunchKernelGGL(k_pincounts<G>, dim3(grid), dim3(kBlock), lds, s, g->m, k, net_words(k),
+                     g->eptr, g->pins, g->ewgt, part, phi, netstate, km1, err, g->n);
+}
+
+int group_lanes(int k) {
+  if (k <= 4) return 4;
+  if (k <= 8) return 8;
+  if (k <= 16) return 16;
+  if (k <= 32) return 32;
+  return 64;
+}
+
+hipError_t launch_pincounts(hg_graph_s* g, int k, const int* part, int* phi,
+                            unsigned* netstate, long long* block_w, long long* km1,
+                            hipStream_t s) {
+  int* err = (int*)(g->ws + g->lay.flags);
+  hipError_t e;
+  if (km1) {
+    e = fill_i64(km1, 0, 1, s);
+    if (e != hipSuccess) return e;
+  }
+  unsigned long long* km1u = (unsigned long long*)km1;
+  switch (group_lanes(k)) {
+    case 4: launch_pincounts_g<4>(g, k, part, phi, netstate, km1u, err, s); break;
+    case 8: launch_pincounts_g<8>(g, k, part, phi, netstate, km1u, err, s); break;
+    case 16: launch_pincounts_g<16>(g, k, part, phi, netstate, km1u, err, s); break;
+    case 32: launch_pincounts_g<32>(g, k, part, phi, netstate, km1u, err, s); break;
+    default: launch_pincounts_g<64>(g, k, part, phi, netstate, km1u, err, s); break;
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = fill_i64(block_w, 0, k, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_block_weights, dim3(persistent_grid(g->n, kBlock * 16)), dim3(kBlock),
+                     0, s, g->n, k, part, g->vwgt, (unsigned long long*)block_w, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_km1(hg_graph_s* g, int k, const unsigned* netstate, long long* km1,
+                      hipStream_t s) {
+  hipError_t e = fill_i64(km1, 0, 1, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_km1, dim3(persistent_grid(g->m, kBlock * 8)), dim3(kBlock), 0, s, g->m,
+                     net_words(k), netstate, (unsigned long long*)km1);
+  return hipGetLastError();
+}
+
+}  // namespace hg

@@ -1,0 +1,266 @@
+"""Python binding of libhgref.so (include/hgref.h): argument marshalling only.
+
+Every function keeps the name of the C entry point it calls.  Device memory
+and streams come from PyTorch (ROCm builds keep the ``cuda`` device name);
+all computation happens in the HIP kernels behind the C ABI.  There is no
+fallback: if the shared library is missing or cannot be loaded, importing
+this module raises.
+"""
+import ctypes
+import os
+
+import torch  # loads the HIP runtime that libhgref.so binds to
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhgref.so")
+
+HG_OK = 0
+HG_ERR_INVALID = -1
+HG_ERR_UNSUPPORTED = -2
+HG_ERR_DEVICE = -3
+HG_ERR_WORKSPACE = -4
+HG_MAX_K = 256
+
+STATS_FIELDS = ("eligible", "boundary", "candidates", "approved", "moved_pins", "touched_nets",
+                "km1_delta", "km1_after", "max_block_weight", "km1_delta_recomputed")
+STATS_WORDS = len(STATS_FIELDS)
+
+
+class HgError(RuntimeError):
+    def __init__(self, code, message):
+        super().__init__("hgref error %d: %s" % (code, message))
+        self.code = code
+        self.message = message
+
+
+class GraphInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("P", ctypes.c_int64),
+                ("total_vertex_weight", ctypes.c_int64), ("total_net_weight", ctypes.c_int64),
+                ("max_degree", ctypes.c_int32), ("max_net_size", ctypes.c_int32),
+                ("max_incident_weight", ctypes.c_int32), ("heavy_vertices", ctypes.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libhgref.so not built (run __graft_entry__.build() or "
+                          "python -m paper_2010_10272_amd.build): %s" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    i32, i64, vp, sz, dbl = (ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t,
+                             ctypes.c_double)
+    lib.hg_net_words.argtypes = [i32]
+    lib.hg_net_words.restype = i32
+    lib.hg_workspace_size.argtypes = [i32, i32, i64, i32]
+    lib.hg_workspace_size.restype = sz
+    lib.hg_load_csr.argtypes = [i32, i32, i64, vp, vp, vp, vp, vp, vp, vp, sz, i32, vp,
+                                ctypes.POINTER(vp)]
+    lib.hg_load_csr.restype = i32
+    lib.hg_free.argtypes = [vp]
+    lib.hg_free.restype = None
+    lib.hg_get_info.argtypes = [vp, ctypes.POINTER(GraphInfo)]
+    lib.hg_get_info.restype = i32
+    lib.hg_max_block_weight.argtypes = [vp, i32, dbl]
+    lib.hg_max_block_weight.restype = i64
+    lib.hg_compute_pincounts.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+    lib.hg_compute_pincounts.restype = i32
+    lib.hg_km1.argtypes = [vp, i32, vp, vp, vp]
+    lib.hg_km1.restype = i32
+    lib.hg_gains.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+    lib.hg_gains.restype = i32
+    lib.hg_lp_round.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.hg_lp_round.restype = i32
+    lib.hg_refine.argtypes = [vp, i32, dbl, i32, vp, vp, vp, vp, vp, vp, vp, i32, vp]
+    lib.hg_refine.restype = i32
+    lib.hg_sync_status.argtypes = [vp, vp]
+    lib.hg_sync_status.restype = i32
+    lib.hg_last_error.argtypes = []
+    lib.hg_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = _load()
+
+
+def _check(rc):
+    if rc != HG_OK:
+        raise HgError(rc, _lib.hg_last_error().decode(errors="replace"))
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dev(x, dtype, device):
+    if x is None:
+        return None
+    if isinstance(x, torch.Tensor):
+        return x.to(device=device, dtype=dtype).contiguous()
+    return torch.as_tensor(x).to(device=device, dtype=dtype).contiguous()
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def hg_net_words(k):
+    return int(_lib.hg_net_words(int(k)))
+
+
+def hg_workspace_size(n, m, P, k_max):
+    return int(_lib.hg_workspace_size(int(n), int(m), int(P), int(k_max)))
+
+
+class Graph:
+    """A loaded hypergraph: owns the device tensors the C handle borrows."""
+
+    def __init__(self, handle, tensors, n, m, P, k_max):
+        self._h = handle
+        self._t = tensors
+        self.n, self.m, self.P, self.k_max = n, m, P, k_max
+        self.device = tensors["eptr"].device
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("graph already freed")
+        return self._h
+
+    def __getattr__(self, name):
+        t = self.__dict__.get("_t")
+        if t is not None and name in t:
+            return t[name]
+        raise AttributeError(name)
+
+    def free(self):
+        if self._h is not None:
+            torch.cuda.synchronize(self.device)
+            _lib.hg_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            if self._h is not None:
+                _lib.hg_free(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+def hg_load_csr(n, eptr, pins, vwgt=None, ewgt=None, k_max=HG_MAX_K, device="cuda",
+                stream=None):
+    """Load a net-CSR hypergraph (arrays or tensors) onto the device and build
+    its incidence CSR.  Returns a Graph.  Synchronizes the stream."""
+    device = torch.device(device)
+    eptr = _dev(eptr, torch.int64, device)
+    pins = _dev(pins, torch.int32, device)
+    vwgt = _dev(vwgt, torch.int32, device)
+    ewgt = _dev(ewgt, torch.int32, device)
+    m = int(eptr.numel() - 1)
+    P = int(pins.numel())
+    ws_bytes = hg_workspace_size(n, m, P, k_max)
+    if ws_bytes == 0:
+        raise HgError(HG_ERR_UNSUPPORTED, "unsupported sizes n=%d m=%d P=%d k_max=%d"
+                      % (n, m, P, k_max))
+    vptr = torch.empty(n + 1, dtype=torch.int64, device=device)
+    vnets = torch.empty(max(P, 1), dtype=torch.int32, device=device)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=device)
+    h = ctypes.c_void_p()
+    _check(_lib.hg_load_csr(int(n), m, P, _ptr(eptr), _ptr(pins), _ptr(vwgt), _ptr(ewgt),
+                            _ptr(vptr), _ptr(vnets), _ptr(ws), ws_bytes, int(k_max),
+                            _stream(stream), ctypes.byref(h)))
+    tensors = dict(eptr=eptr, pins=pins, vwgt=vwgt, ewgt=ewgt, vptr=vptr, vnets=vnets,
+                   workspace=ws)
+    return Graph(h, tensors, int(n), m, P, int(k_max))
+
+
+def hg_get_info(g):
+    info = GraphInfo()
+    _check(_lib.hg_get_info(g.handle, ctypes.byref(info)))
+    return {f: int(getattr(info, f)) for f, _ in GraphInfo._fields_}
+
+
+def hg_max_block_weight(g, k, eps):
+    v = int(_lib.hg_max_block_weight(g.handle, int(k), float(eps)))
+    if v < 0:
+        raise HgError(HG_ERR_INVALID, "bad k or eps")
+    return v
+
+
+class State:
+    """Device state of one k-way partition of a graph (caller-owned buffers)."""
+
+    def __init__(self, g, k, part):
+        dev = g.device
+        self.k = int(k)
+        self.part = _dev(part, torch.int32, dev).clone()
+        self.phi = torch.empty(g.m * self.k, dtype=torch.int32, device=dev)
+        self.netstate = torch.empty(g.m * hg_net_words(k), dtype=torch.int32, device=dev)
+        self.block_w = torch.empty(self.k, dtype=torch.int64, device=dev)
+        self.km1 = torch.empty(1, dtype=torch.int64, device=dev)
+        self.eligible = torch.ones(g.n, dtype=torch.uint8, device=dev)
+        self.moved = torch.zeros(g.n, dtype=torch.uint8, device=dev)
+
+
+def hg_compute_pincounts(g, st, stream=None):
+    _check(_lib.hg_compute_pincounts(g.handle, st.k, _ptr(st.part), _ptr(st.phi),
+                                     _ptr(st.netstate), _ptr(st.block_w), _ptr(st.km1),
+                                     _stream(stream)))
+
+
+def hg_km1(g, k, netstate, out=None, stream=None):
+    if out is None:
+        out = torch.empty(1, dtype=torch.int64, device=netstate.device)
+    _check(_lib.hg_km1(g.handle, int(k), _ptr(netstate), _ptr(out), _stream(stream)))
+    return out
+
+
+def hg_gains(g, k, part, netstate, gains=None, benefit=None, stream=None):
+    dev = netstate.device
+    if gains is None:
+        gains = torch.empty(g.n * int(k), dtype=torch.int64, device=dev)
+    _check(_lib.hg_gains(g.handle, int(k), _ptr(part), _ptr(netstate), _ptr(gains),
+                         _ptr(benefit), _stream(stream)))
+    return gains, benefit
+
+
+def hg_lp_round(g, st, max_block_w, stats, moved=True, stream=None):
+    """One label-propagation round on State st; stats: int64 device tensor of
+    STATS_WORDS entries."""
+    _check(_lib.hg_lp_round(g.handle, st.k, int(max_block_w), _ptr(st.part), _ptr(st.phi),
+                            _ptr(st.netstate), _ptr(st.block_w), _ptr(st.eligible),
+                            _ptr(st.moved) if moved else None, _ptr(st.km1), _ptr(stats),
+                            _stream(stream)))
+
+
+def hg_refine(g, st, eps, rounds, stats, use_graph=True, stream=None):
+    """Pin counts from st.part, then `rounds` LP rounds; stats: int64 device
+    tensor of rounds * STATS_WORDS entries."""
+    _check(_lib.hg_refine(g.handle, st.k, float(eps), int(rounds), _ptr(st.part), _ptr(st.phi),
+                          _ptr(st.netstate), _ptr(st.block_w), _ptr(st.eligible), _ptr(stats),
+                          _ptr(st.km1), 1 if use_graph else 0, _stream(stream)))
+
+
+def hg_sync_status(g, stream=None):
+    _check(_lib.hg_sync_status(g.handle, _stream(stream)))
+
+
+def stats_to_dicts(stats):
+    """Device stats tensor -> list of dicts (synchronizes)."""
+    a = stats.view(-1, STATS_WORDS).cpu().tolist()
+    return [dict(zip(STATS_FIELDS, row)) for row in a]
+
+
+def decode_netstate(netstate, m, k):
+    """Split a net-state tensor into (w, lambda, Lambda words, S words) views."""
+    rw = hg_net_words(k)
+    wk = 1
+    while wk * 32 < k:
+        wk *= 2
+    r = netstate.view(m, rw)
+    return r[:, 0], r[:, 1], r[:, 2:2 + wk], r[:, 2 + wk:2 + 2 * wk]
