@@ -75,7 +75,14 @@ typedef struct {
   int64_t max_block_weight;      /* max_i c(V_i) after the round                    */
   int64_t km1_delta_recomputed;  /* sum over touched nets of (lambda_old -
                                     lambda_new) * w(e); equals km1_delta           */
+  int64_t active_pins;           /* sum of d(u) over active (eligible boundary) u   */
 } hg_round_stats;
+
+/* Phases of a label-propagation round measured by hg_timing_collect. */
+#define HG_PHASE_SELECT 0    /* select sweep (light and heavy vertices)            */
+#define HG_PHASE_APPROVE 1   /* thresholds, tile sums and scan, approve + apply     */
+#define HG_PHASE_FINALIZE 2  /* touched-net finalize and the round record          */
+#define HG_NUM_PHASES 3
 
 /* Static facts about a loaded hypergraph (host memory). */
 typedef struct {
@@ -209,6 +216,17 @@ hg_status hg_refine(hg_graph g, int32_t k, double eps, int32_t rounds, int32_t* 
                     int32_t* phi, uint32_t* netstate, int64_t* block_w, uint8_t* eligible,
                     hg_round_stats* stats, int64_t* km1_out, int32_t use_graph,
                     void* stream);
+
+/* Per-phase timing of label-propagation rounds, off by default.  While on,
+ * every round enqueued outside a stream capture (hg_lp_round, and hg_refine
+ * with use_graph = 0) records four HIP events on its own stream around the
+ * three phases; a recorded hipGraph is never timed. */
+hg_status hg_timing_enable(hg_graph g, int32_t enable);
+
+/* Wait for the recorded events, add each phase's total duration in
+ * milliseconds to ms[HG_NUM_PHASES] and the number of timed rounds to
+ * *rounds, then forget the events. */
+hg_status hg_timing_collect(hg_graph g, double* ms, int64_t* rounds);
 
 /* Synchronize `stream`, then report HG_ERR_INVALID if a device-side check
  * (a partition id outside [0,k)) fired since the last call, HG_ERR_DEVICE

@@ -43,6 +43,7 @@ typedef struct {
   int64_t km1_delta;      /* km1(before) - km1(after), both recomputed        */
   int64_t km1_after;      /* km1 after the round                              */
   int64_t max_block_weight; /* max_i c(V_i) after the round                   */
+  int64_t active_pins;    /* sum of d(u) over active (eligible boundary) u    */
 } or_round_stats;
 
 /* ------------------------------------------------------------------------ */
@@ -252,6 +253,7 @@ int or_lp_round(int32_t n, int32_t m, const int64_t* eptr, const int32_t* pins,
       if (lambda[vnets[j]] > 1) boundary = 1;
     if (!boundary) continue;
     st->boundary += 1;
+    st->active_pins += vptr[u + 1] - vptr[u];
 
     int32_t a = part[u];
     /* b(u) and, for every block, the weight of incident nets that already

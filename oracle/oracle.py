@@ -22,7 +22,7 @@ OR_OK = 0
 OR_ERR_INVALID = -1
 
 STATS_FIELDS = ("eligible", "boundary", "candidates", "approved", "moved_pins",
-                "touched_nets", "km1_delta", "km1_after", "max_block_weight")
+                "touched_nets", "km1_delta", "km1_after", "max_block_weight", "active_pins")
 
 
 class RoundStats(ctypes.Structure):

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <new>
+#include <vector>
 
 #include "hg_internal.h"
 
@@ -66,6 +67,45 @@ hg_status read_info(hg_graph_s* g, hipStream_t s) {
   return HG_OK;
 }
 
+// Events of timed rounds: groups of four (round start, after select, after
+// approve/apply, round end), recorded in order; `used` groups are pending.
+struct TimingState {
+  std::vector<hipEvent_t> events;
+  size_t used = 0;
+};
+
+void release_timing(hg_graph_s* g) {
+  TimingState* t = (TimingState*)g->timing_state;
+  if (!t) return;
+  for (hipEvent_t e : t->events) (void)hipEventDestroy(e);
+  delete t;
+  g->timing_state = nullptr;
+}
+
+// Four events for the next round, or *marks = nullptr when timing is off or
+// the stream is being captured.
+hg_status timing_marks(hg_graph_s* g, hipStream_t s, hipEvent_t** marks) {
+  *marks = nullptr;
+  if (!g->timing) return HG_OK;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HG_TRY(hipStreamIsCapturing(s, &cs), "hipStreamIsCapturing");
+  if (cs != hipStreamCaptureStatusNone) return HG_OK;
+  TimingState* t = (TimingState*)g->timing_state;
+  if (!t) {
+    t = new (std::nothrow) TimingState();
+    if (!t) return fail(HG_ERR_INVALID, "out of host memory");
+    g->timing_state = t;
+  }
+  while (t->events.size() < t->used + 4) {
+    hipEvent_t e;
+    HG_TRY(hipEventCreate(&e), "hipEventCreate");
+    t->events.push_back(e);
+  }
+  *marks = t->events.data() + t->used;
+  t->used += 4;
+  return HG_OK;
+}
+
 }  // namespace
 
 namespace hg {
@@ -86,7 +126,7 @@ WsLayout ws_layout(int n, int m, long long P, int k_max) {
   L.tlist = take(sizeof(int) * 2 * (size_t)m);
   L.heavy = take(sizeof(int) * (size_t)n);
   L.big = take(sizeof(int) * (size_t)n);
-  L.hist = take(sizeof(unsigned long long) * (size_t)k_max * kBuckets);
+  L.hist = take(sizeof(unsigned long long) * (size_t)kHistReplicas * HG_MAX_K * kBuckets);
   L.overflow = take(sizeof(int) * (size_t)k_max);
   L.thr = take(sizeof(Threshold) * (size_t)k_max);
   L.tilesum = take(sizeof(long long) * (size_t)k_max * (size_t)L.num_tiles);
@@ -94,6 +134,7 @@ WsLayout ws_layout(int n, int m, long long P, int k_max) {
   L.info = take(sizeof(LoadInfo));
   L.scan = take(sizeof(long long) * (size_t)L.scan_blocks);
   L.flags = take(256);
+  L.red = take(sizeof(unsigned long long) * kSlots);
   L.total = off;
   return L;
 }
@@ -147,6 +188,8 @@ hg_status hg_load_csr(int32_t n, int32_t m, int64_t P, const int64_t* eptr, cons
   g->lay = lay;
   g->graph_exec = nullptr;
   g->cap_stream = nullptr;
+  g->timing = 0;
+  g->timing_state = nullptr;
   auto bail = [&](hg_status st) {
     delete g;
     return st;
@@ -171,11 +214,13 @@ hg_status hg_load_csr(int32_t n, int32_t m, int64_t P, const int64_t* eptr, cons
   char* ws = g->ws;
   e = hg::fill_i32((int*)(ws + lay.touched), 0, ((long long)m + 31) / 32, s);
   if (e == hipSuccess)
-    e = hg::fill_i64((long long*)(ws + lay.hist), 0, (long long)k_max * hg::kBuckets, s);
+    e = hg::fill_i64((long long*)(ws + lay.hist), 0,
+                     (long long)hg::kHistReplicas * HG_MAX_K * hg::kBuckets, s);
   if (e == hipSuccess) e = hg::fill_i32((int*)(ws + lay.overflow), 0, k_max, s);
   if (e == hipSuccess)
     e = hg::fill_i32((int*)(ws + lay.ctr), 0, sizeof(hg::RoundCounters) / sizeof(int), s);
   if (e == hipSuccess) e = hg::fill_i32((int*)(ws + lay.flags), 0, 64, s);
+  if (e == hipSuccess) e = hg::fill_i64((long long*)(ws + lay.red), 0, hg::kSlots, s);
   if (e != hipSuccess) return bail(hip_fail(e, "workspace init"));
   st = read_info(g, s);
   if (st != HG_OK) return bail(st);
@@ -188,6 +233,7 @@ void hg_free(hg_graph g) {
   if (!g) return;
   if (g->graph_exec) (void)hipGraphExecDestroy((hipGraphExec_t)g->graph_exec);
   if (g->cap_stream) (void)hipStreamDestroy((hipStream_t)g->cap_stream);
+  release_timing(g);
   delete g;
 }
 
@@ -255,8 +301,12 @@ hg_status hg_lp_round(hg_graph g, int32_t k, int64_t max_block_w, int32_t* part,
     return fail(HG_ERR_INVALID,
                 "part, phi, netstate, block_w, eligible, km1 and stats must be non-NULL");
   if (max_block_w < 0) return fail(HG_ERR_INVALID, "max_block_w must be >= 0");
+  hipEvent_t* marks = nullptr;
+  st = timing_marks(g, (hipStream_t)stream, &marks);
+  if (st != HG_OK) return st;
   HG_TRY(hg::launch_lp_round(g, k, max_block_w, part, phi, netstate, (long long*)block_w,
-                             eligible, moved, (long long*)km1, stats, (hipStream_t)stream),
+                             eligible, moved, (long long*)km1, stats, (hipStream_t)stream,
+                             marks),
          "label-propagation round");
   return HG_OK;
 }
@@ -269,9 +319,12 @@ static hipError_t enqueue_refine(hg_graph g, int k, long long lmax, int rounds, 
                                       (long long*)km1, s);
   if (e != hipSuccess) return e;
   e = hg::fill_u8(eligible, 1, g->n, s);
-  for (int r = 0; r < rounds && e == hipSuccess; ++r)
+  for (int r = 0; r < rounds && e == hipSuccess; ++r) {
+    hipEvent_t* marks = nullptr;
+    if (timing_marks(g, s, &marks) != HG_OK) return hipErrorUnknown;
     e = hg::launch_lp_round(g, k, lmax, part, phi, netstate, (long long*)block_w, eligible,
-                            nullptr, (long long*)km1, stats + r, s);
+                            nullptr, (long long*)km1, stats + r, s, marks);
+  }
   return e;
 }
 
@@ -328,6 +381,30 @@ hg_status hg_refine(hg_graph g, int32_t k, double eps, int32_t rounds, int32_t* 
     memcpy(g->graph_key, key, sizeof(key));
   }
   HG_TRY(hipGraphLaunch((hipGraphExec_t)g->graph_exec, s), "hipGraphLaunch");
+  return HG_OK;
+}
+
+hg_status hg_timing_enable(hg_graph g, int32_t enable) {
+  if (!g) return fail(HG_ERR_INVALID, "graph handle is NULL");
+  g->timing = enable ? 1 : 0;
+  return HG_OK;
+}
+
+hg_status hg_timing_collect(hg_graph g, double* ms, int64_t* rounds) {
+  if (!g || !ms || !rounds) return fail(HG_ERR_INVALID, "graph handle, ms and rounds must be non-NULL");
+  TimingState* t = (TimingState*)g->timing_state;
+  if (!t || t->used == 0) return HG_OK;
+  for (size_t i = 0; i < t->used; i += 4) {
+    HG_TRY(hipEventSynchronize(t->events[i + 3]), "hipEventSynchronize");
+    for (int p = 0; p < HG_NUM_PHASES; ++p) {
+      float x = 0.0f;
+      HG_TRY(hipEventElapsedTime(&x, t->events[i + p], t->events[i + p + 1]),
+             "hipEventElapsedTime");
+      ms[p] += x;
+    }
+    *rounds += 1;
+  }
+  t->used = 0;
   return HG_OK;
 }
 

@@ -24,6 +24,9 @@ constexpr int kLightLimit = 255;       // w(I(v)) <= 255: bit-sliced register pa
 constexpr int kPlanes = 8;             // bit planes for counters <= 255
 constexpr int kSmallRow = 64;          // incidence rows up to this length sort in-thread
 constexpr int kNumXcd = 8;             // MI355X: 8 XCDs, each with its own L2
+constexpr int kLdsHistEntries = 2048;  // per-workgroup LDS gain histogram (k * buckets)
+constexpr int kSelectGrid = 2048;      // persistent workgroups of the select sweep
+constexpr int kFinalizeGrid = 1024;    // persistent workgroups of the finalize sweep
 
 // Validation bits raised on the device.
 enum : int {
@@ -35,14 +38,31 @@ enum : int {
   kErrNetWeight = 32,  // total net weight >= 2^31
 };
 
+// Same-address global atomics serialize (tens of ns each), so every
+// accumulator that many workgroups add to is split into kSlots partial sums
+// (workgroup b adds to slot b % kSlots) and the partials are summed once by a
+// single small kernel.  Histograms get one replica per XCD.
+constexpr int kSlots = 64;
+constexpr int kHistReplicas = kNumXcd;
+
+enum CounterId : int {
+  kCtrEligible = 0,
+  kCtrBoundary,
+  kCtrCandidates,
+  kCtrApproved,
+  kCtrMovedPins,
+  kCtrDeltaAttr,    // two's complement int64 sums
+  kCtrDeltaCheck,
+  kCtrActivePins,
+  kNumCounters
+};
+
 // Per-round counters kept in the workspace.  Zero between rounds.
 struct RoundCounters {
-  unsigned long long eligible, boundary, candidates, approved, moved_pins, touched;
-  unsigned long long delta_attr;   // two's complement int64 sums
-  unsigned long long delta_check;
-  unsigned int done_final;         // workgroups of the finalize kernel that have finished
+  unsigned long long slot[kNumCounters][kSlots];
+  unsigned int touched;            // length of the touched-net list
   unsigned int any_overflow;       // some block's threshold fell into the ">=255" bucket
-  unsigned int pad[14];
+  unsigned int pad[62];
 };
 
 // Approval threshold of one target block.
@@ -69,6 +89,7 @@ struct LoadInfo {
 
 struct WsLayout {
   size_t cand, touched, tlist, heavy, big, hist, overflow, thr, tilesum, ctr, info, scan, flags;
+  size_t red;   // kSlots partial sums for whole-array reductions (km1)
   size_t total;
   int num_tiles;
   int scan_blocks;
@@ -114,6 +135,9 @@ struct hg_graph_s {
   void* graph_exec;
   void* cap_stream;
   unsigned long long graph_key[12];
+  // optional per-phase timing of label-propagation rounds (see hg_timing_*)
+  int timing;
+  void* timing_state;
 };
 
 namespace hg {
@@ -136,6 +160,6 @@ hipError_t launch_gains(hg_graph_s* g, int k, const int* part, const unsigned* n
 hipError_t launch_lp_round(hg_graph_s* g, int k, long long lmax, int* part, int* phi,
                            unsigned* netstate, long long* block_w, unsigned char* eligible,
                            unsigned char* moved, long long* km1, hg_round_stats* stats,
-                           hipStream_t s);
+                           hipStream_t s, hipEvent_t* marks = nullptr);
 
 }  // namespace hg

@@ -53,31 +53,50 @@ hipError_t fill_u8(unsigned char* p, unsigned char v, long long count, hipStream
 }
 
 // ------------------------------------------------------------------ checks
+// Load-time checks run on a capped grid and reduce per workgroup, so that
+// each shared LoadInfo field takes at most one atomic per workgroup.
+constexpr int kLoadGrid = 1024;
+
+__device__ __forceinline__ int block_max_int(int v, int* s_tmp) {
+  v = wave_max(v);
+  __syncthreads();
+  if (lane_id() == 0) s_tmp[threadIdx.x / kWave] = v;
+  __syncthreads();
+  int r = s_tmp[0];
+  for (int i = 1; i < kBlock / kWave; ++i) r = s_tmp[i] > r ? s_tmp[i] : r;
+  return r;
+}
+
 // Nets: increasing offsets with fixed ends (no empty net), positive weights.
-__global__ void k_check_nets(int m, long long P, const long long* eptr, const int* ewgt,
-                             LoadInfo* info) {
-  int e = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kBlock) void k_check_nets(int m, long long P,
+                                                       const long long* eptr, const int* ewgt,
+                                                       LoadInfo* info) {
+  __shared__ long long s_tmp[kBlock / kWave];
+  __shared__ int s_imax[kBlock / kWave];
   int err = 0, size = 0;
-  long long w = 0;
-  if (e < m) {
-    long long s = eptr[e], t = eptr[e + 1];
+  long long wsum = 0;
+  const long long stride = (long long)gridDim.x * kBlock;
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < m; e += stride) {
+    const long long s = eptr[e], t = eptr[e + 1];
     if (e == 0 && s != 0) err |= kErrCsr;
     if (e == m - 1 && t != P) err |= kErrCsr;
     if (t <= s || s < 0 || t > P) err |= kErrCsr;
-    else size = (int)((t - s) > 0x7fffffffLL ? 0x7fffffff : (t - s));
-    w = ewgt ? ewgt[e] : 1;
+    else if (t - s > size) size = (int)((t - s) > 0x7fffffffLL ? 0x7fffffff : (t - s));
+    const long long w = ewgt ? ewgt[e] : 1;
     if (w <= 0) err |= kErrWeight;
+    else wsum += w;
   }
   if (err) atomicOr(&info->err, err);
-  int mx = wave_max(size);
-  unsigned long long ws = (unsigned long long)wave_sum(w > 0 ? w : 0LL);
-  if (lane_id() == 0) {
+  const int mx = block_max_int(size, s_imax);
+  const long long ws = block_sum64(wsum, s_tmp);
+  if (threadIdx.x == 0) {
     atomicMax(&info->max_net_size, mx);
-    atomicAdd(&info->total_net_weight, ws);
+    atomicAdd(&info->total_net_weight, (unsigned long long)ws);
   }
 }
 
-__global__ void k_check_pins(int n, long long P, const int* pins, LoadInfo* info) {
+__global__ __launch_bounds__(kBlock) void k_check_pins(int n, long long P, const int* pins,
+                                                       LoadInfo* info) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   long long stride = (long long)gridDim.x * blockDim.x;
   int err = 0;
@@ -88,33 +107,48 @@ __global__ void k_check_pins(int n, long long P, const int* pins, LoadInfo* info
   if (err) atomicOr(&info->err, err);
 }
 
-__global__ void k_check_vertices(int n, const int* vwgt, LoadInfo* info) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
-  long long c = 0;
-  int err = 0;
-  if (v < n) {
-    c = vwgt ? vwgt[v] : 1;
-    if (c <= 0) err = kErrWeight;
+__global__ __launch_bounds__(kBlock) void k_check_vertices(int n, const int* vwgt,
+                                                           LoadInfo* info) {
+  __shared__ long long s_tmp[kBlock / kWave];
+  __shared__ int s_imax[kBlock / kWave];
+  int err = 0, cmax = 0;
+  long long csum = 0;
+  const long long stride = (long long)gridDim.x * kBlock;
+  for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < n; v += stride) {
+    const long long c = vwgt ? vwgt[v] : 1;
+    if (c <= 0) {
+      err = kErrWeight;
+    } else {
+      csum += c;
+      if (c > cmax) cmax = (int)c;
+    }
   }
   if (err) atomicOr(&info->err, err);
-  unsigned long long cs = (unsigned long long)wave_sum(c > 0 ? c : 0LL);
-  int mx = wave_max((int)(c > 0 ? c : 0));
-  if (lane_id() == 0) {
-    atomicAdd(&info->total_vertex_weight, cs);
+  const int mx = block_max_int(cmax, s_imax);
+  const long long cs = block_sum64(csum, s_tmp);
+  if (threadIdx.x == 0) {
+    atomicAdd(&info->total_vertex_weight, (unsigned long long)cs);
     atomicMax(&info->max_vertex_weight, mx);
   }
+}
+
+static unsigned grid_cap_load(long long items) {
+  long long b = (items + kBlock - 1) / kBlock;
+  if (b < 1) b = 1;
+  if (b > kLoadGrid) b = kLoadGrid;
+  return (unsigned)b;
 }
 
 hipError_t load_check(hg_graph_s* g, hipStream_t s) {
   LoadInfo* info = (LoadInfo*)(g->ws + g->lay.info);
   hipError_t e = fill_i32((int*)info, 0, sizeof(LoadInfo) / sizeof(int), s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_check_nets, dim3((g->m + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
-                     g->m, g->P, g->eptr, g->ewgt, info);
+  hipLaunchKernelGGL(k_check_nets, dim3(grid_cap_load(g->m)), dim3(kBlock), 0, s, g->m, g->P,
+                     g->eptr, g->ewgt, info);
   hipLaunchKernelGGL(k_check_pins, dim3(grid_for(g->P, 4)), dim3(kBlock), 0, s, g->n, g->P,
                      g->pins, info);
-  hipLaunchKernelGGL(k_check_vertices, dim3((g->n + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
-                     g->n, g->vwgt, info);
+  hipLaunchKernelGGL(k_check_vertices, dim3(grid_cap_load(g->n)), dim3(kBlock), 0, s, g->n,
+                     g->vwgt, info);
   return hipGetLastError();
 }
 
@@ -207,43 +241,64 @@ __global__ void k_scatter(int m, const long long* eptr, const int* pins, const l
 // Sort incidence rows of length <= kSmallRow in place (one thread per
 // vertex, insertion sort), then gather per-vertex facts.  Longer rows are
 // listed for k_sort_big_rows.
-__global__ void k_sort_small_rows(int n, const long long* vptr, int* vnets, const int* ewgt,
-                                  int* big_list, int* heavy_list, LoadInfo* info) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
-  int deg = 0, err = 0, incw = 0;
-  bool big = false, heavy = false;
-  if (v < n) {
-    long long b = vptr[v];
-    deg = (int)(vptr[v + 1] - b);
-    if (deg > kSmallRow) {
-      big = true;
-    } else {
-      int* row = vnets + b;
-      for (int i = 1; i < deg; ++i) {
-        int x = row[i];
-        int j = i - 1;
-        while (j >= 0 && row[j] > x) {
-          row[j + 1] = row[j];
-          --j;
+__global__ __launch_bounds__(kBlock) void k_sort_small_rows(int n, const long long* vptr,
+                                                            int* vnets, const int* ewgt,
+                                                            int* big_list, int* heavy_list,
+                                                            LoadInfo* info) {
+  __shared__ int s_imax[kBlock / kWave];
+  __shared__ unsigned s_big, s_heavy, s_big_base, s_heavy_base;
+  __shared__ int s_bigv[kBlock], s_heavyv[kBlock];
+  int err = 0, maxdeg = 0, maxincw = 0;
+  const long long stride = (long long)gridDim.x * kBlock;
+  const long long rounds = ((long long)n + stride - 1) / stride;
+  for (long long r = 0; r < rounds; ++r) {
+    const long long v = r * stride + (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (threadIdx.x == 0) s_big = s_heavy = 0;
+    __syncthreads();
+    bool big = false, heavy = false;
+    if (v < n) {
+      const long long b = vptr[v];
+      const int deg = (int)(vptr[v + 1] - b);
+      maxdeg = deg > maxdeg ? deg : maxdeg;
+      if (deg > kSmallRow) {
+        big = true;
+      } else {
+        int* row = vnets + b;
+        for (int i = 1; i < deg; ++i) {
+          const int x = row[i];
+          int j = i - 1;
+          while (j >= 0 && row[j] > x) {
+            row[j + 1] = row[j];
+            --j;
+          }
+          row[j + 1] = x;
         }
-        row[j + 1] = x;
+        long long tot = 0;
+        for (int i = 0; i < deg; ++i) {
+          if (i > 0 && row[i] == row[i - 1]) err = kErrDuplicate;
+          tot += ewgt ? ewgt[row[i]] : 1;
+        }
+        const int incw = tot > 0x7fffffffLL ? 0x7fffffff : (int)tot;
+        maxincw = incw > maxincw ? incw : maxincw;
+        heavy = tot > kLightLimit;
       }
-      long long tot = 0;
-      for (int i = 0; i < deg; ++i) {
-        if (i > 0 && row[i] == row[i - 1]) err = kErrDuplicate;
-        tot += ewgt ? ewgt[row[i]] : 1;
-      }
-      incw = tot > 0x7fffffffLL ? 0x7fffffff : (int)tot;
-      heavy = tot > kLightLimit;
     }
+    if (big) s_bigv[atomicAdd(&s_big, 1u)] = (int)v;
+    if (heavy) s_heavyv[atomicAdd(&s_heavy, 1u)] = (int)v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      s_big_base = s_big ? atomicAdd((unsigned*)&info->big_rows, s_big) : 0;
+      s_heavy_base = s_heavy ? atomicAdd((unsigned*)&info->heavy_count, s_heavy) : 0;
+    }
+    __syncthreads();
+    if (threadIdx.x < s_big) big_list[s_big_base + threadIdx.x] = s_bigv[threadIdx.x];
+    if (threadIdx.x < s_heavy) heavy_list[s_heavy_base + threadIdx.x] = s_heavyv[threadIdx.x];
+    __syncthreads();
   }
   if (err) atomicOr(&info->err, err);
-  int bi = wave_append((unsigned*)&info->big_rows, big);
-  if (big) big_list[bi] = v;
-  int hi = wave_append((unsigned*)&info->heavy_count, heavy);
-  if (heavy) heavy_list[hi] = v;
-  int md = wave_max(deg), mi = wave_max(incw);
-  if (lane_id() == 0) {
+  const int md = block_max_int(maxdeg, s_imax);
+  const int mi = block_max_int(maxincw, s_imax);
+  if (threadIdx.x == 0) {
     atomicMax(&info->max_degree, md);
     atomicMax(&info->max_incident_weight, mi);
   }
@@ -348,8 +403,8 @@ hipError_t load_build(hg_graph_s* g, hipStream_t s) {
   unsigned blocks = (unsigned)((waves + kBlock / kWave - 1) / (kBlock / kWave));
   hipLaunchKernelGGL(k_scatter, dim3(blocks), dim3(kBlock), 0, s, g->m, g->eptr, g->pins,
                      g->vptr, cursor, g->vnets);
-  hipLaunchKernelGGL(k_sort_small_rows, dim3((g->n + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
-                     g->n, g->vptr, g->vnets, g->ewgt, big, heavy, info);
+  hipLaunchKernelGGL(k_sort_small_rows, dim3(grid_cap_load(g->n)), dim3(kBlock), 0, s, g->n,
+                     g->vptr, g->vnets, g->ewgt, big, heavy, info);
   return hipGetLastError();
 }
 

@@ -19,10 +19,12 @@
 //              change summed from the atomics' old values (subsection
 //              "Attributed Gains"), touched nets listed.
 //   finalize   per touched net: Lambda, S and lambda recomputed from the
-//              final Phi row, its pins made eligible for the next round;
-//              the last workgroup writes the round's statistics.
+//              final Phi row, its pins made eligible for the next round.
+//   stats      one workgroup sums the counter slots into the round record.
 //
 // Candidate word: (gain << 32) | target, or -1 for "no candidate".
+#include <limits.h>
+
 #include "hg_bits.h"
 #include "hg_device.h"
 #include "hg_internal.h"
@@ -62,18 +64,28 @@ __device__ __forceinline__ void load_rec(const unsigned* __restrict__ r, int aw,
   }
 }
 
+// Light vertices, one thread each, on a persistent grid: workgroup lb owns
+// a contiguous run of 256-vertex chunks (so each XCD sweeps one vertex range
+// and reuses the net records its neighbours pulled into its L2).  Candidate
+// weights go to an LDS histogram (buckets [0, B) per target block, B =
+// min(256, 2048/k)); higher gains and the final flush go to the histogram
+// replica of this workgroup's XCD.
 template <int WK>
 __global__ __launch_bounds__(kBlock) void k_select_light(
-    int n, int k, int rw, long long lmax, int cmax, const long long* __restrict__ vptr,
-    const int* __restrict__ vnets, const int* __restrict__ vwgt, const int* __restrict__ part,
+    int n, int k, int rw, int lds_buckets, long long lmax, int cmax,
+    const long long* __restrict__ vptr, const int* __restrict__ vnets,
+    const int* __restrict__ vwgt, const int* __restrict__ part,
     const unsigned* __restrict__ netstate, const long long* __restrict__ block_w,
     unsigned char* __restrict__ eligible, unsigned char* __restrict__ moved,
     long long* __restrict__ cand, unsigned long long* __restrict__ hist,
     RoundCounters* __restrict__ ctr, int* __restrict__ err_flags) {
   __shared__ long long s_W[HG_MAX_K];
   __shared__ unsigned s_open[WK];
+  __shared__ unsigned long long s_hist[kLdsHistEntries];
   __shared__ long long s_tmp[kBlock / kWave];
+  const int B = lds_buckets;
   for (int i = threadIdx.x; i < WK; i += kBlock) s_open[i] = 0;
+  for (int i = threadIdx.x; i < k * B; i += kBlock) s_hist[i] = 0;
   __syncthreads();
   for (int i = threadIdx.x; i < k; i += kBlock) {
     long long W = block_w[i];
@@ -81,106 +93,128 @@ __global__ __launch_bounds__(kBlock) void k_select_light(
     if (W + cmax <= lmax) atomicOr(&s_open[i >> 5], 1u << (i & 31));
   }
   __syncthreads();
-  const unsigned lb = xcd_remap(blockIdx.x, gridDim.x);
-  const long long u = (long long)lb * kBlock + threadIdx.x;
-  long long n_elig = 0, n_bnd = 0, n_cand = 0;
-  if (u < n) {
+  unsigned long long* my_hist =
+      hist + (size_t)(blockIdx.x % kHistReplicas) * HG_MAX_K * kBuckets;
+  const long long chunks = ((long long)n + kBlock - 1) / kBlock;
+  const long long per = (chunks + gridDim.x - 1) / gridDim.x;
+  const long long lb = xcd_remap(blockIdx.x, gridDim.x);
+  const long long c_end = (lb + 1) * per < chunks ? (lb + 1) * per : chunks;
+  long long n_elig = 0, n_bnd = 0, n_cand = 0, n_apins = 0;
+  // valid-block masks (only blocks < k; guards against stale caller state)
+  unsigned valid[WK];
+#pragma unroll
+  for (int w = 0; w < WK; ++w) {
+    const int lo = w * 32;
+    valid[w] = k >= lo + 32 ? ~0u : (k > lo ? (1u << (k - lo)) - 1u : 0u);
+  }
+  for (long long c = lb * per; c < c_end; ++c) {
+    const long long u = c * kBlock + threadIdx.x;
+    if (u >= n) continue;
     if (moved) moved[u] = 0;
     const unsigned char el = eligible[u];
+    if (!el) {
+      cand[u] = -1;
+      continue;
+    }
     const int a = part[u];
-    long long out = -1;
-    bool skip = false;   // heavy vertex: the wavefront kernel owns it
-    if (el && (unsigned)a >= (unsigned)k) {
+    if ((unsigned)a >= (unsigned)k) {
       atomicOr(err_flags, kErrPart);
-    } else if (el) {
-      const long long b0 = vptr[u], b1 = vptr[u + 1];
-      if (b1 - b0 > kLightLimit) {
-        skip = true;
-      } else {
-        BitCounters<WK> C;
-        C.clear();
-        int tot = 0, ben = 0;
-        bool bnd = false;
-        const int aw = a >> 5;
-        const unsigned abit = 1u << (a & 31);
-        for (long long j = b0; j < b1; ++j) {
-          const int e = vnets[j];
-          unsigned w, lam, S, L[WK];
-          load_rec<WK>(netstate + (long long)e * rw, aw, w, lam, L, S);
-          tot += (int)w;
-          if (tot > kLightLimit) {
-            skip = true;
-            break;
-          }
-          bnd |= lam > 1u;
-          if (S & abit) ben += (int)w;
-          C.add(L, w);
+      cand[u] = -1;
+      eligible[u] = 0;
+      continue;
+    }
+    const long long b0 = vptr[u], b1 = vptr[u + 1];
+    if (b1 - b0 > kLightLimit) continue;        // heavy vertex: the wavefront kernel owns it
+    BitCounters<WK> C;
+    C.clear();
+    int tot = 0, ben = 0;
+    bool bnd = false, heavy = false;
+    const int aw = a >> 5;
+    const unsigned abit = 1u << (a & 31);
+    for (long long j = b0; j < b1; ++j) {
+      const int e = vnets[j];
+      unsigned w, lam, S, L[WK];
+      load_rec<WK>(netstate + (long long)e * rw, aw, w, lam, L, S);
+      tot += (int)w;
+      if (tot > kLightLimit) {
+        heavy = true;
+        break;
+      }
+      bnd |= lam > 1u;
+      if (S & abit) ben += (int)w;
+      C.add(L, w);
+    }
+    if (heavy) continue;
+    eligible[u] = 0;
+    n_elig += 1;
+    long long out = -1;
+    if (bnd) {
+      n_bnd += 1;
+      n_apins += b1 - b0;
+      const long long cu = vwgt ? vwgt[u] : 1;
+      unsigned T[WK], F[WK];
+      C.nonzero(T);
+      unsigned anyF = 0;
+#pragma unroll
+      for (int w = 0; w < WK; ++w) {
+        T[w] &= valid[w];
+        if (w == aw) T[w] &= ~abit;
+        F[w] = T[w] & s_open[w];
+        unsigned rest = T[w] & ~s_open[w];
+        while (rest) {
+          int b = __ffs(rest) - 1;
+          rest &= rest - 1;
+          if (s_W[w * 32 + b] + cu <= lmax) F[w] |= 1u << b;
         }
-        if (!skip) {
-          n_elig = 1;
-          if (bnd) {
-            n_bnd = 1;
-            const long long cu = vwgt ? vwgt[u] : 1;
-            unsigned T[WK], F[WK];
-            C.nonzero(T);
-            unsigned anyF = 0;
+        anyF |= F[w];
+      }
+      if (anyF) {
+        const int conn = (int)C.narrow_to_max(F);
+        int t = -1;
+        long long tw = 0;
 #pragma unroll
-            for (int w = 0; w < WK; ++w) {
-              // only blocks < k (guards against a caller passing stale state)
-              const int lo = w * 32;
-              T[w] &= k >= lo + 32 ? ~0u : (k > lo ? (1u << (k - lo)) - 1u : 0u);
-              if (w == aw) T[w] &= ~abit;
-              F[w] = T[w] & s_open[w];
-              unsigned rest = T[w] & ~s_open[w];
-              while (rest) {
-                int b = __ffs(rest) - 1;
-                rest &= rest - 1;
-                if (s_W[w * 32 + b] + cu <= lmax) F[w] |= 1u << b;
-              }
-              anyF |= F[w];
-            }
-            if (anyF) {
-              const int conn = (int)C.narrow_to_max(F);
-              int t = -1;
-              long long tw = 0;
-#pragma unroll
-              for (int w = 0; w < WK; ++w) {
-                unsigned x = F[w];
-                while (x) {
-                  int b = __ffs(x) - 1;
-                  x &= x - 1;
-                  int i = w * 32 + b;
-                  long long Wi = s_W[i];
-                  if (t < 0 || Wi < tw) {
-                    t = i;
-                    tw = Wi;
-                  }
-                }
-              }
-              const int g = ben - tot + conn;
-              if (g > 0 || (g == 0 && tw + cu < s_W[a])) {
-                out = pack_cand(g, t);
-                n_cand = 1;
-                atomicAdd(&hist[(long long)t * kBuckets + (g < kBuckets ? g : kBuckets - 1)],
-                          (unsigned long long)cu);
-              }
+        for (int w = 0; w < WK; ++w) {
+          unsigned x = F[w];
+          while (x) {
+            int b = __ffs(x) - 1;
+            x &= x - 1;
+            int i = w * 32 + b;
+            long long Wi = s_W[i];
+            if (t < 0 || Wi < tw) {
+              t = i;
+              tw = Wi;
             }
           }
+        }
+        const int g = ben - tot + conn;
+        if (g > 0 || (g == 0 && tw + cu < s_W[a])) {
+          out = pack_cand(g, t);
+          n_cand += 1;
+          if (g < B)
+            atomicAdd(&s_hist[t * B + g], (unsigned long long)cu);
+          else
+            atomicAdd(&my_hist[t * kBuckets + (g < kBuckets ? g : kBuckets - 1)],
+                      (unsigned long long)cu);
         }
       }
     }
-    if (!skip) {
-      cand[u] = out;
-      if (el) eligible[u] = 0;
-    }
+    cand[u] = out;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < k * B; i += kBlock) {
+    const unsigned long long v = s_hist[i];
+    if (v) atomicAdd(&my_hist[(i / B) * kBuckets + (i % B)], v);
   }
   n_elig = block_sum64(n_elig, s_tmp);
   n_bnd = block_sum64(n_bnd, s_tmp);
   n_cand = block_sum64(n_cand, s_tmp);
+  n_apins = block_sum64(n_apins, s_tmp);
   if (threadIdx.x == 0) {
-    if (n_elig) atomicAdd(&ctr->eligible, (unsigned long long)n_elig);
-    if (n_bnd) atomicAdd(&ctr->boundary, (unsigned long long)n_bnd);
-    if (n_cand) atomicAdd(&ctr->candidates, (unsigned long long)n_cand);
+    const int sl = blockIdx.x % kSlots;
+    if (n_apins) atomicAdd(&ctr->slot[kCtrActivePins][sl], (unsigned long long)n_apins);
+    if (n_elig) atomicAdd(&ctr->slot[kCtrEligible][sl], (unsigned long long)n_elig);
+    if (n_bnd) atomicAdd(&ctr->slot[kCtrBoundary][sl], (unsigned long long)n_bnd);
+    if (n_cand) atomicAdd(&ctr->slot[kCtrCandidates][sl], (unsigned long long)n_cand);
   }
 }
 
@@ -201,13 +235,18 @@ __global__ __launch_bounds__(kBlock) void k_select_heavy(
   const int wv = threadIdx.x / kWave, lane = lane_id();
   const long long idx = (long long)blockIdx.x * (kBlock / kWave) + wv;
   if (idx >= heavy_count) return;
+  const int sl = (int)(idx % kSlots);
+  unsigned long long* my_hist = hist + (size_t)(blockIdx.x % kHistReplicas) * HG_MAX_K * kBuckets;
   const int u = heavy_list[idx];
   const int a = part[u];
   const unsigned char el = eligible[u];
   if (!el || (unsigned)a >= (unsigned)k) {
     if (lane == 0) {
       cand[u] = -1;
-      if (el) atomicOr(err_flags, kErrPart);
+      if (el) {
+        atomicOr(err_flags, kErrPart);
+        eligible[u] = 0;
+      }
     }
     return;
   }
@@ -265,16 +304,17 @@ __global__ __launch_bounds__(kBlock) void k_select_heavy(
   }
   if (lane == 0) {
     eligible[u] = 0;
-    atomicAdd(&ctr->eligible, 1ull);
+    atomicAdd(&ctr->slot[kCtrEligible][sl], 1ull);
     long long out = -1;
     if (bnd) {
-      atomicAdd(&ctr->boundary, 1ull);
+      atomicAdd(&ctr->slot[kCtrBoundary][sl], 1ull);
+      atomicAdd(&ctr->slot[kCtrActivePins][sl], (unsigned long long)(b1 - b0));
       if (bi >= 0) {
         const int g = ben - tot + bc;
         if (g > 0 || (g == 0 && bw + cu < s_W[a])) {
           out = pack_cand(g, bi);
-          atomicAdd(&ctr->candidates, 1ull);
-          atomicAdd(&hist[(long long)bi * kBuckets + (g < kBuckets ? g : kBuckets - 1)],
+          atomicAdd(&ctr->slot[kCtrCandidates][sl], 1ull);
+          atomicAdd(&my_hist[bi * kBuckets + (g < kBuckets ? g : kBuckets - 1)],
                     (unsigned long long)cu);
           if (g > kBuckets - 1) atomicOr(&overflow[bi], 1);
         }
@@ -286,7 +326,8 @@ __global__ __launch_bounds__(kBlock) void k_select_heavy(
 
 // --------------------------------------------------------------- threshold
 
-// One workgroup per target block t; thread j looks at gain bucket 255 - j.
+// One workgroup per target block t; thread j looks at gain bucket 255 - j
+// (summed over the XCD replicas, which it also clears for the next round).
 __global__ __launch_bounds__(kBlock) void k_threshold(int k, long long lmax,
                                                       const long long* __restrict__ block_w,
                                                       unsigned long long* __restrict__ hist,
@@ -297,15 +338,19 @@ __global__ __launch_bounds__(kBlock) void k_threshold(int k, long long lmax,
   __shared__ int s_first;
   const int t = blockIdx.x;
   const int bucket = kBuckets - 1 - threadIdx.x;
-  unsigned long long* row = hist + (long long)t * kBuckets;
-  const long long h = (long long)row[bucket];
+  long long h = 0;
+#pragma unroll
+  for (int rep = 0; rep < kHistReplicas; ++rep) {
+    unsigned long long* cell = hist + ((size_t)rep * HG_MAX_K + t) * kBuckets + bucket;
+    h += (long long)*cell;
+    *cell = 0;
+  }
   const long long budget = lmax - block_w[t];
   if (threadIdx.x == 0) s_first = kBlock;
   long long total;
   const long long above = block_excl_scan64(h, s_tmp, &total);   // weight of higher gains
   if (h > 0 && above + h > budget) atomicMin(&s_first, (int)threadIdx.x);
   __syncthreads();
-  row[bucket] = 0;
   const int f = s_first;
   if ((int)threadIdx.x == (f < kBlock ? f : 0)) {
     Threshold r;
@@ -334,20 +379,18 @@ __global__ __launch_bounds__(kBlock) void k_overflow_resolve(
     int n, int k, const long long* __restrict__ cand, const int* __restrict__ vwgt,
     int* __restrict__ overflow, Threshold* __restrict__ thr, RoundCounters* __restrict__ ctr) {
   __shared__ long long s_tmp[kBlock / kWave];
+  __shared__ long long s_max[kBlock / kWave];
   const int t = blockIdx.x;
   if (!ctr->any_overflow) return;
   if (!overflow[t]) return;
   const long long rem = thr[t].rem;
-  // largest gain present for t
   long long gmax = 0;
   for (long long u = threadIdx.x; u < n; u += kBlock) {
     long long x = cand[u];
     if (x >= 0 && cand_target(x) == t && cand_gain(x) > gmax) gmax = cand_gain(x);
   }
-  __syncthreads();
   {
     long long v = wave_max(gmax);
-    __shared__ long long s_max[kBlock / kWave];
     if (lane_id() == 0) s_max[threadIdx.x / kWave] = v;
     __syncthreads();
     gmax = 0;
@@ -363,8 +406,9 @@ __global__ __launch_bounds__(kBlock) void k_overflow_resolve(
       if (x >= 0 && cand_target(x) == t && cand_gain(x) >= mid) s += vwgt ? vwgt[u] : 1;
     }
     s = block_sum64(s, s_tmp);
-    if (s > rem) lo = mid;
-    else {
+    if (s > rem) {
+      lo = mid;
+    } else {
       hi = mid;
       w_hi = s;
     }
@@ -462,13 +506,26 @@ struct ApplyArgs {
   RoundCounters* ctr;
 };
 
+constexpr int kStage = 512;          // touched nets staged per wavefront before a flush
+
+// Copy a wavefront's staged touched nets to the global list with one atomic.
+__device__ __forceinline__ void flush_stage(const ApplyArgs& A, const TouchedNet* stage, int cnt) {
+  int base = 0;
+  if (lane_id() == 0) base = (int)atomicAdd(&A.ctr->touched, (unsigned)cnt);
+  base = __shfl(base, 0);
+  for (int j = lane_id(); j < cnt; j += kWave) A.tlist[base + j] = stage[j];
+}
+
 // Apply the moves held in s_list[0..count) (vertex ids; targets in s_tgt).
 // Each wave takes 64 movers at a time and walks their incident nets
-// load-balanced.  Block-weight changes go to s_dW.
+// load-balanced.  Block-weight changes go to s_dW; newly touched nets are
+// staged per wavefront in LDS and appended to the global list in bulk.
 __device__ void apply_list(const ApplyArgs& A, const int* s_list, const int* s_tgt, int count,
                            unsigned long long* s_dW, int* s_excl, long long* s_beg,
-                           long long& delta, long long& moved_pins, long long& approved) {
+                           TouchedNet* stage, long long& delta, long long& moved_pins,
+                           long long& approved) {
   const int wv = threadIdx.x / kWave, lane = lane_id();
+  int staged = 0;   // wave-uniform
   for (int base = wv * kWave; base < count; base += kBlock) {
     const int i = base + lane;
     int u = -1, a = 0, t = 0, len = 0;
@@ -506,14 +563,26 @@ __device__ void apply_list(const ApplyArgs& A, const int* s_list, const int* s_t
                     fresh = !(old & bit);
                     if (fresh) lam = (int)r[1];
                   }
-                  const int slot = wave_append((unsigned*)&A.ctr->touched, fresh);
+                  const unsigned long long mask = __ballot(fresh);
                   if (fresh) {
                     TouchedNet tn;
                     tn.net = e;
                     tn.lambda_old = lam;
-                    A.tlist[slot] = tn;
+                    stage[staged + __popcll(mask & (((unsigned long long)1 << lane) - 1))] = tn;
+                  }
+                  staged += __popcll(mask);
+                  if (staged > kStage - kWave) {
+                    wave_lds_sync();
+                    flush_stage(A, stage, staged);
+                    wave_lds_sync();
+                    staged = 0;
                   }
                 });
+  }
+  if (staged) {
+    wave_lds_sync();
+    flush_stage(A, stage, staged);
+    wave_lds_sync();
   }
 }
 
@@ -522,6 +591,7 @@ __global__ __launch_bounds__(kBlock) void k_approve_apply(
     const Threshold* __restrict__ thr, long long* __restrict__ block_w) {
   __shared__ int s_list[kTile];
   __shared__ int s_tgt[kTile];
+  __shared__ TouchedNet s_stage[kBlock / kWave][kStage];
   __shared__ int s_g[HG_MAX_K];
   __shared__ int s_tau[HG_MAX_K];
   __shared__ unsigned long long s_dW[HG_MAX_K];
@@ -553,7 +623,7 @@ __global__ __launch_bounds__(kBlock) void k_approve_apply(
           ok = g > gs || (g == gs && tile < s_tau[t]);
         }
       }
-      const int slot = wave_append(&s_count, ok);   // LDS counter: per-wave aggregated
+      const int slot = wave_append(&s_count, ok);   // LDS counter, one atomic per wave
       if (ok) {
         s_list[slot] = (int)u;
         s_tgt[slot] = t;
@@ -597,7 +667,8 @@ __global__ __launch_bounds__(kBlock) void k_approve_apply(
   __syncthreads();
   const int count = (int)s_count;
   long long delta = 0, moved_pins = 0, approved = 0;
-  apply_list(A, s_list, s_tgt, count, s_dW, s_excl, s_beg, delta, moved_pins, approved);
+  apply_list(A, s_list, s_tgt, count, s_dW, s_excl, s_beg, s_stage[threadIdx.x / kWave], delta,
+             moved_pins, approved);
   __syncthreads();
   for (int i = threadIdx.x; i < k; i += kBlock)
     if (s_dW[i]) atomicAdd((unsigned long long*)&block_w[i], s_dW[i]);
@@ -605,9 +676,10 @@ __global__ __launch_bounds__(kBlock) void k_approve_apply(
   moved_pins = block_sum64(moved_pins, s_tmp);
   approved = block_sum64(approved, s_tmp);
   if (threadIdx.x == 0) {
-    if (delta) atomicAdd(&A.ctr->delta_attr, (unsigned long long)delta);
-    if (moved_pins) atomicAdd(&A.ctr->moved_pins, (unsigned long long)moved_pins);
-    if (approved) atomicAdd(&A.ctr->approved, (unsigned long long)approved);
+    const int sl = blockIdx.x % kSlots;
+    if (delta) atomicAdd(&A.ctr->slot[kCtrDeltaAttr][sl], (unsigned long long)delta);
+    if (moved_pins) atomicAdd(&A.ctr->slot[kCtrMovedPins][sl], (unsigned long long)moved_pins);
+    if (approved) atomicAdd(&A.ctr->slot[kCtrApproved][sl], (unsigned long long)approved);
   }
 }
 
@@ -618,14 +690,12 @@ __global__ __launch_bounds__(kBlock) void k_finalize(
     int k, int rw, const long long* __restrict__ eptr, const int* __restrict__ pins,
     const int* __restrict__ phi, unsigned* __restrict__ netstate,
     unsigned* __restrict__ touched, const TouchedNet* __restrict__ tlist,
-    unsigned char* __restrict__ eligible, RoundCounters* __restrict__ ctr,
-    const long long* __restrict__ block_w, long long* __restrict__ km1,
-    hg_round_stats* __restrict__ stats) {
+    unsigned char* __restrict__ eligible, RoundCounters* __restrict__ ctr) {
   __shared__ long long s_tmp[kBlock / kWave];
-  __shared__ bool s_last;
   const int grp = threadIdx.x / G, gl = threadIdx.x % G;
   const long long ngroups = (long long)gridDim.x * (kBlock / G);
   const long long count = (long long)ctr->touched;
+  const int wk = bit_words(k);
   long long dcheck = 0;
   for (long long idx = (long long)blockIdx.x * (kBlock / G) + grp; idx < count; idx += ngroups) {
     const TouchedNet tn = tlist[idx];
@@ -633,7 +703,6 @@ __global__ __launch_bounds__(kBlock) void k_finalize(
     const int* row = phi + (long long)e * k;
     unsigned* rec = netstate + (long long)e * rw;
     NetBits nb = net_bits<G>(k, gl, [&](int i) { return row[i]; }, [&](int, int) {});
-    const int wk = bit_words(k);
     if (gl >= 1 && gl < 2 + 2 * wk) rec[gl] = nb.word;
     if (gl == 0) {
       const int w = (int)rec[0];
@@ -644,37 +713,49 @@ __global__ __launch_bounds__(kBlock) void k_finalize(
     for (long long p = b + gl; p < t; p += G) eligible[pins[p]] = 1;
   }
   dcheck = block_sum64(dcheck, s_tmp);
-  if (threadIdx.x == 0) {
-    if (dcheck) atomicAdd(&ctr->delta_check, (unsigned long long)dcheck);
-    __threadfence();
-    const unsigned ticket = atomicAdd(&ctr->done_final, 1u);
-    s_last = ticket == gridDim.x - 1;
+  if (threadIdx.x == 0 && dcheck)
+    atomicAdd(&ctr->slot[kCtrDeltaCheck][blockIdx.x % kSlots], (unsigned long long)dcheck);
+}
+
+// One workgroup: sum the counter slots, write the round record, move km1 by
+// the attributed drop, reset the counters for the next round.
+__global__ __launch_bounds__(kBlock) void k_round_stats(int k, RoundCounters* __restrict__ ctr,
+                                                        const long long* __restrict__ block_w,
+                                                        long long* __restrict__ km1,
+                                                        hg_round_stats* __restrict__ stats) {
+  __shared__ long long s_sum[kNumCounters];
+  __shared__ long long s_max[kBlock / kWave];
+  const int lane = lane_id(), wv = threadIdx.x / kWave;
+  for (int c = wv; c < kNumCounters; c += kBlock / kWave) {
+    long long v = (long long)ctr->slot[c][lane];
+    v = wave_sum(v);
+    if (lane == 0) s_sum[c] = v;
+    ctr->slot[c][lane] = 0;
   }
+  long long mx = LLONG_MIN;
+  for (int i = threadIdx.x; i < k; i += kBlock) mx = block_w[i] > mx ? block_w[i] : mx;
+  mx = wave_max(mx);
+  if (lane == 0) s_max[wv] = mx;
   __syncthreads();
-  if (!s_last) return;
-  __threadfence();
   if (threadIdx.x == 0) {
+    long long m = s_max[0];
+    for (int i = 1; i < kBlock / kWave; ++i) m = s_max[i] > m ? s_max[i] : m;
     hg_round_stats st;
-    st.eligible = (long long)atomicAdd(&ctr->eligible, 0ull);
-    st.boundary = (long long)atomicAdd(&ctr->boundary, 0ull);
-    st.candidates = (long long)atomicAdd(&ctr->candidates, 0ull);
-    st.approved = (long long)atomicAdd(&ctr->approved, 0ull);
-    st.moved_pins = (long long)atomicAdd(&ctr->moved_pins, 0ull);
-    st.touched_nets = (long long)atomicAdd(&ctr->touched, 0ull);
-    st.km1_delta = (long long)atomicAdd(&ctr->delta_attr, 0ull);
-    st.km1_delta_recomputed = (long long)atomicAdd(&ctr->delta_check, 0ull);
-    const long long before = *km1;
-    st.km1_after = before - st.km1_delta;
+    st.eligible = s_sum[kCtrEligible];
+    st.boundary = s_sum[kCtrBoundary];
+    st.candidates = s_sum[kCtrCandidates];
+    st.approved = s_sum[kCtrApproved];
+    st.moved_pins = s_sum[kCtrMovedPins];
+    st.touched_nets = (long long)ctr->touched;
+    st.km1_delta = s_sum[kCtrDeltaAttr];
+    st.km1_delta_recomputed = s_sum[kCtrDeltaCheck];
+    st.active_pins = s_sum[kCtrActivePins];
+    st.km1_after = *km1 - st.km1_delta;
+    st.max_block_weight = m;
     *km1 = st.km1_after;
-    long long mx = block_w[0];
-    for (int i = 1; i < k; ++i) mx = block_w[i] > mx ? block_w[i] : mx;
-    st.max_block_weight = mx;
     *stats = st;
-    ctr->eligible = ctr->boundary = ctr->candidates = 0;
-    ctr->approved = ctr->moved_pins = ctr->touched = 0;
-    ctr->delta_attr = ctr->delta_check = 0;
+    ctr->touched = 0;
     ctr->any_overflow = 0;
-    ctr->done_final = 0;
   }
 }
 
@@ -682,38 +763,44 @@ __global__ __launch_bounds__(kBlock) void k_finalize(
 
 int group_lanes(int k);
 
+static int lds_buckets(int k) {
+  int b = kBuckets;
+  while (b > 1 && b * k > kLdsHistEntries) b >>= 1;
+  return b;
+}
+
 template <int WK>
 static void launch_select_light(hg_graph_s* g, int k, long long lmax, const int* part,
                                 const unsigned* netstate, const long long* block_w,
                                 unsigned char* eligible, unsigned char* moved, hipStream_t s) {
   char* ws = g->ws;
-  unsigned grid = (unsigned)(((long long)g->n + kBlock - 1) / kBlock);
+  long long chunks = ((long long)g->n + kBlock - 1) / kBlock;
+  unsigned grid = (unsigned)(chunks < kSelectGrid ? chunks : kSelectGrid);
   hipLaunchKernelGGL(k_select_light<WK>, dim3(grid), dim3(kBlock), 0, s, g->n, k, net_words(k),
-                     lmax, g->info.max_vertex_weight, g->vptr, g->vnets, g->vwgt, part, netstate,
-                     block_w, eligible, moved, (long long*)(ws + g->lay.cand),
+                     lds_buckets(k), lmax, g->info.max_vertex_weight, g->vptr, g->vnets, g->vwgt,
+                     part, netstate, block_w, eligible, moved, (long long*)(ws + g->lay.cand),
                      (unsigned long long*)(ws + g->lay.hist), (RoundCounters*)(ws + g->lay.ctr),
                      (int*)(ws + g->lay.flags));
 }
 
 template <int G>
 static void launch_finalize(hg_graph_s* g, int k, const int* phi, unsigned* netstate,
-                            unsigned char* eligible, const long long* block_w, long long* km1,
-                            hg_round_stats* stats, hipStream_t s) {
+                            unsigned char* eligible, hipStream_t s) {
   char* ws = g->ws;
-  long long groups = (long long)g->m;
-  long long blocks = (groups + (kBlock / G) - 1) / (kBlock / G);
-  if (blocks > 2048) blocks = 2048;
+  long long blocks = ((long long)g->m + (kBlock / G) - 1) / (kBlock / G);
+  if (blocks > kFinalizeGrid) blocks = kFinalizeGrid;
   hipLaunchKernelGGL(k_finalize<G>, dim3((unsigned)blocks), dim3(kBlock), 0, s, k, net_words(k),
                      g->eptr, g->pins, phi, netstate, (unsigned*)(ws + g->lay.touched),
                      (const TouchedNet*)(ws + g->lay.tlist), eligible,
-                     (RoundCounters*)(ws + g->lay.ctr), block_w, km1, stats);
+                     (RoundCounters*)(ws + g->lay.ctr));
 }
 
 hipError_t launch_lp_round(hg_graph_s* g, int k, long long lmax, int* part, int* phi,
                            unsigned* netstate, long long* block_w, unsigned char* eligible,
                            unsigned char* moved, long long* km1, hg_round_stats* stats,
-                           hipStream_t s) {
+                           hipStream_t s, hipEvent_t* marks) {
   char* ws = g->ws;
+  if (marks) (void)hipEventRecord(marks[0], s);
   switch (bit_words(k)) {
     case 1: launch_select_light<1>(g, k, lmax, part, netstate, block_w, eligible, moved, s); break;
     case 2: launch_select_light<2>(g, k, lmax, part, netstate, block_w, eligible, moved, s); break;
@@ -733,6 +820,7 @@ hipError_t launch_lp_round(hg_graph_s* g, int k, long long lmax, int* part, int*
                        netstate, block_w, eligible, cand, hist, overflow, ctr,
                        (int*)(ws + g->lay.flags));
   }
+  if (marks) (void)hipEventRecord(marks[1], s);
   hipLaunchKernelGGL(k_threshold, dim3(k), dim3(kBlock), 0, s, k, lmax, block_w, hist, overflow,
                      thr, ctr);
   if (heavy > 0)
@@ -758,13 +846,16 @@ hipError_t launch_lp_round(hg_graph_s* g, int k, long long lmax, int* part, int*
   A.ctr = ctr;
   hipLaunchKernelGGL(k_approve_apply, dim3(nt + k), dim3(kBlock), 0, s, g->n, nt, A, cand, thr,
                      block_w);
+  if (marks) (void)hipEventRecord(marks[2], s);
   switch (group_lanes(k)) {
-    case 4: launch_finalize<4>(g, k, phi, netstate, eligible, block_w, km1, stats, s); break;
-    case 8: launch_finalize<8>(g, k, phi, netstate, eligible, block_w, km1, stats, s); break;
-    case 16: launch_finalize<16>(g, k, phi, netstate, eligible, block_w, km1, stats, s); break;
-    case 32: launch_finalize<32>(g, k, phi, netstate, eligible, block_w, km1, stats, s); break;
-    default: launch_finalize<64>(g, k, phi, netstate, eligible, block_w, km1, stats, s); break;
+    case 4: launch_finalize<4>(g, k, phi, netstate, eligible, s); break;
+    case 8: launch_finalize<8>(g, k, phi, netstate, eligible, s); break;
+    case 16: launch_finalize<16>(g, k, phi, netstate, eligible, s); break;
+    case 32: launch_finalize<32>(g, k, phi, netstate, eligible, s); break;
+    default: launch_finalize<64>(g, k, phi, netstate, eligible, s); break;
   }
+  hipLaunchKernelGGL(k_round_stats, dim3(1), dim3(kBlock), 0, s, k, ctr, block_w, km1, stats);
+  if (marks) (void)hipEventRecord(marks[3], s);
   return hipGetLastError();
 }
 

@@ -13,44 +13,54 @@
 
 namespace hg {
 
+constexpr int kStateGrid = 2048;   // persistent workgroups of the net sweep
+
 // G lanes per net (G divides 64); LDS counters: (kBlock/G) groups x k ints.
+// Workgroup lb owns a contiguous run of nets (XCD-aware order).
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_pincounts(int m, int k, int rw,
-                                                      const long long* eptr, const int* pins,
-                                                      const int* ewgt, const int* part,
-                                                      int* phi, unsigned* netstate,
-                                                      unsigned long long* km1_acc,
-                                                      int* err_flags, int n) {
+                                                      const long long* __restrict__ eptr,
+                                                      const int* __restrict__ pins,
+                                                      const int* __restrict__ ewgt,
+                                                      const int* __restrict__ part,
+                                                      int* __restrict__ phi,
+                                                      unsigned* __restrict__ netstate,
+                                                      unsigned long long* __restrict__ km1_slots,
+                                                      int* __restrict__ err_flags) {
   extern __shared__ int s_cnt[];   // [kBlock/G][k]
   __shared__ long long s_tmp[kBlock / kWave];
-  const int grp_in_block = threadIdx.x / G;
-  const int gl = threadIdx.x % G;                      // lane within group
-  int* cnt = s_cnt + grp_in_block * k;
-  const long long groups = (long long)gridDim.x * (kBlock / G);
-  const unsigned lb = xcd_remap(blockIdx.x, gridDim.x);
+  constexpr int kGroups = kBlock / G;
+  const int grp = threadIdx.x / G;
+  const int gl = threadIdx.x % G;
+  int* cnt = s_cnt + grp * k;
+  const long long lb = xcd_remap(blockIdx.x, gridDim.x);
+  const long long per = (((long long)m + kGroups - 1) / kGroups + gridDim.x - 1) / gridDim.x;
+  const long long e_begin = lb * per * kGroups;
+  long long e_end = e_begin + per * kGroups;
+  if (e_end > m) e_end = m;
   long long km1_local = 0;
   int err = 0;
-  for (long long e = (long long)lb * (kBlock / G) + grp_in_block; e < m; e += groups) {
+  for (long long e = e_begin + grp; e < e_end; e += kGroups) {
     for (int i = gl; i < k; i += G) cnt[i] = 0;
     wave_lds_sync();
-    long long b = eptr[e], t = eptr[e + 1];
+    const long long b = eptr[e], t = eptr[e + 1];
     for (long long p = b + gl; p < t; p += G) {
-      int v = pins[p];
-      int blk = part[v];
+      const int blk = part[pins[p]];
       if ((unsigned)blk < (unsigned)k) atomicAdd(&cnt[blk], 1);
       else err = kErrPart;
     }
     wave_lds_sync();
     NetBits bits;
     netbits_from_counts<G>(cnt, k, gl, bits, phi + e * (long long)k);
-    int w = ewgt ? ewgt[e] : 1;
+    const int w = ewgt ? ewgt[e] : 1;
     write_netrec(netstate + e * (long long)rw, gl, w, bits, k);
     if (gl == 0) km1_local += (long long)(bits.lambda - 1) * w;
     wave_lds_sync();
   }
   if (err) atomicOr(err_flags, err);
-  long long tot = block_sum64(km1_local, s_tmp);
-  if (threadIdx.x == 0 && km1_acc) atomicAdd(km1_acc, (unsigned long long)tot);
+  const long long tot = block_sum64(km1_local, s_tmp);
+  if (threadIdx.x == 0 && tot)
+    atomicAdd(&km1_slots[blockIdx.x % kSlots], (unsigned long long)tot);
 }
 
 // Block weights: LDS partial sums per workgroup, then one atomic per block.
@@ -76,9 +86,9 @@ __global__ __launch_bounds__(kBlock) void k_block_weights(int n, int k, const in
     if (s_w[i]) atomicAdd(&block_w[i], s_w[i]);
 }
 
-// km1 = sum_e (lambda(e) - 1) w(e) from the net-state records.
+// km1 partial sums from the net-state records.
 __global__ __launch_bounds__(kBlock) void k_km1(int m, int rw, const unsigned* netstate,
-                                                unsigned long long* km1_acc) {
+                                                unsigned long long* km1_slots) {
   __shared__ long long s_tmp[kBlock / kWave];
   long long stride = (long long)gridDim.x * kBlock;
   long long acc = 0;
@@ -87,24 +97,33 @@ __global__ __launch_bounds__(kBlock) void k_km1(int m, int rw, const unsigned* n
     acc += (long long)((int)r[1] - 1) * (int)r[0];
   }
   acc = block_sum64(acc, s_tmp);
-  if (threadIdx.x == 0) atomicAdd(km1_acc, (unsigned long long)acc);
+  if (threadIdx.x == 0 && acc) atomicAdd(&km1_slots[blockIdx.x % kSlots], (unsigned long long)acc);
 }
 
-static unsigned persistent_grid(long long items, int per_block) {
+// Sum the kSlots partials into *out and clear them (one wavefront).
+__global__ void k_sum_slots(unsigned long long* slots, long long* out) {
+  const int lane = lane_id();
+  long long v = (long long)slots[lane];
+  slots[lane] = 0;
+  v = wave_sum(v);
+  if (lane == 0) *out = v;
+}
+
+static unsigned grid_cap(long long items, int per_block, int cap) {
   long long b = (items + per_block - 1) / per_block;
   if (b < 1) b = 1;
-  if (b > 32768) b = 32768;
+  if (b > cap) b = cap;
   return (unsigned)b;
 }
 
 template <int G>
 static void launch_pincounts_g(hg_graph_s* g, int k, const int* part, int* phi,
-                               unsigned* netstate, unsigned long long* km1, int* err,
+                               unsigned* netstate, unsigned long long* slots, int* err,
                                hipStream_t s) {
-  unsigned grid = persistent_grid(g->m, kBlock / G);
+  unsigned grid = grid_cap(g->m, kBlock / G, kStateGrid);
   size_t lds = sizeof(int) * (size_t)(kBlock / G) * k;
   hipLaunchKernelGGL(k_pincounts<G>, dim3(grid), dim3(kBlock), lds, s, g->m, k, net_words(k),
-                     g->eptr, g->pins, g->ewgt, part, phi, netstate, km1, err, g->n);
+                     g->eptr, g->pins, g->ewgt, part, phi, netstate, slots, err);
 }
 
 int group_lanes(int k) {
@@ -119,34 +138,35 @@ hipError_t launch_pincounts(hg_graph_s* g, int k, const int* part, int* phi,
                             unsigned* netstate, long long* block_w, long long* km1,
                             hipStream_t s) {
   int* err = (int*)(g->ws + g->lay.flags);
-  hipError_t e;
+  unsigned long long* slots = (unsigned long long*)(g->ws + g->lay.red);
+  switch (group_lanes(k)) {
+    case 4: launch_pincounts_g<4>(g, k, part, phi, netstate, slots, err, s); break;
+    case 8: launch_pincounts_g<8>(g, k, part, phi, netstate, slots, err, s); break;
+    case 16: launch_pincounts_g<16>(g, k, part, phi, netstate, slots, err, s); break;
+    case 32: launch_pincounts_g<32>(g, k, part, phi, netstate, slots, err, s); break;
+    default: launch_pincounts_g<64>(g, k, part, phi, netstate, slots, err, s); break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   if (km1) {
-    e = fill_i64(km1, 0, 1, s);
+    hipLaunchKernelGGL(k_sum_slots, dim3(1), dim3(kWave), 0, s, slots, km1);
+  } else {
+    e = fill_i64((long long*)slots, 0, kSlots, s);
     if (e != hipSuccess) return e;
   }
-  unsigned long long* km1u = (unsigned long long*)km1;
-  switch (group_lanes(k)) {
-    case 4: launch_pincounts_g<4>(g, k, part, phi, netstate, km1u, err, s); break;
-    case 8: launch_pincounts_g<8>(g, k, part, phi, netstate, km1u, err, s); break;
-    case 16: launch_pincounts_g<16>(g, k, part, phi, netstate, km1u, err, s); break;
-    case 32: launch_pincounts_g<32>(g, k, part, phi, netstate, km1u, err, s); break;
-    default: launch_pincounts_g<64>(g, k, part, phi, netstate, km1u, err, s); break;
-  }
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
   e = fill_i64(block_w, 0, k, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_block_weights, dim3(persistent_grid(g->n, kBlock * 16)), dim3(kBlock),
-                     0, s, g->n, k, part, g->vwgt, (unsigned long long*)block_w, err);
+  hipLaunchKernelGGL(k_block_weights, dim3(grid_cap(g->n, kBlock * 16, 4096)), dim3(kBlock), 0,
+                     s, g->n, k, part, g->vwgt, (unsigned long long*)block_w, err);
   return hipGetLastError();
 }
 
 hipError_t launch_km1(hg_graph_s* g, int k, const unsigned* netstate, long long* km1,
                       hipStream_t s) {
-  hipError_t e = fill_i64(km1, 0, 1, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_km1, dim3(persistent_grid(g->m, kBlock * 8)), dim3(kBlock), 0, s, g->m,
-                     net_words(k), netstate, (unsigned long long*)km1);
+  unsigned long long* slots = (unsigned long long*)(g->ws + g->lay.red);
+  hipLaunchKernelGGL(k_km1, dim3(grid_cap(g->m, kBlock * 8, kStateGrid)), dim3(kBlock), 0, s,
+                     g->m, net_words(k), netstate, slots);
+  hipLaunchKernelGGL(k_sum_slots, dim3(1), dim3(kWave), 0, s, slots, km1);
   return hipGetLastError();
 }
 

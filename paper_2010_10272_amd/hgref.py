@@ -22,7 +22,9 @@ HG_ERR_WORKSPACE = -4
 HG_MAX_K = 256
 
 STATS_FIELDS = ("eligible", "boundary", "candidates", "approved", "moved_pins", "touched_nets",
-                "km1_delta", "km1_after", "max_block_weight", "km1_delta_recomputed")
+                "km1_delta", "km1_after", "max_block_weight", "km1_delta_recomputed",
+                "active_pins")
+HG_PHASES = ("select", "approve", "finalize")
 STATS_WORDS = len(STATS_FIELDS)
 
 
@@ -70,6 +72,10 @@ def _load():
     lib.hg_lp_round.restype = i32
     lib.hg_refine.argtypes = [vp, i32, dbl, i32, vp, vp, vp, vp, vp, vp, vp, i32, vp]
     lib.hg_refine.restype = i32
+    lib.hg_timing_enable.argtypes = [vp, i32]
+    lib.hg_timing_enable.restype = i32
+    lib.hg_timing_collect.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+    lib.hg_timing_collect.restype = i32
     lib.hg_sync_status.argtypes = [vp, vp]
     lib.hg_sync_status.restype = i32
     lib.hg_last_error.argtypes = []
@@ -153,9 +159,10 @@ class Graph:
 
 
 def hg_load_csr(n, eptr, pins, vwgt=None, ewgt=None, k_max=HG_MAX_K, device="cuda",
-                stream=None):
+                stream=None, out=None):
     """Load a net-CSR hypergraph (arrays or tensors) onto the device and build
-    its incidence CSR.  Returns a Graph.  Synchronizes the stream."""
+    its incidence CSR.  Returns a Graph.  Synchronizes the stream.  `out` may
+    supply preallocated (vptr, vnets, workspace) device tensors."""
     device = torch.device(device)
     eptr = _dev(eptr, torch.int64, device)
     pins = _dev(pins, torch.int32, device)
@@ -167,9 +174,14 @@ def hg_load_csr(n, eptr, pins, vwgt=None, ewgt=None, k_max=HG_MAX_K, device="cud
     if ws_bytes == 0:
         raise HgError(HG_ERR_UNSUPPORTED, "unsupported sizes n=%d m=%d P=%d k_max=%d"
                       % (n, m, P, k_max))
-    vptr = torch.empty(n + 1, dtype=torch.int64, device=device)
-    vnets = torch.empty(max(P, 1), dtype=torch.int32, device=device)
-    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=device)
+    if out is not None:
+        vptr, vnets, ws = out
+        if vptr.numel() < n + 1 or vnets.numel() < P or ws.numel() < ws_bytes:
+            raise ValueError("preallocated buffers too small")
+    else:
+        vptr = torch.empty(n + 1, dtype=torch.int64, device=device)
+        vnets = torch.empty(max(P, 1), dtype=torch.int32, device=device)
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device=device)
     h = ctypes.c_void_p()
     _check(_lib.hg_load_csr(int(n), m, P, _ptr(eptr), _ptr(pins), _ptr(vwgt), _ptr(ewgt),
                             _ptr(vptr), _ptr(vnets), _ptr(ws), ws_bytes, int(k_max),
@@ -244,6 +256,19 @@ def hg_refine(g, st, eps, rounds, stats, use_graph=True, stream=None):
     _check(_lib.hg_refine(g.handle, st.k, float(eps), int(rounds), _ptr(st.part), _ptr(st.phi),
                           _ptr(st.netstate), _ptr(st.block_w), _ptr(st.eligible), _ptr(stats),
                           _ptr(st.km1), 1 if use_graph else 0, _stream(stream)))
+
+
+def hg_timing_enable(g, enable=True):
+    _check(_lib.hg_timing_enable(g.handle, 1 if enable else 0))
+
+
+def hg_timing_collect(g):
+    """Per-phase milliseconds summed over the rounds timed since the last call,
+    and the number of those rounds."""
+    ms = (ctypes.c_double * len(HG_PHASES))()
+    rounds = ctypes.c_int64(0)
+    _check(_lib.hg_timing_collect(g.handle, ms, ctypes.byref(rounds)))
+    return dict(zip(HG_PHASES, list(ms))), int(rounds.value)
 
 
 def hg_sync_status(g, stream=None):

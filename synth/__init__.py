@@ -3,4 +3,4 @@
 Input generation only: nothing here computes pin counts, gains or moves.
 """
 from .hypergraphs import (Instance, describe, random_power_law, sparse_matrix,  # noqa: F401
-                          tiny_plain, vlsi_grid)
+                          tiny_plain, vlsi_grid, with_k)

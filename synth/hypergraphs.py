@@ -166,7 +166,17 @@ def sparse_matrix(k, seed=2, rows=1_000_000, cols=1_000_000, band=5_000, rounds=
     w = np.ones(rows, np.int32)
     part = (perm % k).astype(np.int32)
     return Instance("sparse-matrix-1Mx1M-k%d" % k, cols, eptr, pins, c, w, part, k, 0.03,
-                    rounds, {"seed": seed})
+                    rounds, {"seed": seed, "perm": perm})
+
+
+def with_k(inst, k):
+    """The same hypergraph with the start partition perm[v] mod k (for the
+    instances whose start is drawn as a random permutation)."""
+    perm = inst.meta["perm"]
+    part = (perm % k).astype(np.int32)
+    name = inst.name.rsplit("-k", 1)[0] + "-k%d" % k
+    return Instance(name, inst.n, inst.eptr, inst.pins, inst.c, inst.w, part, k, inst.eps,
+                    inst.rounds, dict(inst.meta))
 
 
 def vlsi_grid(seed=3, side=2000, height=2000, m=4_200_000, k=16, rounds=10):

@@ -57,7 +57,7 @@ def lp_round(nets, n, c, w, k, lmax, part, eligible):
     cw = (lambda v: 1) if c is None else (lambda v: int(c[v]))
     cands = []
     stats = dict(eligible=0, boundary=0, candidates=0, approved=0, moved_pins=0,
-                 touched_nets=0)
+                 touched_nets=0, active_pins=0)
     for u in range(n):
         if not eligible[u]:
             continue
@@ -66,6 +66,7 @@ def lp_round(nets, n, c, w, k, lmax, part, eligible):
         if not any(len(blocks_of(nets[j], part)) > 1 for j in inc):
             continue
         stats["boundary"] += 1
+        stats["active_pins"] += len(inc)
         a = part[u]
         neighbour_blocks = set()
         for j in inc:
