@@ -90,6 +90,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-rounds", type=int, default=4)
     ap.add_argument("--latency-reps", type=int, default=5)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run one plain device-to-device copy of MIB MiB (a known "
+                         "byte count for scaling HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -246,6 +249,15 @@ def main():
         "graph_refine_ms": graph_ms,
         "km1_final": {"k%d" % k: per_k[k][-1]["km1_after"] for k in KS},
     }
+    if args.calibrate_copy > 0:
+        nb = args.calibrate_copy << 20
+        src = torch.ones(nb // 4, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibrate_copy_bytes"] = nb
+        del src, dst
     if not args.no_cpu:
         print("cpu baseline ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_rounds)

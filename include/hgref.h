@@ -100,18 +100,29 @@ typedef struct {
  * 2 + 2*ceil(k/32) rounded up to a power of two (4, 8, 16 or 32).  Returns 0
  * for an unsupported k.
  *
- * Net-state layout (uint32 netstate[m * hg_net_words(k)], row e):
+ * Net-state layout: uint32 netstate[hg_netstate_words(m, k)].  The first
+ * m * hg_net_words(k) words hold one record per net (row e):
  *   word 0                 w(e), the net weight (copied at pin-count time)
  *   word 1                 lambda(e) = |Lambda(e)|
  *   words 2 .. 2+W-1       Lambda(e) as a bitset: bit i%32 of word 2+i/32 is
- *                          set iff Phi(e,i) > 0          (W = ceil(k/32))
+ *                          set iff Phi(e,i) > 0  (W = ceil(k/32) rounded up
+ *                          to 1, 2, 4 or 8)
  *   words 2+W .. 2+2W-1    S(e): bit i set iff Phi(e,i) == 1 (blocks holding
  *                          exactly one pin of e; b(u) needs only this)
  *   remaining words        zero
+ * For k <= 64 a compact copy of the two bitsets follows the records, V words
+ * per net (V = 1 for k <= 16: Lambda in bits 0-15, S in bits 16-31; V = 2 for
+ * k <= 32: Lambda, S; V = 4 for k <= 64: Lambda lo, hi, S lo, hi).  It is
+ * kept up to date only when every net weight is 1, and then the gain sweeps
+ * read it instead of the full records.  Callers treat it as opaque.
  * The paper keeps Phi(e,i) and Lambda(e) per net in its partition data
  * structure (subsection "Data Structures for Gain Calculation"); this packs
  * what a gain computation reads for one net into one aligned record. */
 int32_t hg_net_words(int32_t k);
+
+/* Total 32-bit words of a net-state array for m nets and k blocks (records
+ * plus the compact copy described above); 0 for unsupported arguments. */
+int64_t hg_netstate_words(int32_t m, int32_t k);
 
 /* Bytes of device workspace needed for a hypergraph with n vertices, m nets
  * and P pins, refined with any k <= k_max.  0 if the sizes are unsupported. */

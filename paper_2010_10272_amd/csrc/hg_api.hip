@@ -122,8 +122,7 @@ WsLayout ws_layout(int n, int m, long long P, int k_max) {
   L.num_tiles = (int)(((long long)n + kTile - 1) / kTile);
   L.scan_blocks = (int)(((long long)n + kBlock * 8 - 1) / (kBlock * 8));
   L.cand = take(sizeof(long long) * (size_t)n);
-  L.touched = take(sizeof(unsigned) * (((size_t)m + 31) / 32));
-  L.tlist = take(sizeof(int) * 2 * (size_t)m);
+  L.touched = take(touched_bytes(m));   // one flag byte per net, zero past m
   L.heavy = take(sizeof(int) * (size_t)n);
   L.big = take(sizeof(int) * (size_t)n);
   L.hist = take(sizeof(unsigned long long) * (size_t)kHistReplicas * HG_MAX_K * kBuckets);
@@ -144,6 +143,11 @@ WsLayout ws_layout(int n, int m, long long P, int k_max) {
 extern "C" {
 
 int32_t hg_net_words(int32_t k) { return hg::net_words(k); }
+
+int64_t hg_netstate_words(int32_t m, int32_t k) {
+  if (m < 1 || hg::net_words(k) == 0) return 0;
+  return (int64_t)m * (hg::net_words(k) + hg::view_words(k));
+}
 
 size_t hg_workspace_size(int32_t n, int32_t m, int64_t P, int32_t k_max) {
   if (n < 1 || m < 1 || P < m || P > kMaxPins || k_max < 2 || k_max > HG_MAX_K) return 0;
@@ -212,7 +216,7 @@ hg_status hg_load_csr(int32_t n, int32_t m, int64_t P, const int64_t* eptr, cons
   if (e != hipSuccess) return bail(hip_fail(e, "incidence sort"));
   // zero the round state kept in the workspace
   char* ws = g->ws;
-  e = hg::fill_i32((int*)(ws + lay.touched), 0, ((long long)m + 31) / 32, s);
+  e = hg::fill_u8((unsigned char*)(ws + lay.touched), 0, (long long)hg::touched_bytes(m), s);
   if (e == hipSuccess)
     e = hg::fill_i64((long long*)(ws + lay.hist), 0,
                      (long long)hg::kHistReplicas * HG_MAX_K * hg::kBuckets, s);
@@ -225,6 +229,7 @@ hg_status hg_load_csr(int32_t n, int32_t m, int64_t P, const int64_t* eptr, cons
   st = read_info(g, s);
   if (st != HG_OK) return bail(st);
   if (g->info.err) return bail(fail(HG_ERR_INVALID, "%s", describe_err(g->info.err)));
+  g->unit_nets = g->info.total_net_weight == (unsigned long long)m;
   *out = g;
   return HG_OK;
 }

@@ -9,13 +9,15 @@
 #include "hg_bits.h"
 #include "hg_device.h"
 #include "hg_internal.h"
+#include "hg_sweep.h"
 
 namespace hg {
 
-template <int WK>
+template <int WK, int VIEW>
 __global__ __launch_bounds__(kBlock) void k_gains_light(
     int n, int k, int rw, const long long* __restrict__ vptr, const int* __restrict__ vnets,
     const int* __restrict__ part, const unsigned* __restrict__ netstate,
+    const unsigned* __restrict__ view,
     long long* __restrict__ gains, long long* __restrict__ benefit, int* __restrict__ err_flags) {
   const unsigned lb = xcd_remap(blockIdx.x, gridDim.x);
   const long long u = (long long)lb * kBlock + threadIdx.x;
@@ -35,25 +37,32 @@ __global__ __launch_bounds__(kBlock) void k_gains_light(
   int tot = 0, ben = 0;
   const int aw = a >> 5;
   const unsigned abit = 1u << (a & 31);
-  for (long long j = b0; j < b1; ++j) {
-    const unsigned* r = netstate + (long long)vnets[j] * rw;
-    const uint4 q = *reinterpret_cast<const uint4*>(r);
-    const unsigned w = q.x;
-    tot += (int)w;
-    if (tot > kLightLimit) return;                  // heavy: other kernel
-    unsigned L[WK];
-    L[0] = q.z;
-    unsigned S;
-    if (WK == 1) {
-      S = q.w;
-    } else {
-      L[1] = q.w;
+  for (long long j = b0; j < b1; j += kUnroll) {
+    unsigned w[kUnroll], S[kUnroll], L[kUnroll][WK];
+    bool cut[kUnroll];
+    int e[kUnroll];
 #pragma unroll
-      for (int x = 2; x < WK; ++x) L[x] = r[2 + x];
-      S = r[2 + WK + aw];
+    for (int q = 0; q < kUnroll; ++q) e[q] = j + q < b1 ? vnets[j + q] : -1;
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) {
+      if (e[q] >= 0) {
+        read_net<WK, VIEW>(netstate, rw, view, e[q], aw, w[q], cut[q], L[q], S[q]);
+      } else {
+        w[q] = 0;
+        S[q] = 0;
+#pragma unroll
+        for (int x = 0; x < WK; ++x) L[q][x] = 0;
+      }
     }
-    if (S & abit) ben += (int)w;
-    C.add(L, w);
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) {
+      tot += (int)w[q];
+      if (S[q] & abit) ben += (int)w[q];
+    }
+    if (tot > kLightLimit) return;                  // heavy: other kernel
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q)
+      if (w[q]) C.add(L[q], w[q]);
   }
   const long long base = (long long)ben - tot;
 #pragma unroll
@@ -123,8 +132,16 @@ template <int WK>
 static void launch_light(hg_graph_s* g, int k, const int* part, const unsigned* netstate,
                          long long* gains, long long* benefit, hipStream_t s) {
   unsigned grid = (unsigned)(((long long)g->n + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_gains_light<WK>, dim3(grid), dim3(kBlock), 0, s, g->n, k, net_words(k),
-                     g->vptr, g->vnets, part, netstate, gains, benefit,
+  const unsigned* view = netstate + (size_t)g->m * net_words(k);
+  auto kern = k_gains_light<WK, kViewFull>;
+  switch (net_view(k, g->unit_nets)) {
+    case kView16: kern = k_gains_light<1, kView16>; break;
+    case kView32: kern = k_gains_light<1, kView32>; break;
+    case kView64: kern = k_gains_light<2, kView64>; break;
+    default: break;
+  }
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, g->n, k, net_words(k), g->vptr,
+                     g->vnets, part, netstate, view, gains, benefit,
                      (int*)(g->ws + g->lay.flags));
 }
 

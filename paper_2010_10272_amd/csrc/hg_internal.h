@@ -17,7 +17,7 @@ namespace hg {
 
 constexpr int kWave = 64;
 constexpr int kBlock = 256;            // threads per workgroup in every kernel
-constexpr int kTile = 4096;            // vertices per approval tile (256 threads x 16)
+constexpr int kTile = 1024;            // vertices per approval tile (256 threads x 4)
 constexpr int kPerThreadTile = kTile / kBlock;
 constexpr int kBuckets = 256;          // gain buckets per target block (0..254 exact, 255 = ">=255")
 constexpr int kLightLimit = 255;       // w(I(v)) <= 255: bit-sliced register path
@@ -26,7 +26,8 @@ constexpr int kSmallRow = 64;          // incidence rows up to this length sort 
 constexpr int kNumXcd = 8;             // MI355X: 8 XCDs, each with its own L2
 constexpr int kLdsHistEntries = 2048;  // per-workgroup LDS gain histogram (k * buckets)
 constexpr int kSelectGrid = 2048;      // persistent workgroups of the select sweep
-constexpr int kFinalizeGrid = 1024;    // persistent workgroups of the finalize sweep
+constexpr int kUnroll = 4;             // record gathers in flight per thread in the sweeps
+constexpr int kFinalizeGrid = 16384;   // persistent workgroups of the finalize sweep
 
 // Validation bits raised on the device.
 enum : int {
@@ -54,15 +55,15 @@ enum CounterId : int {
   kCtrDeltaAttr,    // two's complement int64 sums
   kCtrDeltaCheck,
   kCtrActivePins,
+  kCtrTouched,
   kNumCounters
 };
 
 // Per-round counters kept in the workspace.  Zero between rounds.
 struct RoundCounters {
   unsigned long long slot[kNumCounters][kSlots];
-  unsigned int touched;            // length of the touched-net list
   unsigned int any_overflow;       // some block's threshold fell into the ">=255" bucket
-  unsigned int pad[62];
+  unsigned int pad[63];
 };
 
 // Approval threshold of one target block.
@@ -88,7 +89,7 @@ struct LoadInfo {
 };
 
 struct WsLayout {
-  size_t cand, touched, tlist, heavy, big, hist, overflow, thr, tilesum, ctr, info, scan, flags;
+  size_t cand, touched, heavy, big, hist, overflow, thr, tilesum, ctr, info, scan, flags;
   size_t red;   // kSlots partial sums for whole-array reductions (km1)
   size_t total;
   int num_tiles;
@@ -97,12 +98,41 @@ struct WsLayout {
 
 WsLayout ws_layout(int n, int m, long long P, int k_max);
 
+// Touched-net flags: one byte per net, padded to whole finalize chunks of
+// 1024 nets so that the sweep reads them four at a time without bounds tests.
+inline size_t touched_bytes(int m) { return (((size_t)m + 1023) / 1024) * 1024; }
+
 // 32-bit words per block bitset in a net record: ceil(k/32) rounded up to a
 // power of two (1, 2, 4 or 8), so that word offsets are compile-time friendly.
 __host__ __device__ inline int bit_words(int k) {
   int w = 1;
   while (w * 32 < k) w *= 2;
   return w;
+}
+
+// Compact per-net view read by the select and gain sweeps when every net
+// weight is 1 and k <= 64: only the Lambda and S bitsets, packed into 4, 8 or
+// 16 bytes (w(e) = 1 is implied and lambda(e) = popcount(Lambda)).  With k <=
+// 16 a million nets take 4 MB, one XCD's L2.  kViewFull means the sweeps read
+// the full net record instead.
+enum NetView : int { kViewFull = 0, kView16 = 1, kView32 = 2, kView64 = 3 };
+
+__host__ __device__ inline int net_view(int k, bool unit_nets) {
+  if (!unit_nets) return kViewFull;
+  if (k <= 16) return kView16;
+  if (k <= 32) return kView32;
+  if (k <= 64) return kView64;
+  return kViewFull;
+}
+
+__host__ __device__ inline int view_bytes(int view) {
+  return view == kView16 ? 4 : view == kView32 ? 8 : view == kView64 ? 16 : 0;
+}
+
+// 32-bit words per net reserved for the compact view in a net-state array
+// (present for every k <= 64; maintained only for unit net weights).
+__host__ __device__ inline int view_words(int k) {
+  return k <= 16 ? 1 : k <= 32 ? 2 : k <= 64 ? 4 : 0;
 }
 
 // Words per net record: 2 + 2 * bit_words(k) rounded up to a power of two.
@@ -128,6 +158,7 @@ struct hg_graph_s {
   char* ws;
   size_t ws_bytes;
   int k_max;
+  bool unit_nets;    // every net weight is 1 (the compact net view is maintained)
   hg::WsLayout lay;
   hg::LoadInfo info;
   // recorded refinement graph (hipGraphExec_t) and the private stream it is

@@ -29,6 +29,7 @@
 #include "hg_device.h"
 #include "hg_internal.h"
 #include "hg_netrec.h"
+#include "hg_sweep.h"
 
 namespace hg {
 
@@ -38,31 +39,7 @@ __device__ __forceinline__ long long pack_cand(int gain, int target) {
 __device__ __forceinline__ int cand_target(long long x) { return (int)(x & 0xffffffffLL); }
 __device__ __forceinline__ int cand_gain(long long x) { return (int)(x >> 32); }
 
-struct TouchedNet {
-  int net;
-  int lambda_old;
-};
-
 // --------------------------------------------------------------- select
-
-// Record words 0 .. 1+WK (w, lambda, Lambda) plus the S word of block a.
-template <int WK>
-__device__ __forceinline__ void load_rec(const unsigned* __restrict__ r, int aw, unsigned& w,
-                                         unsigned& lam, unsigned (&L)[WK], unsigned& S) {
-  const uint4 q = *reinterpret_cast<const uint4*>(r);
-  w = q.x;
-  lam = q.y;
-  if (WK == 1) {
-    L[0] = q.z;
-    S = q.w;
-  } else {
-    L[0] = q.z;
-    L[1] = q.w;
-#pragma unroll
-    for (int j = 2; j < WK; ++j) L[j] = r[2 + j];
-    S = r[2 + WK + aw];
-  }
-}
 
 // Light vertices, one thread each, on a persistent grid: workgroup lb owns
 // a contiguous run of 256-vertex chunks (so each XCD sweeps one vertex range
@@ -70,12 +47,13 @@ __device__ __forceinline__ void load_rec(const unsigned* __restrict__ r, int aw,
 // weights go to an LDS histogram (buckets [0, B) per target block, B =
 // min(256, 2048/k)); higher gains and the final flush go to the histogram
 // replica of this workgroup's XCD.
-template <int WK>
+template <int WK, int VIEW>
 __global__ __launch_bounds__(kBlock) void k_select_light(
     int n, int k, int rw, int lds_buckets, long long lmax, int cmax,
     const long long* __restrict__ vptr, const int* __restrict__ vnets,
     const int* __restrict__ vwgt, const int* __restrict__ part,
-    const unsigned* __restrict__ netstate, const long long* __restrict__ block_w,
+    const unsigned* __restrict__ netstate, const unsigned* __restrict__ view,
+    const long long* __restrict__ block_w,
     unsigned char* __restrict__ eligible, unsigned char* __restrict__ moved,
     long long* __restrict__ cand, unsigned long long* __restrict__ hist,
     RoundCounters* __restrict__ ctr, int* __restrict__ err_flags) {
@@ -95,10 +73,16 @@ __global__ __launch_bounds__(kBlock) void k_select_light(
   __syncthreads();
   unsigned long long* my_hist =
       hist + (size_t)(blockIdx.x % kHistReplicas) * HG_MAX_K * kBuckets;
+  // XCD x sweeps vertex chunks [x*per_xcd, (x+1)*per_xcd); its workgroups
+  // take consecutive chunks side by side, so at any time one XCD works on a
+  // narrow window of vertices whose net records stay in its L2.
   const long long chunks = ((long long)n + kBlock - 1) / kBlock;
-  const long long per = (chunks + gridDim.x - 1) / gridDim.x;
-  const long long lb = xcd_remap(blockIdx.x, gridDim.x);
-  const long long c_end = (lb + 1) * per < chunks ? (lb + 1) * per : chunks;
+  const int xcd = blockIdx.x % kNumXcd;
+  const long long wg_on_xcd = (gridDim.x - xcd + kNumXcd - 1) / kNumXcd;
+  const long long li = blockIdx.x / kNumXcd;
+  const long long per_xcd = (chunks + kNumXcd - 1) / kNumXcd;
+  const long long c_begin = xcd * per_xcd;
+  const long long c_end = c_begin + per_xcd < chunks ? c_begin + per_xcd : chunks;
   long long n_elig = 0, n_bnd = 0, n_cand = 0, n_apins = 0;
   // valid-block masks (only blocks < k; guards against stale caller state)
   unsigned valid[WK];
@@ -107,7 +91,7 @@ __global__ __launch_bounds__(kBlock) void k_select_light(
     const int lo = w * 32;
     valid[w] = k >= lo + 32 ? ~0u : (k > lo ? (1u << (k - lo)) - 1u : 0u);
   }
-  for (long long c = lb * per; c < c_end; ++c) {
+  for (long long c = c_begin + li; c < c_end; c += wg_on_xcd) {
     const long long u = c * kBlock + threadIdx.x;
     if (u >= n) continue;
     if (moved) moved[u] = 0;
@@ -131,18 +115,39 @@ __global__ __launch_bounds__(kBlock) void k_select_light(
     bool bnd = false, heavy = false;
     const int aw = a >> 5;
     const unsigned abit = 1u << (a & 31);
-    for (long long j = b0; j < b1; ++j) {
-      const int e = vnets[j];
-      unsigned w, lam, S, L[WK];
-      load_rec<WK>(netstate + (long long)e * rw, aw, w, lam, L, S);
-      tot += (int)w;
+    // Software-pipelined sweep: issue kUnroll independent record gathers
+    // before consuming any of them.
+    for (long long j = b0; j < b1 && !heavy; j += kUnroll) {
+      unsigned w[kUnroll], S[kUnroll], L[kUnroll][WK];
+      bool cut[kUnroll];
+      int e[kUnroll];
+#pragma unroll
+      for (int q = 0; q < kUnroll; ++q) e[q] = j + q < b1 ? vnets[j + q] : -1;
+#pragma unroll
+      for (int q = 0; q < kUnroll; ++q) {
+        if (e[q] >= 0) {
+          read_net<WK, VIEW>(netstate, rw, view, e[q], aw, w[q], cut[q], L[q], S[q]);
+        } else {
+          w[q] = 0;
+          cut[q] = false;
+          S[q] = 0;
+#pragma unroll
+          for (int x = 0; x < WK; ++x) L[q][x] = 0;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kUnroll; ++q) {
+        tot += (int)w[q];
+        bnd |= cut[q];
+        if (S[q] & abit) ben += (int)w[q];
+      }
       if (tot > kLightLimit) {
         heavy = true;
         break;
       }
-      bnd |= lam > 1u;
-      if (S & abit) ben += (int)w;
-      C.add(L, w);
+#pragma unroll
+      for (int q = 0; q < kUnroll; ++q)
+        if (w[q]) C.add(L[q], w[q]);
     }
     if (heavy) continue;
     eligible[u] = 0;
@@ -494,6 +499,7 @@ __global__ __launch_bounds__(kBlock) void k_tilescan(int num_tiles,
 
 struct ApplyArgs {
   int k, rw;
+  bool unit_nets;
   const long long* vptr;
   const int* vnets;
   const int* vwgt;
@@ -501,88 +507,72 @@ struct ApplyArgs {
   int* phi;
   const unsigned* netstate;
   unsigned char* moved;
-  unsigned* touched;
-  TouchedNet* tlist;
+  unsigned char* touched;
   RoundCounters* ctr;
 };
 
-constexpr int kStage = 512;          // touched nets staged per wavefront before a flush
-
-// Copy a wavefront's staged touched nets to the global list with one atomic.
-__device__ __forceinline__ void flush_stage(const ApplyArgs& A, const TouchedNet* stage, int cnt) {
-  int base = 0;
-  if (lane_id() == 0) base = (int)atomicAdd(&A.ctr->touched, (unsigned)cnt);
-  base = __shfl(base, 0);
-  for (int j = lane_id(); j < cnt; j += kWave) A.tlist[base + j] = stage[j];
-}
-
-// Apply the moves held in s_list[0..count) (vertex ids; targets in s_tgt).
-// Each wave takes 64 movers at a time and walks their incident nets
-// load-balanced.  Block-weight changes go to s_dW; newly touched nets are
-// staged per wavefront in LDS and appended to the global list in bulk.
+// Apply the moves held in s_list[0..count) (vertex ids; targets in s_tgt):
+// part, moved flags and block-weight deltas per mover, then the movers'
+// incident nets as one flattened range split over all 256 threads (so a tile
+// with few movers still keeps four wavefronts busy, and a high-degree mover is
+// spread over the workgroup).  Phi is updated with integer atomics whose old
+// values give the attributed km1 change; every incident net gets its touched
+// flag (a plain byte store: all writers store the same value).
 __device__ void apply_list(const ApplyArgs& A, const int* s_list, const int* s_tgt, int count,
-                           unsigned long long* s_dW, int* s_excl, long long* s_beg,
-                           TouchedNet* stage, long long& delta, long long& moved_pins,
+                           int* s_from, long long* s_beg, int* s_off, long long* s_tmp,
+                           unsigned long long* s_dW, long long& delta, long long& moved_pins,
                            long long& approved) {
-  const int wv = threadIdx.x / kWave, lane = lane_id();
-  int staged = 0;   // wave-uniform
-  for (int base = wv * kWave; base < count; base += kBlock) {
-    const int i = base + lane;
-    int u = -1, a = 0, t = 0, len = 0;
-    long long b = 0;
+  // per mover: move it, record where its incident nets start
+  long long my_len = 0;
+  int lens[kPerThreadTile];
+  const int first = threadIdx.x * kPerThreadTile;   // entries [first, first + kPerThreadTile)
+#pragma unroll
+  for (int q = 0; q < kPerThreadTile; ++q) {
+    const int i = first + q;
+    lens[q] = 0;
     if (i < count) {
-      u = s_list[i];
-      t = s_tgt[i];
-      a = A.part[u];
-      b = A.vptr[u];
-      len = (int)(A.vptr[u + 1] - b);
+      const int u = s_list[i], t = s_tgt[i];
+      const int a = A.part[u];
+      const long long b = A.vptr[u];
+      const int len = (int)(A.vptr[u + 1] - b);
       const long long cu = A.vwgt ? A.vwgt[u] : 1;
       A.part[u] = t;
       if (A.moved) A.moved[u] = 1;
       atomicAdd(&s_dW[t], (unsigned long long)cu);
       atomicAdd(&s_dW[a], (unsigned long long)(-cu));
+      s_from[i] = a;
+      s_beg[i] = b;
+      lens[q] = len;
+      my_len += len;
       moved_pins += len;
       approved += 1;
     }
-    wave_expand(b, len, s_excl + wv * kWave, s_beg + wv * kWave,
-                [&](bool act, int owner, long long j) {
-                  const int ao = __shfl(a, owner);
-                  const int to = __shfl(t, owner);
-                  bool fresh = false;
-                  int e = 0, lam = 0;
-                  if (act) {
-                    e = A.vnets[j];
-                    const unsigned* r = A.netstate + (long long)e * A.rw;
-                    const int w = (int)r[0];
-                    const int oa = atomicSub(&A.phi[(long long)e * A.k + ao], 1);
-                    const int ot = atomicAdd(&A.phi[(long long)e * A.k + to], 1);
-                    if (oa == 1) delta += w;    // Phi(e, a) drops to zero
-                    if (ot == 0) delta -= w;    // Phi(e, t) rises from zero
-                    const unsigned bit = 1u << (e & 31);
-                    const unsigned old = atomicOr(&A.touched[e >> 5], bit);
-                    fresh = !(old & bit);
-                    if (fresh) lam = (int)r[1];
-                  }
-                  const unsigned long long mask = __ballot(fresh);
-                  if (fresh) {
-                    TouchedNet tn;
-                    tn.net = e;
-                    tn.lambda_old = lam;
-                    stage[staged + __popcll(mask & (((unsigned long long)1 << lane) - 1))] = tn;
-                  }
-                  staged += __popcll(mask);
-                  if (staged > kStage - kWave) {
-                    wave_lds_sync();
-                    flush_stage(A, stage, staged);
-                    wave_lds_sync();
-                    staged = 0;
-                  }
-                });
   }
-  if (staged) {
-    wave_lds_sync();
-    flush_stage(A, stage, staged);
-    wave_lds_sync();
+  long long total;
+  long long off = block_excl_scan64(my_len, s_tmp, &total);
+#pragma unroll
+  for (int q = 0; q < kPerThreadTile; ++q) {
+    if (first + q < count) s_off[first + q] = (int)off;
+    off += lens[q];
+  }
+  __syncthreads();
+  for (long long j = threadIdx.x; j < total; j += kBlock) {
+    // owner: largest i < count with s_off[i] <= j
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_off[mid] <= j) lo = mid; else hi = mid - 1;
+    }
+    const int e = A.vnets[s_beg[lo] + (j - s_off[lo])];
+    const int ao = s_from[lo], to = s_tgt[lo];
+    const int oa = atomicSub(&A.phi[(long long)e * A.k + ao], 1);
+    const int ot = atomicAdd(&A.phi[(long long)e * A.k + to], 1);
+    if (oa == 1 || ot == 0) {
+      const int w = A.unit_nets ? 1 : (int)A.netstate[(long long)e * A.rw];
+      if (oa == 1) delta += w;    // Phi(e, a) drops to zero
+      if (ot == 0) delta -= w;    // Phi(e, t) rises from zero
+    }
+    A.touched[e] = 1;
   }
 }
 
@@ -591,12 +581,12 @@ __global__ __launch_bounds__(kBlock) void k_approve_apply(
     const Threshold* __restrict__ thr, long long* __restrict__ block_w) {
   __shared__ int s_list[kTile];
   __shared__ int s_tgt[kTile];
-  __shared__ TouchedNet s_stage[kBlock / kWave][kStage];
+  __shared__ int s_from[kTile];
+  __shared__ int s_off[kTile];
+  __shared__ long long s_beg[kTile];
   __shared__ int s_g[HG_MAX_K];
   __shared__ int s_tau[HG_MAX_K];
   __shared__ unsigned long long s_dW[HG_MAX_K];
-  __shared__ int s_excl[kBlock];
-  __shared__ long long s_beg[kBlock];
   __shared__ long long s_tmp[kBlock / kWave];
   __shared__ unsigned s_count;
   const int k = A.k;
@@ -667,8 +657,9 @@ __global__ __launch_bounds__(kBlock) void k_approve_apply(
   __syncthreads();
   const int count = (int)s_count;
   long long delta = 0, moved_pins = 0, approved = 0;
-  apply_list(A, s_list, s_tgt, count, s_dW, s_excl, s_beg, s_stage[threadIdx.x / kWave], delta,
-             moved_pins, approved);
+  if (count > 0)
+    apply_list(A, s_list, s_tgt, count, s_from, s_beg, s_off, s_tmp, s_dW, delta, moved_pins,
+               approved);
   __syncthreads();
   for (int i = threadIdx.x; i < k; i += kBlock)
     if (s_dW[i]) atomicAdd((unsigned long long*)&block_w[i], s_dW[i]);
@@ -685,36 +676,68 @@ __global__ __launch_bounds__(kBlock) void k_approve_apply(
 
 // --------------------------------------------------------------- finalize
 
+// Workgroup lb owns a contiguous run of nets (XCD-aware).  It reads their
+// touched flags 1024 at a time (coalesced), lists the touched ones in LDS and
+// hands them to groups of G lanes: Lambda, S and lambda are rebuilt from the
+// final Phi row, the flag is cleared and every pin becomes eligible.  The
+// lane that rewrites lambda(e) reads the old value first, so the drop
+// (lambda_old - lambda_new) * w(e) summed over touched nets checks the
+// attributed total.
+constexpr int kFinalChunk = kBlock;
+
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_finalize(
-    int k, int rw, const long long* __restrict__ eptr, const int* __restrict__ pins,
+    int m, int k, int rw, const long long* __restrict__ eptr, const int* __restrict__ pins,
     const int* __restrict__ phi, unsigned* __restrict__ netstate,
-    unsigned* __restrict__ touched, const TouchedNet* __restrict__ tlist,
-    unsigned char* __restrict__ eligible, RoundCounters* __restrict__ ctr) {
+    unsigned char* __restrict__ touched, unsigned char* __restrict__ eligible,
+    RoundCounters* __restrict__ ctr, unsigned* __restrict__ view, int view_kind) {
+  __shared__ int s_list[kFinalChunk];
   __shared__ long long s_tmp[kBlock / kWave];
+  __shared__ unsigned s_cnt;
+  constexpr int kGroups = kBlock / G;
   const int grp = threadIdx.x / G, gl = threadIdx.x % G;
-  const long long ngroups = (long long)gridDim.x * (kBlock / G);
-  const long long count = (long long)ctr->touched;
   const int wk = bit_words(k);
-  long long dcheck = 0;
-  for (long long idx = (long long)blockIdx.x * (kBlock / G) + grp; idx < count; idx += ngroups) {
-    const TouchedNet tn = tlist[idx];
-    const int e = tn.net;
-    const int* row = phi + (long long)e * k;
-    unsigned* rec = netstate + (long long)e * rw;
-    NetBits nb = net_bits<G>(k, gl, [&](int i) { return row[i]; }, [&](int, int) {});
-    if (gl >= 1 && gl < 2 + 2 * wk) rec[gl] = nb.word;
-    if (gl == 0) {
-      const int w = (int)rec[0];
-      dcheck += (long long)(tn.lambda_old - nb.lambda) * w;
-      atomicAnd(&touched[e >> 5], ~(1u << (e & 31)));
+  const long long chunks = ((long long)m + kFinalChunk - 1) / kFinalChunk;
+  const long long per = (chunks + gridDim.x - 1) / gridDim.x;
+  const long long lb = xcd_remap(blockIdx.x, gridDim.x);
+  const long long c_end = (lb + 1) * per < chunks ? (lb + 1) * per : chunks;
+  long long dcheck = 0, ntouched = 0;
+  for (long long c = lb * per; c < c_end; ++c) {
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
+    // one flag per thread (the flag array is padded to whole chunks, zero past m)
+    const long long e0 = c * kFinalChunk + threadIdx.x;
+    const bool t0 = touched[e0] != 0;
+    const int slot = wave_append(&s_cnt, t0);
+    if (t0) s_list[slot] = (int)e0;
+    __syncthreads();
+    const int cnt = (int)s_cnt;
+    ntouched += cnt;
+    for (int i = grp; i < cnt; i += kGroups) {
+      const int e = s_list[i];
+      const int* row = phi + (long long)e * k;
+      unsigned* rec = netstate + (long long)e * rw;
+      int lam_old = 0, w = 0;
+      if (gl == 1) {
+        lam_old = (int)rec[1];
+        w = (int)rec[0];
+      }
+      NetBits nb = net_bits<G>(k, gl, [&](int i2) { return row[i2]; }, [&](int, int) {});
+      if (gl >= 1 && gl < 2 + 2 * wk) rec[gl] = nb.word;
+      if (view_kind != kViewFull) write_view(view, e, view_kind, gl, nb);
+      if (gl == 1) dcheck += (long long)(lam_old - nb.lambda) * w;
+      if (gl == 0) touched[e] = 0;
+      const long long b = eptr[e], t = eptr[e + 1];
+      for (long long p = b + gl; p < t; p += G) eligible[pins[p]] = 1;
     }
-    const long long b = eptr[e], t = eptr[e + 1];
-    for (long long p = b + gl; p < t; p += G) eligible[pins[p]] = 1;
+    __syncthreads();
   }
   dcheck = block_sum64(dcheck, s_tmp);
-  if (threadIdx.x == 0 && dcheck)
-    atomicAdd(&ctr->slot[kCtrDeltaCheck][blockIdx.x % kSlots], (unsigned long long)dcheck);
+  if (threadIdx.x == 0) {
+    const int sl = blockIdx.x % kSlots;
+    if (dcheck) atomicAdd(&ctr->slot[kCtrDeltaCheck][sl], (unsigned long long)dcheck);
+    if (ntouched) atomicAdd(&ctr->slot[kCtrTouched][sl], (unsigned long long)ntouched);
+  }
 }
 
 // One workgroup: sum the counter slots, write the round record, move km1 by
@@ -746,7 +769,7 @@ __global__ __launch_bounds__(kBlock) void k_round_stats(int k, RoundCounters* __
     st.candidates = s_sum[kCtrCandidates];
     st.approved = s_sum[kCtrApproved];
     st.moved_pins = s_sum[kCtrMovedPins];
-    st.touched_nets = (long long)ctr->touched;
+    st.touched_nets = s_sum[kCtrTouched];
     st.km1_delta = s_sum[kCtrDeltaAttr];
     st.km1_delta_recomputed = s_sum[kCtrDeltaCheck];
     st.active_pins = s_sum[kCtrActivePins];
@@ -754,7 +777,6 @@ __global__ __launch_bounds__(kBlock) void k_round_stats(int k, RoundCounters* __
     st.max_block_weight = m;
     *km1 = st.km1_after;
     *stats = st;
-    ctr->touched = 0;
     ctr->any_overflow = 0;
   }
 }
@@ -776,9 +798,17 @@ static void launch_select_light(hg_graph_s* g, int k, long long lmax, const int*
   char* ws = g->ws;
   long long chunks = ((long long)g->n + kBlock - 1) / kBlock;
   unsigned grid = (unsigned)(chunks < kSelectGrid ? chunks : kSelectGrid);
-  hipLaunchKernelGGL(k_select_light<WK>, dim3(grid), dim3(kBlock), 0, s, g->n, k, net_words(k),
+  const unsigned* view = netstate + (size_t)g->m * net_words(k);
+  auto kern = k_select_light<WK, kViewFull>;
+  switch (net_view(k, g->unit_nets)) {
+    case kView16: kern = k_select_light<1, kView16>; break;
+    case kView32: kern = k_select_light<1, kView32>; break;
+    case kView64: kern = k_select_light<2, kView64>; break;
+    default: break;
+  }
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, g->n, k, net_words(k),
                      lds_buckets(k), lmax, g->info.max_vertex_weight, g->vptr, g->vnets, g->vwgt,
-                     part, netstate, block_w, eligible, moved, (long long*)(ws + g->lay.cand),
+                     part, netstate, view, block_w, eligible, moved, (long long*)(ws + g->lay.cand),
                      (unsigned long long*)(ws + g->lay.hist), (RoundCounters*)(ws + g->lay.ctr),
                      (int*)(ws + g->lay.flags));
 }
@@ -787,12 +817,13 @@ template <int G>
 static void launch_finalize(hg_graph_s* g, int k, const int* phi, unsigned* netstate,
                             unsigned char* eligible, hipStream_t s) {
   char* ws = g->ws;
-  long long blocks = ((long long)g->m + (kBlock / G) - 1) / (kBlock / G);
+  long long blocks = ((long long)g->m + kFinalChunk - 1) / kFinalChunk;
   if (blocks > kFinalizeGrid) blocks = kFinalizeGrid;
-  hipLaunchKernelGGL(k_finalize<G>, dim3((unsigned)blocks), dim3(kBlock), 0, s, k, net_words(k),
-                     g->eptr, g->pins, phi, netstate, (unsigned*)(ws + g->lay.touched),
-                     (const TouchedNet*)(ws + g->lay.tlist), eligible,
-                     (RoundCounters*)(ws + g->lay.ctr));
+  hipLaunchKernelGGL(k_finalize<G>, dim3((unsigned)blocks), dim3(kBlock), 0, s, g->m, k,
+                     net_words(k), g->eptr, g->pins, phi, netstate,
+                     (unsigned char*)(ws + g->lay.touched), eligible,
+                     (RoundCounters*)(ws + g->lay.ctr),
+                     netstate + (size_t)g->m * net_words(k), net_view(k, g->unit_nets));
 }
 
 hipError_t launch_lp_round(hg_graph_s* g, int k, long long lmax, int* part, int* phi,
@@ -841,8 +872,8 @@ hipError_t launch_lp_round(hg_graph_s* g, int k, long long lmax, int* part, int*
   A.phi = phi;
   A.netstate = netstate;
   A.moved = moved;
-  A.touched = (unsigned*)(ws + g->lay.touched);
-  A.tlist = (TouchedNet*)(ws + g->lay.tlist);
+  A.touched = (unsigned char*)(ws + g->lay.touched);
+  A.unit_nets = g->unit_nets;
   A.ctr = ctr;
   hipLaunchKernelGGL(k_approve_apply, dim3(nt + k), dim3(kBlock), 0, s, g->n, nt, A, cand, thr,
                      block_w);

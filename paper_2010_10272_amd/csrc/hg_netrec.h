@@ -26,19 +26,33 @@ __device__ __forceinline__ NetBits net_bits(int k, int gl, Get get, Put put) {
   r.lambda = 0;
   r.word = 0;
   const int nchunks = (k + G - 1) / G;
+  // all counts first (independent loads in flight together), then the ballots
+  constexpr int kMaxChunks = (HG_MAX_K + G - 1) / G < 8 ? (HG_MAX_K + G - 1) / G : 8;
+  int cvs[kMaxChunks];
+#pragma unroll
+  for (int c = 0; c < kMaxChunks; ++c) {
+    const int i = c * G + gl;
+    cvs[c] = 0;
+    if (c < nchunks && i < k) cvs[c] = get(i);
+  }
   for (int c = 0; c < nchunks; ++c) {
     int i = c * G + gl;
     int cv = 0;
-    if (i < k) {
-      cv = get(i);
-      put(i, cv);
+    if (c < kMaxChunks) {
+#pragma unroll
+      for (int x = 0; x < kMaxChunks; ++x)
+        if (x == c) cv = cvs[x];
+    } else if (i < k) {
+      cv = get(i);                    // only when k needs more than kMaxChunks chunks
     }
+    if (i < k) put(i, cv);
     unsigned long long nz = (__ballot(cv > 0) >> shift) & gmask;
     unsigned long long one = (__ballot(cv == 1) >> shift) & gmask;
     r.lambda += __popcll(nz);
-    if (G <= 32) {                    // then k <= G: one word per bitset
-      if (gl == 2) r.word = (unsigned)nz;
-      if (gl == 3) r.word = (unsigned)one;
+    if (G <= 32) {                    // chunk c fills bits [c*G % 32, +G) of word c*G/32
+      const int wd = (c * G) >> 5, sh = (c * G) & 31;
+      if (gl == 2 + wd) r.word |= (unsigned)nz << sh;
+      if (gl == 2 + wk + wd) r.word |= (unsigned)one << sh;
     } else {
       int j0 = 2 * c;
       if (gl == 2 + j0) r.word = (unsigned)nz;
@@ -71,6 +85,21 @@ __device__ __forceinline__ void write_netrec(unsigned* rec, int gl, int w, const
     if (gl == 0) val = (unsigned)w;
     else if (gl < 2 + 2 * wk) val = b.word;
     rec[gl] = val;
+  }
+}
+
+// Write net e's entry of the compact Lambda/S view (NetView) from the record
+// words held by the group's lanes (lane 2.. holds Lambda, then S).  All lanes
+// of the group must call it.
+__device__ __forceinline__ void write_view(unsigned* view, long long e, int view_kind, int gl,
+                                           const NetBits& b) {
+  const unsigned next = __shfl(b.word, lane_id() + 1);   // the word of lane gl + 1
+  if (view_kind == kView16) {
+    if (gl == 2) view[e] = (b.word & 0xffffu) | (next << 16);
+  } else if (view_kind == kView32) {
+    if (gl == 2 || gl == 3) view[e * 2 + (gl - 2)] = b.word;
+  } else if (view_kind == kView64) {
+    if (gl >= 2 && gl < 6) view[e * 4 + (gl - 2)] = b.word;
   }
 }
 

@@ -13,7 +13,7 @@
 
 namespace hg {
 
-constexpr int kStateGrid = 2048;   // persistent workgroups of the net sweep
+constexpr int kStateGrid = 8192;   // persistent workgroups of the net sweep
 
 // G lanes per net (G divides 64); LDS counters: (kBlock/G) groups x k ints.
 // Workgroup lb owns a contiguous run of nets (XCD-aware order).
@@ -26,7 +26,8 @@ __global__ __launch_bounds__(kBlock) void k_pincounts(int m, int k, int rw,
                                                       int* __restrict__ phi,
                                                       unsigned* __restrict__ netstate,
                                                       unsigned long long* __restrict__ km1_slots,
-                                                      int* __restrict__ err_flags) {
+                                                      int* __restrict__ err_flags,
+                                                      unsigned* __restrict__ view, int view_kind) {
   extern __shared__ int s_cnt[];   // [kBlock/G][k]
   __shared__ long long s_tmp[kBlock / kWave];
   constexpr int kGroups = kBlock / G;
@@ -54,6 +55,7 @@ __global__ __launch_bounds__(kBlock) void k_pincounts(int m, int k, int rw,
     netbits_from_counts<G>(cnt, k, gl, bits, phi + e * (long long)k);
     const int w = ewgt ? ewgt[e] : 1;
     write_netrec(netstate + e * (long long)rw, gl, w, bits, k);
+    if (view_kind != kViewFull) write_view(view, e, view_kind, gl, bits);
     if (gl == 0) km1_local += (long long)(bits.lambda - 1) * w;
     wave_lds_sync();
   }
@@ -123,15 +125,18 @@ static void launch_pincounts_g(hg_graph_s* g, int k, const int* part, int* phi,
   unsigned grid = grid_cap(g->m, kBlock / G, kStateGrid);
   size_t lds = sizeof(int) * (size_t)(kBlock / G) * k;
   hipLaunchKernelGGL(k_pincounts<G>, dim3(grid), dim3(kBlock), lds, s, g->m, k, net_words(k),
-                     g->eptr, g->pins, g->ewgt, part, phi, netstate, slots, err);
+                     g->eptr, g->pins, g->ewgt, part, phi, netstate, slots, err,
+                     netstate + (size_t)g->m * net_words(k), net_view(k, g->unit_nets));
 }
 
+// Lanes per net for the net-centric sweeps: enough lanes to hold every word
+// of the net record (2 + 2 * bit_words(k), padded), few enough that a wave
+// works on several nets at once (most nets have only a handful of pins).
 int group_lanes(int k) {
   if (k <= 4) return 4;
   if (k <= 8) return 8;
-  if (k <= 16) return 16;
-  if (k <= 32) return 32;
-  return 64;
+  if (k <= 128) return 16;
+  return 32;
 }
 
 hipError_t launch_pincounts(hg_graph_s* g, int k, const int* part, int* phi,
@@ -148,6 +153,12 @@ hipError_t launch_pincounts(hg_graph_s* g, int k, const int* part, int* phi,
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (net_view(k, g->unit_nets) == kViewFull && view_words(k) > 0) {
+    // the compact copy is not used for weighted nets: keep it defined (zero)
+    e = fill_i32((int*)netstate + (size_t)g->m * net_words(k), 0,
+                 (long long)g->m * view_words(k), s);
+    if (e != hipSuccess) return e;
+  }
   if (km1) {
     hipLaunchKernelGGL(k_sum_slots, dim3(1), dim3(kWave), 0, s, slots, km1);
   } else {

@@ -51,6 +51,8 @@ def _load():
                              ctypes.c_double)
     lib.hg_net_words.argtypes = [i32]
     lib.hg_net_words.restype = i32
+    lib.hg_netstate_words.argtypes = [i32, i32]
+    lib.hg_netstate_words.restype = i64
     lib.hg_workspace_size.argtypes = [i32, i32, i64, i32]
     lib.hg_workspace_size.restype = sz
     lib.hg_load_csr.argtypes = [i32, i32, i64, vp, vp, vp, vp, vp, vp, vp, sz, i32, vp,
@@ -116,6 +118,10 @@ def _stream(stream=None):
 
 def hg_net_words(k):
     return int(_lib.hg_net_words(int(k)))
+
+
+def hg_netstate_words(m, k):
+    return int(_lib.hg_netstate_words(int(m), int(k)))
 
 
 def hg_workspace_size(n, m, P, k_max):
@@ -212,7 +218,7 @@ class State:
         self.k = int(k)
         self.part = _dev(part, torch.int32, dev).clone()
         self.phi = torch.empty(g.m * self.k, dtype=torch.int32, device=dev)
-        self.netstate = torch.empty(g.m * hg_net_words(k), dtype=torch.int32, device=dev)
+        self.netstate = torch.empty(hg_netstate_words(g.m, k), dtype=torch.int32, device=dev)
         self.block_w = torch.empty(self.k, dtype=torch.int64, device=dev)
         self.km1 = torch.empty(1, dtype=torch.int64, device=dev)
         self.eligible = torch.ones(g.n, dtype=torch.uint8, device=dev)
@@ -287,5 +293,5 @@ def decode_netstate(netstate, m, k):
     wk = 1
     while wk * 32 < k:
         wk *= 2
-    r = netstate.view(m, rw)
+    r = netstate[:m * rw].view(m, rw)
     return r[:, 0], r[:, 1], r[:, 2:2 + wk], r[:, 2 + wk:2 + 2 * wk]

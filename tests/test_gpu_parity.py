@@ -49,6 +49,20 @@ def _check_state(H, g, st, h, k, part_np):
     assert np.array_equal(w_g, h.w if h.w is not None else np.ones(g.m, np.int32))
     assert np.array_equal(_bits_to_sets(conn_g, k), phi_o > 0)
     assert np.array_equal(_bits_to_sets(single_g, k), phi_o == 1)
+    unit = h.w is None or bool((h.w == 1).all())
+    if unit and k <= 64:
+        # compact Lambda/S copy behind the records (maintained for unit nets)
+        rw = H.hg_net_words(k)
+        tail = st.netstate[g.m * rw:].cpu().numpy().astype(np.uint32)
+        if k <= 16:
+            lam_w = (tail & 0xffff)[:, None]
+            s_w = (tail >> 16)[:, None]
+        else:
+            v = tail.reshape(g.m, -1)
+            half = v.shape[1] // 2
+            lam_w, s_w = v[:, :half], v[:, half:]
+        assert np.array_equal(_bits_to_sets(lam_w, k), phi_o > 0)
+        assert np.array_equal(_bits_to_sets(s_w, k), phi_o == 1)
     assert np.array_equal(st.block_w.cpu().numpy(), O.block_weights(h, part_np, k))
     return lam_o
 
