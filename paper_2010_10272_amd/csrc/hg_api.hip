@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "hg_internal.h"
+#include "hg_lp.h"
 
 namespace hg {
 hipError_t load_sort_big(hg_graph_s* g, int big_rows, hipStream_t s);
@@ -125,7 +126,7 @@ WsLayout ws_layout(int n, int m, long long P, int k_max) {
   L.touched = take(touched_bytes(m));   // one flag byte per net, zero past m
   L.heavy = take(sizeof(int) * (size_t)n);
   L.big = take(sizeof(int) * (size_t)n);
-  L.hist = take(sizeof(unsigned long long) * (size_t)kHistReplicas * HG_MAX_K * kBuckets);
+  L.hist = take(sizeof(unsigned long long) * (size_t)kHistReplicas * k_max * kBuckets);
   L.overflow = take(sizeof(int) * (size_t)k_max);
   L.thr = take(sizeof(Threshold) * (size_t)k_max);
   L.tilesum = take(sizeof(long long) * (size_t)k_max * (size_t)L.num_tiles);
@@ -136,6 +137,53 @@ WsLayout ws_layout(int n, int m, long long P, int k_max) {
   L.red = take(sizeof(unsigned long long) * kSlots);
   L.total = off;
   return L;
+}
+
+InstDesc make_desc(hg_graph_s* g, int k, long long lmax, int* part, int* phi,
+                   unsigned* netstate, long long* block_w, unsigned char* eligible,
+                   unsigned char* moved, long long* km1, hg_round_stats* stats) {
+  InstDesc d;
+  memset(&d, 0, sizeof(d));
+  char* ws = g->ws;
+  d.n = g->n;
+  d.m = g->m;
+  d.P = g->P;
+  d.k = k;
+  d.rw = net_words(k);
+  d.view = net_view(k, g->unit_nets);
+  d.unit_nets = g->unit_nets ? 1 : 0;
+  d.cmax = g->info.max_vertex_weight;
+  d.lds_buckets = lds_buckets(k);
+  d.heavy_count = g->info.heavy_count;
+  d.num_tiles = g->lay.num_tiles;
+  d.hist_stride = g->k_max * kBuckets;
+  d.lmax = lmax;
+  d.eptr = g->eptr;
+  d.pins = g->pins;
+  d.vwgt = g->vwgt;
+  d.ewgt = g->ewgt;
+  d.vptr = g->vptr;
+  d.vnets = g->vnets;
+  d.heavy_list = (const int*)(ws + g->lay.heavy);
+  d.part = part;
+  d.phi = phi;
+  d.netstate = netstate;
+  d.view_ptr = netstate ? netstate + (size_t)g->m * d.rw : nullptr;
+  d.block_w = block_w;
+  d.eligible = eligible;
+  d.moved = moved;
+  d.km1 = km1;
+  d.stats = stats;
+  d.cand = (long long*)(ws + g->lay.cand);
+  d.touched = (unsigned char*)(ws + g->lay.touched);
+  d.hist = (unsigned long long*)(ws + g->lay.hist);
+  d.overflow = (int*)(ws + g->lay.overflow);
+  d.thr = (Threshold*)(ws + g->lay.thr);
+  d.tilesum = (long long*)(ws + g->lay.tilesum);
+  d.ctr = (RoundCounters*)(ws + g->lay.ctr);
+  d.err_flags = (int*)(ws + g->lay.flags);
+  d.red = (unsigned long long*)(ws + g->lay.red);
+  return d;
 }
 
 }  // namespace hg
@@ -219,7 +267,7 @@ hg_status hg_load_csr(int32_t n, int32_t m, int64_t P, const int64_t* eptr, cons
   e = hg::fill_u8((unsigned char*)(ws + lay.touched), 0, (long long)hg::touched_bytes(m), s);
   if (e == hipSuccess)
     e = hg::fill_i64((long long*)(ws + lay.hist), 0,
-                     (long long)hg::kHistReplicas * HG_MAX_K * hg::kBuckets, s);
+                     (long long)hg::kHistReplicas * k_max * hg::kBuckets, s);
   if (e == hipSuccess) e = hg::fill_i32((int*)(ws + lay.overflow), 0, k_max, s);
   if (e == hipSuccess)
     e = hg::fill_i32((int*)(ws + lay.ctr), 0, sizeof(hg::RoundCounters) / sizeof(int), s);
@@ -270,9 +318,11 @@ hg_status hg_compute_pincounts(hg_graph g, int32_t k, const int32_t* part, int32
   if (st != HG_OK) return st;
   if (!part || !phi || !netstate || !block_w)
     return fail(HG_ERR_INVALID, "part, phi, netstate and block_w must be non-NULL");
-  HG_TRY(hg::launch_pincounts(g, k, part, phi, netstate, (long long*)block_w, (long long*)km1_out,
-                              (hipStream_t)stream),
-         "pin counts");
+  hg::InstDesc d = hg::make_desc(g, k, 0, (int*)part, phi, netstate, (long long*)block_w, nullptr,
+                                 nullptr, (long long*)km1_out, nullptr);
+  hg::CountPlan plan;
+  hg::single_count_plan(d, plan);
+  HG_TRY(hg::launch_counts(plan, km1_out != nullptr, (hipStream_t)stream), "pin counts");
   return HG_OK;
 }
 
@@ -291,8 +341,9 @@ hg_status hg_gains(hg_graph g, int32_t k, const int32_t* part, const uint32_t* n
   if (st != HG_OK) return st;
   if (!part || !netstate || !gains)
     return fail(HG_ERR_INVALID, "part, netstate and gains must be non-NULL");
-  HG_TRY(hg::launch_gains(g, k, part, netstate, (long long*)gains, (long long*)benefit,
-                          (hipStream_t)stream),
+  hg::InstDesc d = hg::make_desc(g, k, 0, (int*)part, nullptr, (unsigned*)netstate, nullptr,
+                                 nullptr, nullptr, nullptr, nullptr);
+  HG_TRY(hg::launch_gains(g, d, (long long*)gains, (long long*)benefit, (hipStream_t)stream),
          "gains");
   return HG_OK;
 }
@@ -309,10 +360,11 @@ hg_status hg_lp_round(hg_graph g, int32_t k, int64_t max_block_w, int32_t* part,
   hipEvent_t* marks = nullptr;
   st = timing_marks(g, (hipStream_t)stream, &marks);
   if (st != HG_OK) return st;
-  HG_TRY(hg::launch_lp_round(g, k, max_block_w, part, phi, netstate, (long long*)block_w,
-                             eligible, moved, (long long*)km1, stats, (hipStream_t)stream,
-                             marks),
-         "label-propagation round");
+  hg::InstDesc d = hg::make_desc(g, k, max_block_w, part, phi, netstate, (long long*)block_w,
+                                 eligible, moved, (long long*)km1, stats);
+  hg::RoundPlan plan;
+  hg::single_round_plan(d, plan);
+  HG_TRY(hg::launch_round(plan, (hipStream_t)stream, marks), "label-propagation round");
   return HG_OK;
 }
 
@@ -320,15 +372,20 @@ static hipError_t enqueue_refine(hg_graph g, int k, long long lmax, int rounds, 
                                  int32_t* phi, uint32_t* netstate, int64_t* block_w,
                                  uint8_t* eligible, hg_round_stats* stats, int64_t* km1,
                                  hipStream_t s) {
-  hipError_t e = hg::launch_pincounts(g, k, part, phi, netstate, (long long*)block_w,
-                                      (long long*)km1, s);
+  hg::InstDesc d = hg::make_desc(g, k, lmax, part, phi, netstate, (long long*)block_w, eligible,
+                                 nullptr, (long long*)km1, stats);
+  hg::CountPlan cplan;
+  hg::single_count_plan(d, cplan);
+  hipError_t e = hg::launch_counts(cplan, true, s);
   if (e != hipSuccess) return e;
   e = hg::fill_u8(eligible, 1, g->n, s);
+  hg::RoundPlan plan;
   for (int r = 0; r < rounds && e == hipSuccess; ++r) {
     hipEvent_t* marks = nullptr;
     if (timing_marks(g, s, &marks) != HG_OK) return hipErrorUnknown;
-    e = hg::launch_lp_round(g, k, lmax, part, phi, netstate, (long long*)block_w, eligible,
-                            nullptr, (long long*)km1, stats + r, s, marks);
+    d.stats = stats + r;
+    hg::single_round_plan(d, plan);
+    e = hg::launch_round(plan, s, marks);
   }
   return e;
 }

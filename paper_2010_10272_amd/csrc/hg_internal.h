@@ -88,6 +88,60 @@ struct LoadInfo {
   int pad[5];
 };
 
+// Everything a kernel needs about one instance: a loaded hypergraph, its
+// workspace, and one k-way partition state.  Single-instance entry points pass
+// one by value inside the kernel arguments; batched launches pass a device
+// array and a per-workgroup work table.
+struct InstDesc {
+  int n, m;
+  int k, rw, view, unit_nets;
+  int cmax, lds_buckets, heavy_count, num_tiles;
+  int hist_stride;               // k_max * kBuckets: distance between histogram replicas
+  int pad0;
+  long long P, lmax;
+  const long long* eptr;
+  const int* pins;
+  const int* vwgt;
+  const int* ewgt;
+  const long long* vptr;
+  const int* vnets;
+  const int* heavy_list;
+  int* part;
+  int* phi;
+  unsigned* netstate;
+  unsigned* view_ptr;            // compact Lambda/S copy (behind the records)
+  long long* block_w;
+  unsigned char* eligible;
+  unsigned char* moved;          // may be null
+  long long* km1;
+  hg_round_stats* stats;
+  long long* cand;
+  unsigned char* touched;
+  unsigned long long* hist;
+  int* overflow;
+  Threshold* thr;
+  long long* tilesum;
+  RoundCounters* ctr;
+  int* err_flags;
+  unsigned long long* red;
+};
+
+// One workgroup's share of a batched launch: instance, and the units it
+// handles: first, first + stride, ... (count of them).  What a unit is
+// depends on the kernel (a 256-vertex chunk, a target block, a tile, ...).
+struct WorkItem {
+  int inst, first, count, stride;
+};
+
+// Kernel argument: a batch (descs + items, both device arrays) or one
+// instance by value (descs == nullptr; each kernel then derives its units
+// from blockIdx as documented with it).
+struct Launch {
+  const InstDesc* descs;
+  const WorkItem* items;
+  InstDesc one;
+};
+
 struct WsLayout {
   size_t cand, touched, heavy, big, hist, overflow, thr, tilesum, ctr, info, scan, flags;
   size_t red;   // kSlots partial sums for whole-array reductions (km1)
@@ -181,16 +235,16 @@ hipError_t fill_i32(int* p, int v, long long count, hipStream_t s);
 hipError_t load_check(hg_graph_s* g, hipStream_t s);
 hipError_t load_build(hg_graph_s* g, hipStream_t s);
 
-hipError_t launch_pincounts(hg_graph_s* g, int k, const int* part, int* phi,
-                            unsigned* netstate, long long* block_w, long long* km1,
-                            hipStream_t s);
-hipError_t launch_km1(hg_graph_s* g, int k, const unsigned* netstate, long long* km1,
-                      hipStream_t s);
-hipError_t launch_gains(hg_graph_s* g, int k, const int* part, const unsigned* netstate,
-                        long long* gains, long long* benefit, hipStream_t s);
-hipError_t launch_lp_round(hg_graph_s* g, int k, long long lmax, int* part, int* phi,
-                           unsigned* netstate, long long* block_w, unsigned char* eligible,
-                           unsigned char* moved, long long* km1, hg_round_stats* stats,
-                           hipStream_t s, hipEvent_t* marks = nullptr);
+// Gain-histogram buckets kept in LDS per target block by the select sweep.
+inline int lds_buckets(int k) {
+  int b = kBuckets;
+  while (b > 1 && b * k > kLdsHistEntries) b >>= 1;
+  return b;
+}
+
+// Descriptor of one instance: graph g, its workspace, and the caller's state.
+InstDesc make_desc(hg_graph_s* g, int k, long long lmax, int* part, int* phi,
+                   unsigned* netstate, long long* block_w, unsigned char* eligible,
+                   unsigned char* moved, long long* km1, hg_round_stats* stats);
 
 }  // namespace hg

@@ -1,0 +1,61 @@
+// hg_lp.h -- launch plans: which kernels a round (or a pin-count pass) runs,
+// with which grid and arguments, for one instance or a batch.
+#pragma once
+
+#include <vector>
+
+#include "hg_internal.h"
+
+namespace hg {
+
+constexpr int kFinalChunk = kBlock;   // nets per unit of the finalize sweep
+
+typedef void (*SelectKernel)(Launch);
+typedef void (*FinalizeKernel)(Launch);
+typedef void (*GroupKernel)(Launch);
+typedef void (*GainsKernel)(Launch);
+
+struct PlanLaunch {
+  void* kernel = nullptr;   // for templated kernels: which instantiation
+  unsigned grid = 0;
+  size_t lds = 0;           // dynamic LDS bytes (pin counts)
+  Launch L{};
+};
+
+// One LP round: select launches (one per kernel variant in a batch), heavy
+// select, per-block kernels (threshold, overflow, tilescan), tiles, approve,
+// finalize launches (one per group width), stats.
+struct RoundPlan {
+  std::vector<PlanLaunch> select, heavy, finalize;
+  PlanLaunch blocks, tiles, approve, stats;
+  bool any_heavy = false;
+};
+
+// Pin counts (one launch per group width), then the per-instance km1 slot
+// sums, the block-weight reset and sweep.
+struct CountPlan {
+  std::vector<PlanLaunch> pincounts;
+  PlanLaunch instances;     // one workgroup per instance
+  PlanLaunch vertices;      // block weights: units of kBwChunk vertices
+};
+
+constexpr int kBwChunk = kBlock * 16;   // vertices per unit of the block-weight sweep
+
+SelectKernel select_kernel(int k, int view);
+FinalizeKernel finalize_kernel(int k);
+GroupKernel pincount_kernel(int k);
+GainsKernel gains_kernel(int k, int view);
+int group_lanes(int k);
+
+hipError_t launch_round(const RoundPlan& plan, hipStream_t s, hipEvent_t* marks);
+void single_round_plan(const InstDesc& d, RoundPlan& plan);
+
+hipError_t launch_counts(const CountPlan& plan, bool want_km1, hipStream_t s);
+void single_count_plan(const InstDesc& d, CountPlan& plan);
+
+hipError_t launch_gains(hg_graph_s* g, const InstDesc& d, long long* gains, long long* benefit,
+                        hipStream_t s);
+hipError_t launch_km1(hg_graph_s* g, int k, const unsigned* netstate, long long* km1,
+                      hipStream_t s);
+
+}  // namespace hg

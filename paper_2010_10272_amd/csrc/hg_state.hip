@@ -9,86 +9,128 @@
 // is deterministic by construction.
 #include "hg_device.h"
 #include "hg_internal.h"
+#include "hg_lp.h"
 #include "hg_netrec.h"
 
 namespace hg {
 
-constexpr int kStateGrid = 8192;   // persistent workgroups of the net sweep
+constexpr int kStateGrid = 8192;   // persistent workgroups of the single-instance net sweep
+constexpr int kKm1Chunk = kBlock * 8;
 
-// G lanes per net (G divides 64); LDS counters: (kBlock/G) groups x k ints.
-// Workgroup lb owns a contiguous run of nets (XCD-aware order).
+__device__ __forceinline__ WorkItem work_item_s(const Launch& L, WorkItem fallback) {
+  return L.items ? L.items[blockIdx.x] : fallback;
+}
+__device__ __forceinline__ InstDesc inst_desc_s(const Launch& L, int inst) {
+  return L.descs ? L.descs[inst] : L.one;
+}
+__device__ __forceinline__ WorkItem contiguous_units(long long units) {
+  const long long lb = xcd_remap(blockIdx.x, gridDim.x);
+  const long long per = (units + gridDim.x - 1) / gridDim.x;
+  long long end = (lb + 1) * per;
+  if (end > units) end = units;
+  WorkItem w;
+  w.inst = 0;
+  w.first = (int)(lb * per);
+  w.stride = 1;
+  w.count = lb * per < end ? (int)(end - lb * per) : 0;
+  return w;
+}
+
+// Unit: kBlock/G consecutive nets (one per group).  G lanes per net (G
+// divides 64); LDS counters: (kBlock/G) groups x k ints.
 template <int G>
-__global__ __launch_bounds__(kBlock) void k_pincounts(int m, int k, int rw,
-                                                      const long long* __restrict__ eptr,
-                                                      const int* __restrict__ pins,
-                                                      const int* __restrict__ ewgt,
-                                                      const int* __restrict__ part,
-                                                      int* __restrict__ phi,
-                                                      unsigned* __restrict__ netstate,
-                                                      unsigned long long* __restrict__ km1_slots,
-                                                      int* __restrict__ err_flags,
-                                                      unsigned* __restrict__ view, int view_kind) {
+__global__ __launch_bounds__(kBlock) void k_pincounts(Launch L) {
   extern __shared__ int s_cnt[];   // [kBlock/G][k]
   __shared__ long long s_tmp[kBlock / kWave];
   constexpr int kGroups = kBlock / G;
+  const WorkItem wi = work_item_s(L, contiguous_units((L.one.m + kGroups - 1) / kGroups));
+  const InstDesc D = inst_desc_s(L, wi.inst);
   const int grp = threadIdx.x / G;
   const int gl = threadIdx.x % G;
+  const int k = D.k, m = D.m, rw = D.rw;
   int* cnt = s_cnt + grp * k;
-  const long long lb = xcd_remap(blockIdx.x, gridDim.x);
-  const long long per = (((long long)m + kGroups - 1) / kGroups + gridDim.x - 1) / gridDim.x;
-  const long long e_begin = lb * per * kGroups;
-  long long e_end = e_begin + per * kGroups;
-  if (e_end > m) e_end = m;
   long long km1_local = 0;
   int err = 0;
-  for (long long e = e_begin + grp; e < e_end; e += kGroups) {
-    for (int i = gl; i < k; i += G) cnt[i] = 0;
-    wave_lds_sync();
-    const long long b = eptr[e], t = eptr[e + 1];
-    for (long long p = b + gl; p < t; p += G) {
-      const int blk = part[pins[p]];
-      if ((unsigned)blk < (unsigned)k) atomicAdd(&cnt[blk], 1);
-      else err = kErrPart;
+  for (int it = 0; it < wi.count; ++it) {
+    const long long e = ((long long)wi.first + (long long)it * wi.stride) * kGroups + grp;
+    if (e < m) {
+      for (int i = gl; i < k; i += G) cnt[i] = 0;
     }
     wave_lds_sync();
-    NetBits bits;
-    netbits_from_counts<G>(cnt, k, gl, bits, phi + e * (long long)k);
-    const int w = ewgt ? ewgt[e] : 1;
-    write_netrec(netstate + e * (long long)rw, gl, w, bits, k);
-    if (view_kind != kViewFull) write_view(view, e, view_kind, gl, bits);
-    if (gl == 0) km1_local += (long long)(bits.lambda - 1) * w;
+    if (e < m) {
+      const long long b = D.eptr[e], t = D.eptr[e + 1];
+      for (long long p = b + gl; p < t; p += G) {
+        const int blk = D.part[D.pins[p]];
+        if ((unsigned)blk < (unsigned)k) atomicAdd(&cnt[blk], 1);
+        else err = kErrPart;
+      }
+    }
+    wave_lds_sync();
+    if (e < m) {
+      NetBits bits;
+      netbits_from_counts<G>(cnt, k, gl, bits, D.phi + e * (long long)k);
+      const int w = D.ewgt ? D.ewgt[e] : 1;
+      write_netrec(D.netstate + e * (long long)rw, gl, w, bits, k);
+      if (D.view != kViewFull) {
+        write_view(D.view_ptr, e, D.view, gl, bits);
+      } else if (gl < view_words(k)) {
+        // the compact copy is not used for weighted nets: keep it defined (zero)
+        D.view_ptr[e * view_words(k) + gl] = 0u;
+      }
+      if (gl == 0) km1_local += (long long)(bits.lambda - 1) * w;
+    }
     wave_lds_sync();
   }
-  if (err) atomicOr(err_flags, err);
+  if (err) atomicOr(D.err_flags, err);
   const long long tot = block_sum64(km1_local, s_tmp);
   if (threadIdx.x == 0 && tot)
-    atomicAdd(&km1_slots[blockIdx.x % kSlots], (unsigned long long)tot);
+    atomicAdd(&D.red[blockIdx.x % kSlots], (unsigned long long)tot);
 }
 
-// Block weights: LDS partial sums per workgroup, then one atomic per block.
-__global__ __launch_bounds__(kBlock) void k_block_weights(int n, int k, const int* part,
-                                                          const int* vwgt,
-                                                          unsigned long long* block_w,
-                                                          int* err_flags) {
+// Unit: one instance.  Sum its km1 slots into *km1 (or just clear them) and
+// clear the block weights for the sweep that follows.
+__global__ __launch_bounds__(kBlock) void k_count_epilogue(Launch L, int want_km1) {
+  const WorkItem wi = work_item_s(L, WorkItem{0, 0, 1, 1});
+  const InstDesc D = inst_desc_s(L, wi.inst);
+  if (threadIdx.x < kWave) {
+    const int lane = lane_id();
+    long long v = (long long)D.red[lane];
+    D.red[lane] = 0;
+    v = wave_sum(v);
+    if (lane == 0 && want_km1) *D.km1 = v;
+  }
+  for (int i = threadIdx.x; i < D.k; i += kBlock) D.block_w[i] = 0;
+}
+
+// Unit: kBwChunk consecutive vertices.  LDS partial sums per workgroup, then
+// one atomic per block.
+__global__ __launch_bounds__(kBlock) void k_block_weights(Launch L) {
   __shared__ unsigned long long s_w[HG_MAX_K];
+  const WorkItem wi = work_item_s(L, contiguous_units((L.one.n + kBwChunk - 1) / kBwChunk));
+  const InstDesc D = inst_desc_s(L, wi.inst);
+  const int k = D.k, n = D.n;
   for (int i = threadIdx.x; i < k; i += kBlock) s_w[i] = 0;
   __syncthreads();
-  long long stride = (long long)gridDim.x * kBlock;
   int err = 0;
-  for (long long v = (long long)blockIdx.x * kBlock + threadIdx.x; v < n; v += stride) {
-    int blk = part[v];
-    if ((unsigned)blk < (unsigned)k)
-      atomicAdd(&s_w[blk], (unsigned long long)(vwgt ? vwgt[v] : 1));
-    else
-      err = kErrPart;
+  for (int it = 0; it < wi.count; ++it) {
+    const long long base = ((long long)wi.first + (long long)it * wi.stride) * kBwChunk;
+    for (int j = 0; j < kBwChunk / kBlock; ++j) {
+      const long long v = base + (long long)j * kBlock + threadIdx.x;
+      if (v >= n) break;
+      const int blk = D.part[v];
+      if ((unsigned)blk < (unsigned)k)
+        atomicAdd(&s_w[blk], (unsigned long long)(D.vwgt ? D.vwgt[v] : 1));
+      else
+        err = kErrPart;
+    }
   }
-  if (err) atomicOr(err_flags, err);
+  if (err) atomicOr(D.err_flags, err);
   __syncthreads();
   for (int i = threadIdx.x; i < k; i += kBlock)
-    if (s_w[i]) atomicAdd(&block_w[i], s_w[i]);
+    if (s_w[i]) atomicAdd((unsigned long long*)&D.block_w[i], s_w[i]);
 }
 
-// km1 partial sums from the net-state records.
+// km1 partial sums from the net-state records (single instance only).
 __global__ __launch_bounds__(kBlock) void k_km1(int m, int rw, const unsigned* netstate,
                                                 unsigned long long* km1_slots) {
   __shared__ long long s_tmp[kBlock / kWave];
@@ -118,17 +160,6 @@ static unsigned grid_cap(long long items, int per_block, int cap) {
   return (unsigned)b;
 }
 
-template <int G>
-static void launch_pincounts_g(hg_graph_s* g, int k, const int* part, int* phi,
-                               unsigned* netstate, unsigned long long* slots, int* err,
-                               hipStream_t s) {
-  unsigned grid = grid_cap(g->m, kBlock / G, kStateGrid);
-  size_t lds = sizeof(int) * (size_t)(kBlock / G) * k;
-  hipLaunchKernelGGL(k_pincounts<G>, dim3(grid), dim3(kBlock), lds, s, g->m, k, net_words(k),
-                     g->eptr, g->pins, g->ewgt, part, phi, netstate, slots, err,
-                     netstate + (size_t)g->m * net_words(k), net_view(k, g->unit_nets));
-}
-
 // Lanes per net for the net-centric sweeps: enough lanes to hold every word
 // of the net record (2 + 2 * bit_words(k), padded), few enough that a wave
 // works on several nets at once (most nets have only a handful of pins).
@@ -139,43 +170,48 @@ int group_lanes(int k) {
   return 32;
 }
 
-hipError_t launch_pincounts(hg_graph_s* g, int k, const int* part, int* phi,
-                            unsigned* netstate, long long* block_w, long long* km1,
-                            hipStream_t s) {
-  int* err = (int*)(g->ws + g->lay.flags);
-  unsigned long long* slots = (unsigned long long*)(g->ws + g->lay.red);
+GroupKernel pincount_kernel(int k) {
   switch (group_lanes(k)) {
-    case 4: launch_pincounts_g<4>(g, k, part, phi, netstate, slots, err, s); break;
-    case 8: launch_pincounts_g<8>(g, k, part, phi, netstate, slots, err, s); break;
-    case 16: launch_pincounts_g<16>(g, k, part, phi, netstate, slots, err, s); break;
-    case 32: launch_pincounts_g<32>(g, k, part, phi, netstate, slots, err, s); break;
-    default: launch_pincounts_g<64>(g, k, part, phi, netstate, slots, err, s); break;
+    case 4: return k_pincounts<4>;
+    case 8: return k_pincounts<8>;
+    case 16: return k_pincounts<16>;
+    default: return k_pincounts<32>;
   }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  if (net_view(k, g->unit_nets) == kViewFull && view_words(k) > 0) {
-    // the compact copy is not used for weighted nets: keep it defined (zero)
-    e = fill_i32((int*)netstate + (size_t)g->m * net_words(k), 0,
-                 (long long)g->m * view_words(k), s);
-    if (e != hipSuccess) return e;
-  }
-  if (km1) {
-    hipLaunchKernelGGL(k_sum_slots, dim3(1), dim3(kWave), 0, s, slots, km1);
-  } else {
-    e = fill_i64((long long*)slots, 0, kSlots, s);
-    if (e != hipSuccess) return e;
-  }
-  e = fill_i64(block_w, 0, k, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_block_weights, dim3(grid_cap(g->n, kBlock * 16, 4096)), dim3(kBlock), 0,
-                     s, g->n, k, part, g->vwgt, (unsigned long long*)block_w, err);
+}
+
+void single_count_plan(const InstDesc& d, CountPlan& plan) {
+  plan = CountPlan();
+  Launch L;
+  L.descs = nullptr;
+  L.items = nullptr;
+  L.one = d;
+  PlanLaunch pc;
+  pc.kernel = (void*)pincount_kernel(d.k);
+  pc.grid = grid_cap(d.m, kBlock / group_lanes(d.k), kStateGrid);
+  pc.lds = sizeof(int) * (size_t)(kBlock / group_lanes(d.k)) * d.k;
+  pc.L = L;
+  plan.pincounts.push_back(pc);
+  plan.instances.grid = 1;
+  plan.instances.L = L;
+  plan.vertices.grid = grid_cap(d.n, kBwChunk, 4096);
+  plan.vertices.L = L;
+}
+
+// Pin counts, then km1 / block-weight reset / view zeroing, then block weights.
+hipError_t launch_counts(const CountPlan& plan, bool want_km1, hipStream_t s) {
+  for (const PlanLaunch& pl : plan.pincounts)
+    hipLaunchKernelGGL((GroupKernel)pl.kernel, dim3(pl.grid), dim3(kBlock), pl.lds, s, pl.L);
+  hipLaunchKernelGGL(k_count_epilogue, dim3(plan.instances.grid), dim3(kBlock), 0, s,
+                     plan.instances.L, want_km1 ? 1 : 0);
+  hipLaunchKernelGGL(k_block_weights, dim3(plan.vertices.grid), dim3(kBlock), 0, s,
+                     plan.vertices.L);
   return hipGetLastError();
 }
 
 hipError_t launch_km1(hg_graph_s* g, int k, const unsigned* netstate, long long* km1,
                       hipStream_t s) {
   unsigned long long* slots = (unsigned long long*)(g->ws + g->lay.red);
-  hipLaunchKernelGGL(k_km1, dim3(grid_cap(g->m, kBlock * 8, kStateGrid)), dim3(kBlock), 0, s,
+  hipLaunchKernelGGL(k_km1, dim3(grid_cap(g->m, kKm1Chunk, kStateGrid)), dim3(kBlock), 0, s,
                      g->m, net_words(k), netstate, slots);
   hipLaunchKernelGGL(k_sum_slots, dim3(1), dim3(kWave), 0, s, slots, km1);
   return hipGetLastError();
