@@ -247,6 +247,101 @@ hg_status hg_sync_status(hg_graph g, void* stream);
 /* Message for the last non-OK status returned on this host thread. */
 const char* hg_last_error(void);
 
+/* ------------------------------------------------------------------ batches
+ * Many independent refinements advanced together.  Every kernel of a round
+ * (and of the pin-count pass that starts a refinement) is launched once for
+ * the whole batch; each workgroup reads its instance and its share of the
+ * work from a table in caller device memory.  An instance's sweeps are
+ * placed on one XCD (large instances: spread over all eight), so its net
+ * records stay in that XCD's L2.  The arithmetic is that of the single-
+ * instance calls: every output is bit-identical to hg_refine on the instance
+ * alone, whatever else shares the batch. */
+
+typedef struct hg_batch_s* hg_batch;
+
+/* One member of a batch: a loaded hypergraph and the caller's state for one
+ * k-way partition of it (the buffers hg_refine takes, same layouts).  A graph
+ * handle may appear in at most one member of a batch, and in at most one
+ * batch (or hg_* call) whose work is in flight: its workspace is the
+ * refinement's scratch space. */
+typedef struct {
+  hg_graph g;
+  int32_t k;                 /* 2 <= k <= k_max of g                            */
+  int32_t reserved;          /* set to 0                                         */
+  double eps;                /* L_max = hg_max_block_weight(g, k, eps)           */
+  int32_t* part;             /* int32[n] in/out                                  */
+  int32_t* phi;              /* int32[m*k]                                       */
+  uint32_t* netstate;        /* uint32[hg_netstate_words(m, k)]                  */
+  int64_t* block_w;          /* int64[k]                                         */
+  uint8_t* eligible;         /* uint8[n]                                         */
+  hg_round_stats* stats;     /* round r of hg_batch_round writes stats[r]        */
+  int64_t* km1;              /* int64[1]: km1 of the current state               */
+} hg_instance;
+
+/* How the batched sweeps split one instance's work into workgroups, for the
+ * instances of one size class.  Any schedule gives the same results; only the
+ * speed differs (hg_batch_autotune measures). */
+typedef struct {
+  int32_t select_chunks;     /* 256-vertex chunks per select workgroup, 1..64    */
+  int32_t finalize_chunks;   /* 256-net chunks per finalize workgroup, 1..64     */
+  int32_t count_chunks;      /* 256-net chunks per pin-count workgroup, 1..64    */
+  int32_t net_lanes;         /* lanes per net in the pin-count and finalize
+                                sweeps: 0 = the minimum for k (4 for k <= 4, 8
+                                for k <= 8, 16 for k <= 128, else 32), or 4, 8,
+                                16, 32 (raised to that minimum)                  */
+} hg_schedule;
+
+/* Size classes, by vertex count n: [0, 2^13), [2^13, 2^16), [2^16, 2^19),
+ * [2^19, 2^31).  A schedule argument is an array of HG_SIZE_CLASSES entries;
+ * NULL means the built-in defaults. */
+#define HG_SIZE_CLASSES 4
+
+/* Device bytes of the work table for these members: enough for every
+ * schedule (so hg_batch_autotune can use the same table).  0 on bad input. */
+size_t hg_batch_table_bytes(const hg_instance* members, int32_t count);
+
+/* Check the members (as hg_refine checks its arguments, plus: no graph
+ * twice), place them on XCDs, build the work tables for `sched` and copy
+ * them to `table` (device, table_bytes >= hg_batch_table_bytes) on `stream`.
+ * The handle keeps a host copy of the members; `table` must stay alive until
+ * hg_batch_free.  Members are numbered 0..count-1 in the given order. */
+hg_status hg_batch_create(const hg_instance* members, int32_t count, const hg_schedule* sched,
+                          void* table, size_t table_bytes, void* stream, hg_batch* out);
+
+/* Release the handle (waits for its last table copy; device arrays stay). */
+void hg_batch_free(hg_batch b);
+
+/* Start every member's refinement: pin counts, net state, block weights and
+ * km1 from its partition, every vertex eligible (hg_compute_pincounts plus
+ * the set-up hg_refine does). */
+hg_status hg_batch_start(hg_batch b, void* stream);
+
+/* One label-propagation round (as hg_lp_round with L_max from eps and no
+ * moved flags) for every member; member i's record goes to stats_i[round]. */
+hg_status hg_batch_round(hg_batch b, int32_t round, void* stream);
+
+/* hg_batch_start, then rounds 0..rounds-1.  use_graph != 0 records the whole
+ * sequence once into one hipGraph (kept in the handle while `rounds` stays
+ * the same) and launches it. */
+hg_status hg_batch_refine(hg_batch b, int32_t rounds, int32_t use_graph, void* stream);
+
+/* Measure schedules and keep the fastest per size class.  For each class
+ * present, each field of the schedule in turn takes each of its candidate
+ * values (chunks 1, 2, 4, 8, 16; lanes 0, 2x minimum); a trial runs
+ * hg_batch_start and one round on the members of that class, `repeats` times
+ * (best time wins).  The members' partitions are saved into part_save
+ * (device int32, at least the sum of their n) first and restored after every
+ * trial, so on return each member's `part` is unchanged and its other state
+ * must be rebuilt (hg_batch_start).  Synchronizes `stream`.  The chosen
+ * schedules are written to best[HG_SIZE_CLASSES] (may be NULL) and the
+ * batch's tables are rebuilt with them. */
+hg_status hg_batch_autotune(hg_batch b, int32_t* part_save, int64_t save_elems,
+                            int32_t repeats, void* stream, hg_schedule* best);
+
+/* The batch's current schedules (HG_SIZE_CLASSES entries); with b == NULL
+ * the built-in defaults. */
+hg_status hg_batch_get_schedule(hg_batch b, hg_schedule* sched);
+
 #ifdef __cplusplus
 }
 #endif

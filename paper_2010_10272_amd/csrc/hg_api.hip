@@ -16,8 +16,10 @@ hipError_t load_sort_big(hg_graph_s* g, int big_rows, hipStream_t s);
 }
 
 namespace {
-
 thread_local char g_msg[512] = "";
+}  // namespace
+
+namespace hg {
 
 hg_status fail(hg_status code, const char* fmt, ...) {
   va_list ap;
@@ -31,11 +33,23 @@ hg_status hip_fail(hipError_t e, const char* what) {
   return fail(HG_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define HG_TRY(expr, what)                       \
-  do {                                           \
-    hipError_t _e = (expr);                      \
-    if (_e != hipSuccess) return hip_fail(_e, what); \
-  } while (0)
+hg_status check_k(hg_graph g, int k) {
+  if (!g) return fail(HG_ERR_INVALID, "graph handle is NULL");
+  if (k < 2) return fail(HG_ERR_INVALID, "k must be at least 2 (got %d)", k);
+  if (k > HG_MAX_K) return fail(HG_ERR_UNSUPPORTED, "k must be at most %d (got %d)", HG_MAX_K, k);
+  if (k > g->k_max)
+    return fail(HG_ERR_WORKSPACE, "k = %d exceeds the k_max = %d the workspace was sized for", k,
+                g->k_max);
+  return HG_OK;
+}
+
+}  // namespace hg
+
+namespace {
+
+using hg::check_k;
+using hg::fail;
+using hg::hip_fail;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -48,16 +62,6 @@ const char* describe_err(int err) {
   if (err & hg::kErrDuplicate) return "a vertex appears twice in one net (nets are sets)";
   if (err & hg::kErrPart) return "a partition id lies outside [0, k)";
   return "invalid input";
-}
-
-hg_status check_k(hg_graph g, int k) {
-  if (!g) return fail(HG_ERR_INVALID, "graph handle is NULL");
-  if (k < 2) return fail(HG_ERR_INVALID, "k must be at least 2 (got %d)", k);
-  if (k > HG_MAX_K) return fail(HG_ERR_UNSUPPORTED, "k must be at most %d (got %d)", HG_MAX_K, k);
-  if (k > g->k_max)
-    return fail(HG_ERR_WORKSPACE, "k = %d exceeds the k_max = %d the workspace was sized for", k,
-                g->k_max);
-  return HG_OK;
 }
 
 hg_status read_info(hg_graph_s* g, hipStream_t s) {
@@ -157,6 +161,7 @@ InstDesc make_desc(hg_graph_s* g, int k, long long lmax, int* part, int* phi,
   d.heavy_count = g->info.heavy_count;
   d.num_tiles = g->lay.num_tiles;
   d.hist_stride = g->k_max * kBuckets;
+  d.hist_reps = kHistReplicas;
   d.lmax = lmax;
   d.eptr = g->eptr;
   d.pins = g->pins;
@@ -322,7 +327,7 @@ hg_status hg_compute_pincounts(hg_graph g, int32_t k, const int32_t* part, int32
                                  nullptr, (long long*)km1_out, nullptr);
   hg::CountPlan plan;
   hg::single_count_plan(d, plan);
-  HG_TRY(hg::launch_counts(plan, km1_out != nullptr, (hipStream_t)stream), "pin counts");
+  HG_TRY(hg::launch_counts(plan, km1_out != nullptr, false, (hipStream_t)stream), "pin counts");
   return HG_OK;
 }
 
@@ -364,7 +369,7 @@ hg_status hg_lp_round(hg_graph g, int32_t k, int64_t max_block_w, int32_t* part,
                                  eligible, moved, (long long*)km1, stats);
   hg::RoundPlan plan;
   hg::single_round_plan(d, plan);
-  HG_TRY(hg::launch_round(plan, (hipStream_t)stream, marks), "label-propagation round");
+  HG_TRY(hg::launch_round(plan, 0, (hipStream_t)stream, marks), "label-propagation round");
   return HG_OK;
 }
 
@@ -376,16 +381,14 @@ static hipError_t enqueue_refine(hg_graph g, int k, long long lmax, int rounds, 
                                  nullptr, (long long*)km1, stats);
   hg::CountPlan cplan;
   hg::single_count_plan(d, cplan);
-  hipError_t e = hg::launch_counts(cplan, true, s);
-  if (e != hipSuccess) return e;
-  e = hg::fill_u8(eligible, 1, g->n, s);
+  hipError_t e = hg::launch_counts(cplan, true, true, s);
   hg::RoundPlan plan;
   for (int r = 0; r < rounds && e == hipSuccess; ++r) {
     hipEvent_t* marks = nullptr;
     if (timing_marks(g, s, &marks) != HG_OK) return hipErrorUnknown;
     d.stats = stats + r;
     hg::single_round_plan(d, plan);
-    e = hg::launch_round(plan, s, marks);
+    e = hg::launch_round(plan, 0, s, marks);
   }
   return e;
 }

@@ -14,13 +14,6 @@
 
 namespace hg {
 
-__device__ __forceinline__ WorkItem work_item_g(const Launch& L, WorkItem fallback) {
-  return L.items ? L.items[blockIdx.x] : fallback;
-}
-__device__ __forceinline__ InstDesc inst_desc_g(const Launch& L, int inst) {
-  return L.descs ? L.descs[inst] : L.one;
-}
-
 // Unit: a chunk of 256 vertices (single instance: blockIdx, XCD-remapped).
 // Row u of `gains` (k int64) and benefit[u] are written.
 template <int WK, int VIEW>
@@ -31,8 +24,8 @@ __global__ __launch_bounds__(kBlock) void k_gains_light(Launch L, long long* __r
   fb.first = (int)xcd_remap(blockIdx.x, gridDim.x);
   fb.count = 1;
   fb.stride = 1;
-  const WorkItem wi = work_item_g(L, fb);
-  const InstDesc D = inst_desc_g(L, wi.inst);
+  const WorkItem wi = work_item(L, fb);
+  const InstDesc D = inst_desc(L, wi.inst);
   const int k = D.k;
   const long long u = (long long)wi.first * kBlock + threadIdx.x;
   if (u >= D.n) return;
@@ -110,8 +103,8 @@ __global__ __launch_bounds__(kBlock) void k_gains_heavy(Launch L, long long* __r
   fb.first = blockIdx.x;
   fb.count = 1;
   fb.stride = 1;
-  const WorkItem wi = work_item_g(L, fb);
-  const InstDesc D = inst_desc_g(L, wi.inst);
+  const WorkItem wi = work_item(L, fb);
+  const InstDesc D = inst_desc(L, wi.inst);
   const int k = D.k;
   const int wv = threadIdx.x / kWave, lane = lane_id();
   const long long idx = (long long)wi.first * (kBlock / kWave) + wv;
@@ -169,10 +162,7 @@ GainsKernel gains_kernel(int k, int view) {
 hipError_t launch_gains(hg_graph_s* g, const InstDesc& d, long long* gains, long long* benefit,
                         hipStream_t s) {
   typedef void (*K)(Launch, long long*, long long*);
-  Launch L;
-  L.descs = nullptr;
-  L.items = nullptr;
-  L.one = d;
+  const Launch L = single_launch(d);
   unsigned grid = (unsigned)(((long long)d.n + kBlock - 1) / kBlock);
   hipLaunchKernelGGL((K)(void*)gains_kernel(d.k, d.view), dim3(grid), dim3(kBlock), 0, s, L,
                      gains, benefit);

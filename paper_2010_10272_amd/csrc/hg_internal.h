@@ -97,7 +97,7 @@ struct InstDesc {
   int k, rw, view, unit_nets;
   int cmax, lds_buckets, heavy_count, num_tiles;
   int hist_stride;               // k_max * kBuckets: distance between histogram replicas
-  int pad0;
+  int hist_reps;                 // histogram replicas in use (workgroup b adds to b % hist_reps)
   long long P, lmax;
   const long long* eptr;
   const int* pins;
@@ -136,11 +136,56 @@ struct WorkItem {
 // Kernel argument: a batch (descs + items, both device arrays) or one
 // instance by value (descs == nullptr; each kernel then derives its units
 // from blockIdx as documented with it).
+//
+// In a batch the items are either one per workgroup (split == 0) or grouped
+// by XCD (split == 1): workgroup b runs on XCD b % 8 and takes item
+// b / 8 of that XCD's queue items[xoff[x] .. xoff[x+1]), or nothing once the
+// queue is used up.  Grouping keeps an instance's sweep on the XCD (and L2)
+// it was placed on.
 struct Launch {
   const InstDesc* descs;
   const WorkItem* items;
+  int round;                     // round record index: stats + round (k_round_stats)
+  int split;
+  int xoff[kNumXcd + 1];
+  int pad;
   InstDesc one;
 };
+
+// This workgroup's work item; `fallback` in single-instance mode.  An empty
+// item (count == 0) means: nothing to do.
+__device__ __forceinline__ WorkItem work_item(const Launch& L, WorkItem fallback) {
+  if (!L.items) return fallback;
+  if (!L.split) return L.items[blockIdx.x];
+  const int x = (int)(blockIdx.x % kNumXcd);
+  const int o = L.xoff[x] + (int)(blockIdx.x / kNumXcd);
+  if (o >= L.xoff[x + 1]) {
+    WorkItem w;
+    w.inst = 0;
+    w.first = 0;
+    w.count = 0;
+    w.stride = 1;
+    return w;
+  }
+  return L.items[o];
+}
+
+__device__ __forceinline__ InstDesc inst_desc(const Launch& L, int inst) {
+  return L.descs ? L.descs[inst] : L.one;
+}
+
+// Launch argument for one instance (kernels take their units from blockIdx).
+inline Launch single_launch(const InstDesc& d) {
+  Launch L;
+  L.descs = nullptr;
+  L.items = nullptr;
+  L.round = 0;
+  L.split = 0;
+  for (int x = 0; x <= kNumXcd; ++x) L.xoff[x] = 0;
+  L.pad = 0;
+  L.one = d;
+  return L;
+}
 
 struct WsLayout {
   size_t cand, touched, heavy, big, hist, overflow, thr, tilesum, ctr, info, scan, flags;
@@ -226,6 +271,17 @@ struct hg_graph_s {
 };
 
 namespace hg {
+
+// ---- error reporting (hg_last_error) ----
+hg_status fail(hg_status code, const char* fmt, ...);
+hg_status hip_fail(hipError_t e, const char* what);
+hg_status check_k(hg_graph_s* g, int k);
+
+#define HG_TRY(expr, what)                               \
+  do {                                                   \
+    hipError_t _e = (expr);                              \
+    if (_e != hipSuccess) return hg::hip_fail(_e, what); \
+  } while (0)
 
 // ---- launch helpers implemented in the .hip files (return hipError_t) ----
 hipError_t fill_i64(long long* p, long long v, long long count, hipStream_t s);

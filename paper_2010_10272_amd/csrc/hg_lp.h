@@ -42,15 +42,20 @@ struct CountPlan {
 constexpr int kBwChunk = kBlock * 16;   // vertices per unit of the block-weight sweep
 
 SelectKernel select_kernel(int k, int view);
-FinalizeKernel finalize_kernel(int k);
+FinalizeKernel finalize_kernel(int k);       // lanes per net: group_lanes(k)
+FinalizeKernel finalize_kernel_g(int G);     // G lanes per net (4, 8, 16 or 32)
 GroupKernel pincount_kernel(int k);
+GroupKernel pincount_kernel_g(int G);
 GainsKernel gains_kernel(int k, int view);
 int group_lanes(int k);
 
-hipError_t launch_round(const RoundPlan& plan, hipStream_t s, hipEvent_t* marks);
+// Enqueue one round; the round record goes to stats[round] of every instance.
+hipError_t launch_round(const RoundPlan& plan, int round, hipStream_t s, hipEvent_t* marks);
 void single_round_plan(const InstDesc& d, RoundPlan& plan);
 
-hipError_t launch_counts(const CountPlan& plan, bool want_km1, hipStream_t s);
+// Pin counts, block weights and (want_km1) km1 of every instance; with
+// mark_eligible every vertex is made eligible as well.
+hipError_t launch_counts(const CountPlan& plan, bool want_km1, bool mark_eligible, hipStream_t s);
 void single_count_plan(const InstDesc& d, CountPlan& plan);
 
 hipError_t launch_gains(hg_graph_s* g, const InstDesc& d, long long* gains, long long* benefit,

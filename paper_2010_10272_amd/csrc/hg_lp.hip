@@ -44,15 +44,6 @@ __device__ __forceinline__ long long pack_cand(int gain, int target) {
 __device__ __forceinline__ int cand_target(long long x) { return (int)(x & 0xffffffffLL); }
 __device__ __forceinline__ int cand_gain(long long x) { return (int)(x >> 32); }
 
-// Work item of this workgroup.  Single-instance mode: `fallback` (computed by
-// the kernel from blockIdx).
-__device__ __forceinline__ WorkItem work_item(const Launch& L, WorkItem fallback) {
-  return L.items ? L.items[blockIdx.x] : fallback;
-}
-__device__ __forceinline__ InstDesc inst_desc(const Launch& L, int inst) {
-  return L.descs ? L.descs[inst] : L.one;
-}
-
 // XCD-aware strided split of `units` over `grid` workgroups: XCD x owns the
 // contiguous range [x*per_xcd, (x+1)*per_xcd) and its workgroups take
 // neighbouring units side by side.
@@ -111,6 +102,7 @@ __global__ __launch_bounds__(kBlock) void k_select_light(Launch L) {
   __shared__ long long s_tmp[kBlock / kWave];
   const InstDesc D0 = L.one;
   const WorkItem wi = work_item(L, xcd_sweep((D0.n + kBlock - 1) / kBlock));
+  if (wi.count == 0) return;
   const InstDesc D = inst_desc(L, wi.inst);
   const int k = D.k, B = D.lds_buckets, n = D.n;
   const long long lmax = D.lmax;
@@ -123,7 +115,7 @@ __global__ __launch_bounds__(kBlock) void k_select_light(Launch L) {
     if (W + D.cmax <= lmax) atomicOr(&s_open[i >> 5], 1u << (i & 31));
   }
   __syncthreads();
-  unsigned long long* my_hist = D.hist + (size_t)(blockIdx.x % kHistReplicas) * D.hist_stride;
+  unsigned long long* my_hist = D.hist + (size_t)(blockIdx.x % D.hist_reps) * D.hist_stride;
   long long n_elig = 0, n_bnd = 0, n_cand = 0, n_apins = 0;
   // valid-block masks (only blocks < k; guards against stale caller state)
   unsigned valid[WK];
@@ -286,7 +278,7 @@ __global__ __launch_bounds__(kBlock) void k_select_heavy(Launch L) {
   const long long idx = (long long)wi.first * (kBlock / kWave) + wv;
   if (idx >= D.heavy_count) return;
   const int sl = (int)(idx % kSlots);
-  unsigned long long* my_hist = D.hist + (size_t)(blockIdx.x % kHistReplicas) * D.hist_stride;
+  unsigned long long* my_hist = D.hist + (size_t)(blockIdx.x % D.hist_reps) * D.hist_stride;
   RoundCounters* ctr = D.ctr;
   const int u = D.heavy_list[idx];
   const int a = D.part[u];
@@ -389,6 +381,7 @@ __global__ __launch_bounds__(kBlock) void k_threshold(Launch L) {
   long long h = 0;
 #pragma unroll
   for (int rep = 0; rep < kHistReplicas; ++rep) {
+    if (rep >= D.hist_reps) break;
     unsigned long long* cell = D.hist + (size_t)rep * D.hist_stride + (size_t)t * kBuckets + bucket;
     h += (long long)*cell;
     *cell = 0;
@@ -738,6 +731,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Launch L) {
   __shared__ unsigned s_cnt;
   constexpr int kGroups = kBlock / G;
   const WorkItem wi = work_item(L, xcd_block((L.one.m + kFinalChunk - 1) / kFinalChunk));
+  if (wi.count == 0) return;
   const InstDesc D = inst_desc(L, wi.inst);
   const int grp = threadIdx.x / G, gl = threadIdx.x % G;
   const int k = D.k, wk = bit_words(k), rw = D.rw;
@@ -817,7 +811,7 @@ __global__ __launch_bounds__(kBlock) void k_round_stats(Launch L) {
     st.km1_after = *D.km1 - st.km1_delta;
     st.max_block_weight = m;
     *D.km1 = st.km1_after;
-    *D.stats = st;
+    D.stats[L.round] = st;
     ctr->any_overflow = 0;
   }
 }
@@ -842,8 +836,10 @@ SelectKernel select_kernel(int k, int view) {
   }
 }
 
-FinalizeKernel finalize_kernel(int k) {
-  switch (group_lanes(k)) {
+FinalizeKernel finalize_kernel(int k) { return finalize_kernel_g(group_lanes(k)); }
+
+FinalizeKernel finalize_kernel_g(int G) {
+  switch (G) {
     case 4: return k_finalize<4>;
     case 8: return k_finalize<8>;
     case 16: return k_finalize<16>;
@@ -853,7 +849,7 @@ FinalizeKernel finalize_kernel(int k) {
 
 // Launch one round of every kernel for a batch (items per kernel kind) or a
 // single instance (L.descs == nullptr).
-hipError_t launch_round(const RoundPlan& plan, hipStream_t s, hipEvent_t* marks) {
+hipError_t launch_round(const RoundPlan& plan, int round, hipStream_t s, hipEvent_t* marks) {
   if (marks) (void)hipEventRecord(marks[0], s);
   for (const PlanLaunch& pl : plan.select)
     hipLaunchKernelGGL((SelectKernel)pl.kernel, dim3(pl.grid), dim3(kBlock), 0, s, pl.L);
@@ -871,7 +867,9 @@ hipError_t launch_round(const RoundPlan& plan, hipStream_t s, hipEvent_t* marks)
   if (marks) (void)hipEventRecord(marks[2], s);
   for (const PlanLaunch& pl : plan.finalize)
     hipLaunchKernelGGL((FinalizeKernel)pl.kernel, dim3(pl.grid), dim3(kBlock), 0, s, pl.L);
-  hipLaunchKernelGGL(k_round_stats, dim3(plan.stats.grid), dim3(kBlock), 0, s, plan.stats.L);
+  Launch ls = plan.stats.L;
+  ls.round = round;
+  hipLaunchKernelGGL(k_round_stats, dim3(plan.stats.grid), dim3(kBlock), 0, s, ls);
   if (marks) (void)hipEventRecord(marks[3], s);
   return hipGetLastError();
 }
@@ -879,10 +877,7 @@ hipError_t launch_round(const RoundPlan& plan, hipStream_t s, hipEvent_t* marks)
 // Plan for one instance (no work tables; kernels derive units from blockIdx).
 void single_round_plan(const InstDesc& d, RoundPlan& plan) {
   plan = RoundPlan();
-  Launch L;
-  L.descs = nullptr;
-  L.items = nullptr;
-  L.one = d;
+  const Launch L = single_launch(d);
   const long long chunks = ((long long)d.n + kBlock - 1) / kBlock;
   PlanLaunch sel;
   sel.kernel = (void*)select_kernel(d.k, d.view);

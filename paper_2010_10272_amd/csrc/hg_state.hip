@@ -17,12 +17,6 @@ namespace hg {
 constexpr int kStateGrid = 8192;   // persistent workgroups of the single-instance net sweep
 constexpr int kKm1Chunk = kBlock * 8;
 
-__device__ __forceinline__ WorkItem work_item_s(const Launch& L, WorkItem fallback) {
-  return L.items ? L.items[blockIdx.x] : fallback;
-}
-__device__ __forceinline__ InstDesc inst_desc_s(const Launch& L, int inst) {
-  return L.descs ? L.descs[inst] : L.one;
-}
 __device__ __forceinline__ WorkItem contiguous_units(long long units) {
   const long long lb = xcd_remap(blockIdx.x, gridDim.x);
   const long long per = (units + gridDim.x - 1) / gridDim.x;
@@ -43,8 +37,9 @@ __global__ __launch_bounds__(kBlock) void k_pincounts(Launch L) {
   extern __shared__ int s_cnt[];   // [kBlock/G][k]
   __shared__ long long s_tmp[kBlock / kWave];
   constexpr int kGroups = kBlock / G;
-  const WorkItem wi = work_item_s(L, contiguous_units((L.one.m + kGroups - 1) / kGroups));
-  const InstDesc D = inst_desc_s(L, wi.inst);
+  const WorkItem wi = work_item(L, contiguous_units((L.one.m + kGroups - 1) / kGroups));
+  if (wi.count == 0) return;
+  const InstDesc D = inst_desc(L, wi.inst);
   const int grp = threadIdx.x / G;
   const int gl = threadIdx.x % G;
   const int k = D.k, m = D.m, rw = D.rw;
@@ -90,8 +85,8 @@ __global__ __launch_bounds__(kBlock) void k_pincounts(Launch L) {
 // Unit: one instance.  Sum its km1 slots into *km1 (or just clear them) and
 // clear the block weights for the sweep that follows.
 __global__ __launch_bounds__(kBlock) void k_count_epilogue(Launch L, int want_km1) {
-  const WorkItem wi = work_item_s(L, WorkItem{0, 0, 1, 1});
-  const InstDesc D = inst_desc_s(L, wi.inst);
+  const WorkItem wi = work_item(L, WorkItem{0, 0, 1, 1});
+  const InstDesc D = inst_desc(L, wi.inst);
   if (threadIdx.x < kWave) {
     const int lane = lane_id();
     long long v = (long long)D.red[lane];
@@ -103,11 +98,13 @@ __global__ __launch_bounds__(kBlock) void k_count_epilogue(Launch L, int want_km
 }
 
 // Unit: kBwChunk consecutive vertices.  LDS partial sums per workgroup, then
-// one atomic per block.
-__global__ __launch_bounds__(kBlock) void k_block_weights(Launch L) {
+// one atomic per block.  With mark_eligible every vertex is also made
+// eligible (the start of a refinement).
+__global__ __launch_bounds__(kBlock) void k_block_weights(Launch L, int mark_eligible) {
   __shared__ unsigned long long s_w[HG_MAX_K];
-  const WorkItem wi = work_item_s(L, contiguous_units((L.one.n + kBwChunk - 1) / kBwChunk));
-  const InstDesc D = inst_desc_s(L, wi.inst);
+  const WorkItem wi = work_item(L, contiguous_units((L.one.n + kBwChunk - 1) / kBwChunk));
+  if (wi.count == 0) return;
+  const InstDesc D = inst_desc(L, wi.inst);
   const int k = D.k, n = D.n;
   for (int i = threadIdx.x; i < k; i += kBlock) s_w[i] = 0;
   __syncthreads();
@@ -118,6 +115,7 @@ __global__ __launch_bounds__(kBlock) void k_block_weights(Launch L) {
       const long long v = base + (long long)j * kBlock + threadIdx.x;
       if (v >= n) break;
       const int blk = D.part[v];
+      if (mark_eligible) D.eligible[v] = 1;
       if ((unsigned)blk < (unsigned)k)
         atomicAdd(&s_w[blk], (unsigned long long)(D.vwgt ? D.vwgt[v] : 1));
       else
@@ -170,8 +168,10 @@ int group_lanes(int k) {
   return 32;
 }
 
-GroupKernel pincount_kernel(int k) {
-  switch (group_lanes(k)) {
+GroupKernel pincount_kernel(int k) { return pincount_kernel_g(group_lanes(k)); }
+
+GroupKernel pincount_kernel_g(int G) {
+  switch (G) {
     case 4: return k_pincounts<4>;
     case 8: return k_pincounts<8>;
     case 16: return k_pincounts<16>;
@@ -181,10 +181,7 @@ GroupKernel pincount_kernel(int k) {
 
 void single_count_plan(const InstDesc& d, CountPlan& plan) {
   plan = CountPlan();
-  Launch L;
-  L.descs = nullptr;
-  L.items = nullptr;
-  L.one = d;
+  const Launch L = single_launch(d);
   PlanLaunch pc;
   pc.kernel = (void*)pincount_kernel(d.k);
   pc.grid = grid_cap(d.m, kBlock / group_lanes(d.k), kStateGrid);
@@ -198,13 +195,13 @@ void single_count_plan(const InstDesc& d, CountPlan& plan) {
 }
 
 // Pin counts, then km1 / block-weight reset / view zeroing, then block weights.
-hipError_t launch_counts(const CountPlan& plan, bool want_km1, hipStream_t s) {
+hipError_t launch_counts(const CountPlan& plan, bool want_km1, bool mark_eligible, hipStream_t s) {
   for (const PlanLaunch& pl : plan.pincounts)
     hipLaunchKernelGGL((GroupKernel)pl.kernel, dim3(pl.grid), dim3(kBlock), pl.lds, s, pl.L);
   hipLaunchKernelGGL(k_count_epilogue, dim3(plan.instances.grid), dim3(kBlock), 0, s,
                      plan.instances.L, want_km1 ? 1 : 0);
   hipLaunchKernelGGL(k_block_weights, dim3(plan.vertices.grid), dim3(kBlock), 0, s,
-                     plan.vertices.L);
+                     plan.vertices.L, mark_eligible ? 1 : 0);
   return hipGetLastError();
 }
 

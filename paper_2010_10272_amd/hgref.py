@@ -42,6 +42,22 @@ class GraphInfo(ctypes.Structure):
                 ("max_incident_weight", ctypes.c_int32), ("heavy_vertices", ctypes.c_int32)]
 
 
+HG_SIZE_CLASSES = 4
+SCHEDULE_FIELDS = ("select_chunks", "finalize_chunks", "count_chunks", "net_lanes")
+
+
+class HgInstance(ctypes.Structure):
+    _fields_ = [("g", ctypes.c_void_p), ("k", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("eps", ctypes.c_double), ("part", ctypes.c_void_p), ("phi", ctypes.c_void_p),
+                ("netstate", ctypes.c_void_p), ("block_w", ctypes.c_void_p),
+                ("eligible", ctypes.c_void_p), ("stats", ctypes.c_void_p),
+                ("km1", ctypes.c_void_p)]
+
+
+class HgSchedule(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int32) for f in SCHEDULE_FIELDS]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libhgref.so not built (run __graft_entry__.build() or "
@@ -80,6 +96,24 @@ def _load():
     lib.hg_timing_collect.restype = i32
     lib.hg_sync_status.argtypes = [vp, vp]
     lib.hg_sync_status.restype = i32
+    inst_p = ctypes.POINTER(HgInstance)
+    sched_p = ctypes.POINTER(HgSchedule)
+    lib.hg_batch_table_bytes.argtypes = [inst_p, i32]
+    lib.hg_batch_table_bytes.restype = sz
+    lib.hg_batch_create.argtypes = [inst_p, i32, sched_p, vp, sz, vp, ctypes.POINTER(vp)]
+    lib.hg_batch_create.restype = i32
+    lib.hg_batch_free.argtypes = [vp]
+    lib.hg_batch_free.restype = None
+    lib.hg_batch_start.argtypes = [vp, vp]
+    lib.hg_batch_start.restype = i32
+    lib.hg_batch_round.argtypes = [vp, i32, vp]
+    lib.hg_batch_round.restype = i32
+    lib.hg_batch_refine.argtypes = [vp, i32, i32, vp]
+    lib.hg_batch_refine.restype = i32
+    lib.hg_batch_autotune.argtypes = [vp, vp, i64, i32, vp, sched_p]
+    lib.hg_batch_autotune.restype = i32
+    lib.hg_batch_get_schedule.argtypes = [vp, sched_p]
+    lib.hg_batch_get_schedule.restype = i32
     lib.hg_last_error.argtypes = []
     lib.hg_last_error.restype = ctypes.c_char_p
     return lib
@@ -295,3 +329,121 @@ def decode_netstate(netstate, m, k):
         wk *= 2
     r = netstate[:m * rw].view(m, rw)
     return r[:, 0], r[:, 1], r[:, 2:2 + wk], r[:, 2 + wk:2 + 2 * wk]
+
+
+# ---------------------------------------------------------------- batches
+
+class Member:
+    """One refinement in a batch: a Graph, its State, eps and a device stats
+    tensor of at least rounds * STATS_WORDS int64 entries."""
+
+    def __init__(self, g, st, eps, stats):
+        self.g, self.st, self.eps, self.stats = g, st, float(eps), stats
+
+    def _c(self):
+        st = self.st
+        return HgInstance(self.g.handle.value, st.k, 0, self.eps, st.part.data_ptr(),
+                          st.phi.data_ptr(), st.netstate.data_ptr(), st.block_w.data_ptr(),
+                          st.eligible.data_ptr(), self.stats.data_ptr(), st.km1.data_ptr())
+
+
+def _members_c(members):
+    arr = (HgInstance * len(members))()
+    for i, mb in enumerate(members):
+        arr[i] = mb._c()
+    return arr
+
+
+def _schedule_c(sched):
+    if sched is None:
+        return None
+    arr = (HgSchedule * HG_SIZE_CLASSES)()
+    for c in range(HG_SIZE_CLASSES):
+        for f in SCHEDULE_FIELDS:
+            setattr(arr[c], f, int(sched[c][f]))
+    return arr
+
+
+def _schedule_py(arr):
+    return [{f: int(getattr(arr[c], f)) for f in SCHEDULE_FIELDS} for c in range(HG_SIZE_CLASSES)]
+
+
+class Batch:
+    """A batch handle with the device table it reads and the members it
+    refers to (kept alive with it)."""
+
+    def __init__(self, handle, members, table):
+        self._h = handle
+        self.members = list(members)
+        self.table = table
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("batch already freed")
+        return self._h
+
+    def free(self):
+        if self._h is not None:
+            _lib.hg_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def hg_batch_table_bytes(members):
+    arr = _members_c(members)
+    return int(_lib.hg_batch_table_bytes(arr, len(members)))
+
+
+def hg_batch_create(members, sched=None, stream=None, table=None):
+    """Members: list of Member.  sched: None or HG_SIZE_CLASSES dicts with
+    SCHEDULE_FIELDS.  Returns a Batch."""
+    arr = _members_c(members)
+    nbytes = int(_lib.hg_batch_table_bytes(arr, len(members)))
+    if nbytes == 0:
+        raise HgError(HG_ERR_INVALID, _lib.hg_last_error().decode(errors="replace"))
+    dev = members[0].st.part.device
+    if table is None:
+        table = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    h = ctypes.c_void_p()
+    _check(_lib.hg_batch_create(arr, len(members), _schedule_c(sched), _ptr(table),
+                                table.numel() * table.element_size(), _stream(stream),
+                                ctypes.byref(h)))
+    return Batch(h, members, table)
+
+
+def hg_batch_start(b, stream=None):
+    _check(_lib.hg_batch_start(b.handle, _stream(stream)))
+
+
+def hg_batch_round(b, round_index, stream=None):
+    _check(_lib.hg_batch_round(b.handle, int(round_index), _stream(stream)))
+
+
+def hg_batch_refine(b, rounds, use_graph=True, stream=None):
+    _check(_lib.hg_batch_refine(b.handle, int(rounds), 1 if use_graph else 0, _stream(stream)))
+
+
+def hg_batch_autotune(b, repeats=3, stream=None):
+    """Tune the batch's schedules in place; returns the chosen schedules."""
+    total = sum(mb.g.n for mb in b.members)
+    save = torch.empty(max(total, 1), dtype=torch.int32, device=b.table.device)
+    out = (HgSchedule * HG_SIZE_CLASSES)()
+    _check(_lib.hg_batch_autotune(b.handle, _ptr(save), total, int(repeats), _stream(stream),
+                                  out))
+    return _schedule_py(out)
+
+
+def hg_batch_get_schedule(b=None):
+    out = (HgSchedule * HG_SIZE_CLASSES)()
+    _check(_lib.hg_batch_get_schedule(b.handle if b is not None else None, out))
+    return _schedule_py(out)
+
+
+def hg_batch_free(b):
+    b.free()

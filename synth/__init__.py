@@ -2,5 +2,5 @@
 
 Input generation only: nothing here computes pin counts, gains or moves.
 """
-from .hypergraphs import (Instance, describe, random_power_law, sparse_matrix,  # noqa: F401
-                          tiny_plain, vlsi_grid, with_k)
+from .hypergraphs import (Instance, batch_instances, describe, random_power_law,  # noqa: F401
+                          sparse_matrix, tiny_plain, vlsi_grid, with_k)

@@ -239,6 +239,39 @@ def vlsi_grid(seed=3, side=2000, height=2000, m=4_200_000, k=16, rounds=10):
                     k, 0.03, rounds, {"seed": seed})
 
 
+def _batch_member(args):
+    seed, n, m, k, rounds, i = args
+    return random_power_law(seed, n, m, k, hi=64, unit=True, rounds=rounds,
+                            name="batch%d-n%d-k%d" % (i, n, k))
+
+
+def batch_instances(seed=4, count=512, n_lo=1_000, n_hi=500_000, ks=(2, 4, 8, 32, 128),
+                    rounds=8, workers=1):
+    """Many independent power-law hypergraphs of uneven sizes (the batched
+    workload: 512 instances, 8 rounds each).
+
+    Draw order (one generator seeded with `seed`): for all instances, n =
+    round(exp(U(ln n_lo, ln n_hi))); then m = round(n * U(0.8, 1.2)); then k
+    uniform over `ks`; then a 63-bit seed per instance.  Instance i is
+    random_power_law(seed_i, n_i, m_i, k_i) with net sizes in [2, min(64, n)],
+    unit weights and Pi(v) = perm[v] mod k.  `workers` > 1 builds the
+    instances in that many processes (same result: each depends on its own
+    seed only).
+    """
+    rng = np.random.default_rng(seed)
+    ns = np.rint(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), count))).astype(np.int64)
+    ms = np.maximum(np.rint(ns * rng.uniform(0.8, 1.2, count)), 1).astype(np.int64)
+    kk = np.asarray(ks, np.int64)[rng.integers(0, len(ks), count)]
+    seeds = rng.integers(0, 2 ** 63 - 1, count, dtype=np.int64)
+    args = [(int(seeds[i]), int(ns[i]), int(ms[i]), int(kk[i]), rounds, i) for i in range(count)]
+    if workers > 1:
+        from concurrent.futures import ProcessPoolExecutor
+        import multiprocessing as mp
+        with ProcessPoolExecutor(workers, mp_context=mp.get_context("fork")) as ex:
+            return list(ex.map(_batch_member, args, chunksize=4))
+    return [_batch_member(a) for a in args]
+
+
 def describe(inst):
     sizes = np.diff(inst.eptr)
     deg = np.bincount(inst.pins, minlength=inst.n)
