@@ -82,31 +82,156 @@ def cpu_baseline(inst, rounds_per_k):
                                                            inst.P, t_total)}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-rounds", type=int, default=4)
-    ap.add_argument("--latency-reps", type=int, default=5)
-    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
-                    help="also run one plain device-to-device copy of MIB MiB (a known "
-                         "byte count for scaling HBM traffic counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
-        sys.exit(2)
+BATCH_COUNT = 512
+BATCH_ROUNDS = 8
 
+
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def batched_cpu_baseline(insts, budget_s):
+    """Oracle on a bounded sample of the batch: members in order, every LP
+    round of each, until about `budget_s` seconds of oracle time."""
+    from oracle import oracle as O
+    import numpy as np
+    t_total, pin_rounds, done = 0.0, 0, 0
+    for inst in insts:
+        h = O.Hypergraph(inst.n, inst.eptr, inst.pins, inst.c, inst.w)
+        h.incidence()
+        L = O.lmax(O.total_vertex_weight(h), inst.k, inst.eps)
+        part = inst.part.copy()
+        elig = np.ones(inst.n, np.uint8)
+        for _ in range(inst.rounds):
+            t0 = time.perf_counter()
+            part, elig, _, _ = O.lp_round(h, inst.k, L, part, elig)
+            t_total += time.perf_counter() - t0
+            pin_rounds += inst.P
+        done += 1
+        if t_total >= budget_s:
+            break
+    return {"value": pin_rounds / t_total, "unit": "pins/s", "cores": 1, "kind": "oracle",
+            "sample": "all %d rounds of the first %d of the %d batch members (%d pin-rounds), "
+                      "single-threaded C oracle, %.1f s" % (insts[0].rounds, done, len(insts),
+                                                           pin_rounds, t_total)}
+
+
+def batched_leg(args, H, dev):
+    """The batched workload: 512 power-law hypergraphs (n log-uniform in
+    [1e3, 5e5], k in {2,4,8,32,128}), 8 LP rounds each, refined by one
+    recorded hipGraph launch over one segmented allocation, against the same
+    512 refinements as sequential hg_refine calls (each a recorded graph)."""
     import torch
     import synth
-    from paper_2010_10272_amd import hgref as H
+    from paper_2010_10272_amd import segmented
+    print("batched: generating %d instances ..." % args.batch_count, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    insts = synth.batch_instances(seed=4, count=args.batch_count, rounds=BATCH_ROUNDS,
+                                  workers=8)
+    gen_s = time.perf_counter() - t0
+    R = BATCH_ROUNDS
+    P_total = sum(x.P for x in insts)
+    members, ar = segmented.load_batch(insts, dev, rounds=R)
+    part0 = ar.part_bytes.clone()
+    torch.cuda.synchronize()
+    print("batched: loaded (%.2f GB arena), sequential reference ..." % (ar.nbytes / 1e9),
+          file=sys.stderr, flush=True)
 
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", file=sys.stderr)
-        sys.exit(1)
-    dev = torch.device("cuda:0")
+    def timed(run, reps):
+        xs = []
+        for _ in range(reps):
+            ar.part_bytes.copy_(part0)
+            a, b = _events(torch)
+            a.record()
+            run()
+            b.record()
+            b.synchronize()
+            xs.append(a.elapsed_time(b))
+        return xs
+
+    def snapshot():
+        return (ar.part_bytes.clone(), torch.cat([mb.stats for mb in members]),
+                torch.cat([mb.st.km1 for mb in members]))
+
+    def seq():
+        for mb in members:
+            H.hg_refine(mb.g, mb.st, mb.eps, R, mb.stats, use_graph=True)
+
+    timed(seq, 1)                                     # records every member's graph
+    want = snapshot()
+    seq_ms = timed(seq, args.batch_reps)
+
+    b = H.hg_batch_create(members)
+    default_sched = H.hg_batch_get_schedule(b)
+
+    def bat():
+        H.hg_batch_refine(b, R, use_graph=True)
+
+    timed(bat, 1)                                     # records the batch graph
+    got = snapshot()
+    assert all(torch.equal(x, y) for x, y in zip(got, want)), "batched != sequential"
+    default_ms = timed(bat, args.batch_reps)
+    print("batched: autotuning ...", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    tuned = H.hg_batch_autotune(b, repeats=2)
+    tune_s = time.perf_counter() - t0
+    timed(bat, 1)
+    got = snapshot()
+    assert all(torch.equal(x, y) for x, y in zip(got, want)), "tuned batch != sequential"
+    tuned_ms = timed(bat, args.batch_reps)
+    # each batched round alone
+    lat = []
+    for _ in range(max(1, args.batch_reps // 2)):
+        ar.part_bytes.copy_(part0)
+        H.hg_batch_start(b)
+        for r in range(R):
+            a, e = _events(torch)
+            a.record()
+            H.hg_batch_round(b, r)
+            e.record()
+            e.synchronize()
+            lat.append(a.elapsed_time(e))
+    stats = [H.stats_to_dicts(mb.stats) for mb in members]
+    b.free()
+    best_ms = min(percentile(default_ms, 50), percentile(tuned_ms, 50))
+    out = {
+        "metric": "pins/s per LP round, batched",
+        "value": P_total * R / (best_ms / 1e3),
+        "unit": "pins/s",
+        "members": len(insts),
+        "rounds": R,
+        "P_total": P_total,
+        "n_total": sum(x.n for x in insts),
+        "batch_ms": best_ms,
+        "batch_ms_default_schedule": percentile(default_ms, 50),
+        "batch_ms_tuned_schedule": percentile(tuned_ms, 50),
+        "sequential_ms": percentile(seq_ms, 50),
+        "sequential_value": P_total * R / (percentile(seq_ms, 50) / 1e3),
+        "speedup_vs_sequential": percentile(seq_ms, 50) / best_ms,
+        "round_latency": {"p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99)},
+        "schedule_default": default_sched,
+        "schedule_tuned": tuned,
+        "tune_s": tune_s,
+        "moves_total": sum(s["approved"] for st in stats for s in st),
+        "active_pins_total": sum(s["active_pins"] for st in stats for s in st),
+        "generate_s": gen_s,
+        "arena_bytes": ar.nbytes,
+        "check": "final partitions, round records and km1 of all members identical to "
+                 "512 sequential hg_refine calls",
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = batched_cpu_baseline(insts, args.batch_cpu_s)
+    for mb in members:
+        mb.g.free()
+    del members, ar
+    torch.cuda.empty_cache()
+    return out
+
+
+def plain_leg(args, H, dev):
+    """The plain workload (module docstring): returns the JSON record."""
+    import torch
+    import synth
     print("generating workload ...", file=sys.stderr, flush=True)
     inst = synth.sparse_matrix(KS[0])
     n, m, P = inst.n, inst.m, inst.P
@@ -261,6 +386,43 @@ def main():
     if not args.no_cpu:
         print("cpu baseline ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_rounds)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-rounds", type=int, default=4)
+    ap.add_argument("--latency-reps", type=int, default=5)
+    ap.add_argument("--legs", default="plain,batched",
+                    help="comma list of plain, batched")
+    ap.add_argument("--batch-count", type=int, default=BATCH_COUNT)
+    ap.add_argument("--batch-reps", type=int, default=5)
+    ap.add_argument("--batch-cpu-s", type=float, default=8.0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run one plain device-to-device copy of MIB MiB (a known "
+                         "byte count for scaling HBM traffic counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2010_10272_amd import hgref as H
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    legs = set(args.legs.split(","))
+    out = plain_leg(args, H, dev) if "plain" in legs else {"metric": METRIC}
+    if "batched" in legs:
+        torch.cuda.empty_cache()
+        out["batched"] = batched_leg(args, H, dev)
     print(json.dumps(out), flush=True)
 
 

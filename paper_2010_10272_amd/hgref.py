@@ -244,19 +244,37 @@ def hg_max_block_weight(g, k, eps):
     return v
 
 
-class State:
-    """Device state of one k-way partition of a graph (caller-owned buffers)."""
+STATE_FIELDS = ("part", "phi", "netstate", "block_w", "km1", "eligible", "moved")
 
-    def __init__(self, g, k, part):
+
+def state_sizes(n, m, k):
+    """(dtype, element count) of every State buffer for n vertices, m nets, k."""
+    return {"part": (torch.int32, n), "phi": (torch.int32, m * k),
+            "netstate": (torch.int32, hg_netstate_words(m, k)), "block_w": (torch.int64, k),
+            "km1": (torch.int64, 1), "eligible": (torch.uint8, n), "moved": (torch.uint8, n)}
+
+
+class State:
+    """Device state of one k-way partition of a graph (caller-owned buffers).
+
+    `views` may supply every buffer (STATE_FIELDS, sized as state_sizes says),
+    for example slices of one large allocation shared by many instances; the
+    start partition is copied into views["part"]."""
+
+    def __init__(self, g, k, part, views=None):
         dev = g.device
         self.k = int(k)
-        self.part = _dev(part, torch.int32, dev).clone()
-        self.phi = torch.empty(g.m * self.k, dtype=torch.int32, device=dev)
-        self.netstate = torch.empty(hg_netstate_words(g.m, k), dtype=torch.int32, device=dev)
-        self.block_w = torch.empty(self.k, dtype=torch.int64, device=dev)
-        self.km1 = torch.empty(1, dtype=torch.int64, device=dev)
-        self.eligible = torch.ones(g.n, dtype=torch.uint8, device=dev)
-        self.moved = torch.zeros(g.n, dtype=torch.uint8, device=dev)
+        sizes = state_sizes(g.n, g.m, self.k)
+        if views is None:
+            views = {f: torch.empty(cnt, dtype=dt, device=dev) for f, (dt, cnt) in sizes.items()}
+        for f, (dt, cnt) in sizes.items():
+            t = views[f]
+            if t.dtype != dt or t.numel() != cnt or not t.is_contiguous():
+                raise ValueError("state buffer %s must be %d contiguous %s" % (f, cnt, dt))
+            setattr(self, f, t)
+        self.part.copy_(_dev(part, torch.int32, dev))
+        self.eligible.fill_(1)
+        self.moved.zero_()
 
 
 def hg_compute_pincounts(g, st, stream=None):
