@@ -342,6 +342,104 @@ hg_status hg_batch_autotune(hg_batch b, int32_t* part_save, int64_t save_elems,
  * the built-in defaults. */
 hg_status hg_batch_get_schedule(hg_batch b, hg_schedule* sched);
 
+/* ------------------------------------------------------------------ serving
+ * A request server.  Refinement jobs arrive over time.  Each is admitted
+ * into a caller-provided device arena once its exact footprint
+ * (hg_request_bytes) fits, in arrival order.  Admitted jobs are loaded (copied
+ * in, checked, incidence built) on their own stream and host thread, then
+ * advanced together one label-propagation round per step in batched launches:
+ * continuous batching, where a job joins at the next step after its load and
+ * leaves after its last round, and its partition state stays in device memory
+ * in between.  Every result is bit-identical to hg_refine on the job alone.
+ * The server keeps two host threads (loader and executor) and two streams of
+ * default priority; it allocates no device memory. */
+
+typedef struct hg_server_s* hg_server;
+
+/* One refinement job.  Every array is HOST memory and must stay valid until
+ * the job is done; page-locked memory (hipHostMalloc) lets the copies run
+ * asynchronously, pageable memory makes them block the server's threads. */
+typedef struct {
+  int32_t n, m;
+  int64_t P;
+  const int64_t* eptr;        /* [m+1] net CSR offsets                          */
+  const int32_t* pins;        /* [P]                                            */
+  const int32_t* vwgt;        /* [n] or NULL (unit)                             */
+  const int32_t* ewgt;        /* [m] or NULL (unit)                             */
+  const int32_t* part;        /* [n] start partition, ids in [0,k)              */
+  int32_t k;                  /* 2..256                                         */
+  int32_t rounds;             /* label-propagation rounds, 1..1024              */
+  double eps;                 /* 0 < eps < 1                                    */
+  int32_t* part_out;          /* OUT [n] final partition, or NULL               */
+  hg_round_stats* stats_out;  /* OUT [rounds] round records, or NULL            */
+  int64_t* km1_out;           /* OUT [1] final km1, or NULL                     */
+  double arrival_ms;          /* scheduled arrival on the server clock (latency
+                                 is measured from it, not from the submit)      */
+} hg_request;
+
+#define HG_REQ_PENDING 0      /* waiting for memory or a slot                   */
+#define HG_REQ_ADMITTED 1     /* memory reserved, being loaded                  */
+#define HG_REQ_ACTIVE 2       /* loaded, in the batch                           */
+#define HG_REQ_DONE 3         /* finished (status says how)                     */
+
+typedef struct {
+  int32_t state;              /* HG_REQ_*                                       */
+  int32_t status;             /* HG_OK, or the error that ended the job         */
+  double arrival_ms;          /* server clock, milliseconds since creation      */
+  double admit_ms;            /* memory reserved                                */
+  double loaded_ms;           /* loaded and checked                             */
+  double done_ms;             /* its last result copy finished on the GPU       */
+  int64_t footprint;          /* device bytes held while admitted               */
+  int64_t first_step;         /* server step of its first round                 */
+} hg_request_info;
+
+typedef struct {
+  int64_t submitted, completed, failed;
+  int64_t steps;              /* batched rounds launched                        */
+  int64_t member_rounds;      /* sum over steps of the members in the step      */
+  int64_t pin_rounds;         /* sum over steps of the members' pin counts      */
+  int64_t max_members;        /* most members in one step                       */
+  int64_t rebuilds;           /* work-table rebuilds (membership changes)       */
+  int64_t peak_bytes;         /* most arena bytes held by admitted jobs         */
+} hg_server_stats;
+
+/* Device bytes a job of this shape holds while admitted: its net CSR,
+ * incidence CSR, workspace (hg_workspace_size with k_max = k), partition
+ * state (part, Phi, net state, block weights, km1, eligible flags) and round
+ * records, each 256-byte aligned.  0 for unsupported sizes. */
+size_t hg_request_bytes(int32_t n, int32_t m, int64_t P, int32_t k, int32_t rounds,
+                        int32_t weighted_vertices, int32_t weighted_nets);
+
+/* Start a server on device memory [arena, arena + arena_bytes): the first
+ * table_bytes hold the batched work tables (two halves, alternately
+ * rebuilt), the rest is the jobs' memory.  At most max_active jobs are
+ * admitted at once.  sched: HG_SIZE_CLASSES schedules or NULL (defaults).
+ * The current device at the call is the server's device. */
+hg_status hg_server_create(void* arena, size_t arena_bytes, size_t table_bytes,
+                           int32_t max_active, const hg_schedule* sched, hg_server* out);
+
+/* Queue a job (copied; its arrays are read later).  Checks the arguments on
+ * the host; a job whose footprint exceeds the job memory ends with
+ * HG_ERR_WORKSPACE, one whose arrays fail the load checks with
+ * HG_ERR_INVALID or HG_ERR_UNSUPPORTED (see hg_server_info).  *id numbers
+ * the jobs 0, 1, 2, ... in submission order.  Thread-safe. */
+hg_status hg_server_submit(hg_server s, const hg_request* r, int64_t* id);
+
+/* Milliseconds since hg_server_create on the server clock. */
+double hg_server_now_ms(hg_server s);
+
+/* State and timestamps of job `id`. */
+hg_status hg_server_info(hg_server s, int64_t id, hg_request_info* out);
+
+/* Wait until every submitted job is done or timeout_ms passed (< 0: no
+ * limit); *outstanding (may be NULL) receives the number not yet done. */
+hg_status hg_server_drain(hg_server s, double timeout_ms, int64_t* outstanding);
+
+hg_status hg_server_get_stats(hg_server s, hg_server_stats* out);
+
+/* Finish every submitted job, stop the threads, release host resources. */
+void hg_server_free(hg_server s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,10 +1,11 @@
-// hg_batch.hip -- batches of independent refinements (hg_batch_* in hgref.h).
+// hg_batch.hip -- batches of independent refinements (hg_batch_* in hgref.h)
+// and the work-table builder they share with the request server.
 //
 // A batch is a set of members (loaded hypergraph + partition state).  The
 // host builds one work table per kernel launch of a round (and of the
 // pin-count pass that starts a refinement), copies the tables and the
-// members' descriptors into the caller's device table buffer once, and then
-// every round is the same dozen launches whatever the number of members.
+// members' descriptors into a device table buffer, and then every round is
+// the same dozen launches whatever the number of members.
 //
 // Placement: the sweeps (select, finalize, pin counts, block weights) keep a
 // member on one XCD -- members are assigned to the eight XCDs by longest
@@ -20,43 +21,24 @@
 #include <new>
 #include <vector>
 
-#include "hg_internal.h"
-#include "hg_lp.h"
+#include "hg_batch.h"
 
 namespace hg {
-namespace {
-
-constexpr int kMaxScheduleChunks = 64;
-constexpr int kHeavyPerGroup = kBlock / kWave;   // heavy vertices per select workgroup
 
 const hg_schedule kDefaultSchedule[HG_SIZE_CLASSES] = {
     {1, 1, 1, 0}, {2, 2, 2, 0}, {4, 4, 4, 0}, {8, 8, 8, 0}};
 
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+namespace {
 
-int size_class(int n) {
-  if (n < (1 << 13)) return 0;
-  if (n < (1 << 16)) return 1;
-  if (n < (1 << 19)) return 2;
-  return 3;
-}
+constexpr int kMaxScheduleChunks = 64;
+constexpr int kHeavyPerGroup = kBlock / kWave;   // heavy vertices per select workgroup
+constexpr size_t kLaunchSlack = 32 * 256;       // 256-byte alignment of every launch's table
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 long long ceil_div(long long a, long long b) { return (a + b - 1) / b; }
 
 int net_lanes(int k, int want) { return want > group_lanes(k) ? want : group_lanes(k); }
-
-bool valid_schedule(const hg_schedule& s) {
-  auto chunks_ok = [](int c) { return c >= 1 && c <= kMaxScheduleChunks; };
-  const int l = s.net_lanes;
-  return chunks_ok(s.select_chunks) && chunks_ok(s.finalize_chunks) &&
-         chunks_ok(s.count_chunks) && (l == 0 || l == 4 || l == 8 || l == 16 || l == 32);
-}
-
-struct Member {
-  hg_instance in;
-  long long lmax;
-  int cls;
-};
 
 // Work items of one launch, queued per XCD (split) or in one list.
 struct KindItems {
@@ -98,61 +80,50 @@ void add_split(KindItems& kind, int inst, long long units, int per, int xcd) {
 }
 
 }  // namespace
-}  // namespace hg
 
-struct hg_batch_s {
-  std::vector<hg::Member> members;
-  hg_schedule sched[HG_SIZE_CLASSES];
-  char* table = nullptr;        // device
-  size_t table_bytes = 0;
-  char* host = nullptr;         // pinned staging copy of the table
-  size_t host_bytes = 0;
-  hipEvent_t copied = nullptr;  // the last table copy
-  bool copy_pending = false;
-  hg::RoundPlan round;
-  hg::CountPlan counts;
-  unsigned long long table_gen = 0;
-  void* graph_exec = nullptr;
-  void* cap_stream = nullptr;
-  int graph_rounds = -1;
-  unsigned long long graph_gen = 0;
-};
+int size_class(int n) {
+  if (n < (1 << 13)) return 0;
+  if (n < (1 << 16)) return 1;
+  if (n < (1 << 19)) return 2;
+  return 3;
+}
 
-namespace hg {
-namespace {
+bool valid_schedule(const hg_schedule& s) {
+  auto chunks_ok = [](int c) { return c >= 1 && c <= kMaxScheduleChunks; };
+  const int l = s.net_lanes;
+  return chunks_ok(s.select_chunks) && chunks_ok(s.finalize_chunks) &&
+         chunks_ok(s.count_chunks) && (l == 0 || l == 4 || l == 8 || l == 16 || l == 32);
+}
 
-// Bytes of the tables of a set of members for the worst-case schedule (one
-// chunk per item, 32 lanes per net).
-size_t table_bound(const std::vector<Member>& mem) {
+size_t table_bound(const std::vector<BatchMember>& mem, const std::vector<int>& which) {
   long long items = 0;
-  for (const Member& x : mem) {
-    const hg_graph_s* g = x.in.g;
+  for (int i : which) {
+    const BatchMember& x = mem[i];
+    const hg_graph_s* g = x.g;
     const long long tiles = ceil_div(g->n, kTile);
     items += ceil_div(g->n, kBlock);                                 // select
     items += ceil_div(g->info.heavy_count, kHeavyPerGroup);          // heavy select
-    items += x.in.k;                                                 // per block
+    items += x.k;                                                    // per block
     items += tiles;                                                  // tile sums
-    items += tiles + x.in.k;                                         // approve
+    items += tiles + x.k;                                            // approve
     items += ceil_div(g->m, kFinalChunk);                            // finalize
     items += ceil_div(g->m, kBlock);                                 // pin counts
     items += ceil_div(g->n, kBwChunk);                               // block weights
-    items += 1;                                                      // per member
+    items += 2;                                                      // per member
   }
-  // descriptors, items, and 256-byte alignment of every launch's table
-  return align256(sizeof(InstDesc) * mem.size()) + sizeof(WorkItem) * (size_t)items + 64 * 256;
+  return align256(sizeof(InstDesc) * which.size()) + sizeof(WorkItem) * (size_t)items +
+         kLaunchSlack;
 }
 
-// Build the tables of members `which` (indices into b->members) with
-// schedule `sched`, stage them in pinned memory, copy them to the device
-// table on `s` and fill the plans.
-hg_status build_tables(hg_batch_s* b, const std::vector<int>& which, const hg_schedule* sched,
-                       hipStream_t s, RoundPlan& rp, CountPlan& cp) {
+size_t build_plans(const std::vector<BatchMember>& mem, const std::vector<int>& which,
+                   const hg_schedule* sched, char* dev, char* host, size_t at, size_t cap,
+                   RoundPlan* rp, CountPlan* cp) {
   const int cnt = (int)which.size();
   // XCD placement: longest processing time first on P + n
   std::vector<long long> cost(cnt);
   long long total = 0;
   for (int i = 0; i < cnt; ++i) {
-    const hg_graph_s* g = b->members[which[i]].in.g;
+    const hg_graph_s* g = mem[which[i]].g;
     cost[i] = g->P + g->n;
     total += cost[i];
   }
@@ -174,61 +145,65 @@ hg_status build_tables(hg_batch_s* b, const std::vector<int>& which, const hg_sc
   KindItems heavy, blocks, tiles, approve, inst, verts;
   bool any_heavy = false;
   for (int i = 0; i < cnt; ++i) {
-    const Member& M = b->members[which[i]];
-    hg_graph_s* g = M.in.g;
+    const BatchMember& M = mem[which[i]];
+    hg_graph_s* g = M.g;
     const hg_schedule& S = sched[M.cls];
-    InstDesc d = make_desc(g, M.in.k, M.lmax, M.in.part, M.in.phi, M.in.netstate,
-                           (long long*)M.in.block_w, M.in.eligible, nullptr,
-                           (long long*)M.in.km1, M.in.stats);
+    InstDesc d = make_desc(g, M.k, M.lmax, M.part, M.phi, M.netstate, M.block_w, M.eligible,
+                           nullptr, M.km1, M.stats);
     d.hist_reps = home[i] < 0 ? kHistReplicas : 1;
+    d.round_base = M.round_base;
     descs[i] = d;
-    const int k = M.in.k;
+    const int k = M.k;
     const int G = net_lanes(k, S.net_lanes);
-    add_split(*variant(sel, (void*)select_kernel(k, d.view)), i, ceil_div(g->n, kBlock),
-              S.select_chunks, home[i]);
-    add_split(*variant(fin, (void*)finalize_kernel_g(G)), i, ceil_div(g->m, kFinalChunk),
-              S.finalize_chunks, home[i]);
-    KindItems* p = variant(pc, (void*)pincount_kernel_g(G));
-    add_split(*p, i, ceil_div(g->m, kBlock / G), S.count_chunks * G, home[i]);
-    p->lds = std::max(p->lds, sizeof(int) * (size_t)(kBlock / G) * k);
-    add_split(verts, i, ceil_div(g->n, kBwChunk), 1, home[i]);
-    for (long long h = 0; h < ceil_div(g->info.heavy_count, kHeavyPerGroup); ++h)
-      heavy.flat.push_back(WorkItem{i, (int)h, 1, 1});
-    if (g->info.heavy_count > 0) any_heavy = true;
-    for (int t = 0; t < k; ++t) blocks.flat.push_back(WorkItem{i, t, 1, 1});
-    for (int t = 0; t < d.num_tiles; ++t) tiles.flat.push_back(WorkItem{i, t, 1, 1});
-    for (int t = 0; t < d.num_tiles; ++t) approve.flat.push_back(WorkItem{i, t, 1, 1});
-    for (int t = 0; t < k; ++t) approve.flat.push_back(WorkItem{i, t, -1, 1});
+    if (rp) {
+      add_split(*variant(sel, (void*)select_kernel(k, d.view)), i, ceil_div(g->n, kBlock),
+                S.select_chunks, home[i]);
+      add_split(*variant(fin, (void*)finalize_kernel_g(G)), i, ceil_div(g->m, kFinalChunk),
+                S.finalize_chunks, home[i]);
+      for (long long h = 0; h < ceil_div(g->info.heavy_count, kHeavyPerGroup); ++h)
+        heavy.flat.push_back(WorkItem{i, (int)h, 1, 1});
+      if (g->info.heavy_count > 0) any_heavy = true;
+      for (int t = 0; t < k; ++t) blocks.flat.push_back(WorkItem{i, t, 1, 1});
+      for (int t = 0; t < d.num_tiles; ++t) tiles.flat.push_back(WorkItem{i, t, 1, 1});
+      for (int t = 0; t < d.num_tiles; ++t) approve.flat.push_back(WorkItem{i, t, 1, 1});
+      for (int t = 0; t < k; ++t) approve.flat.push_back(WorkItem{i, t, -1, 1});
+    }
+    if (cp) {
+      KindItems* p = variant(pc, (void*)pincount_kernel_g(G));
+      add_split(*p, i, ceil_div(g->m, kBlock / G), S.count_chunks * G, home[i]);
+      p->lds = std::max(p->lds, sizeof(int) * (size_t)(kBlock / G) * k);
+      add_split(verts, i, ceil_div(g->n, kBwChunk), 1, home[i]);
+    }
     inst.flat.push_back(WorkItem{i, 0, 1, 1});
   }
 
   // serialize: descriptors, then every launch's items (256-byte aligned)
-  if (b->copy_pending) {
-    HG_TRY(hipEventSynchronize(b->copied), "hipEventSynchronize");
-    b->copy_pending = false;
-  }
-  size_t off = align256(sizeof(InstDesc) * cnt);
-  if (off > b->host_bytes) return fail(HG_ERR_WORKSPACE, "batch table too small");
-  memcpy(b->host, descs.data(), sizeof(InstDesc) * cnt);
+  size_t off = align256(at);
+  const size_t desc_at = off;
+  if (off + sizeof(InstDesc) * cnt > cap) return 0;
+  memcpy(host + off, descs.data(), sizeof(InstDesc) * cnt);
+  off += sizeof(InstDesc) * cnt;
   Launch base;
   memset(&base, 0, sizeof(base));
-  base.descs = (const InstDesc*)b->table;
-  auto put = [&](const WorkItem* src, size_t n) -> bool {
-    if (off + sizeof(WorkItem) * n > b->host_bytes) return false;
-    memcpy(b->host + off, src, sizeof(WorkItem) * n);
-    off += sizeof(WorkItem) * n;
-    return true;
-  };
+  base.descs = (const InstDesc*)(dev + desc_at);
   bool ok = true;
+  auto put = [&](const WorkItem* src, size_t n) {
+    if (!ok || off + sizeof(WorkItem) * n > cap) {
+      ok = false;
+      return;
+    }
+    memcpy(host + off, src, sizeof(WorkItem) * n);
+    off += sizeof(WorkItem) * n;
+  };
   auto emit_split = [&](const KindItems& kind, PlanLaunch& pl) {
     off = align256(off);
     Launch L = base;
-    L.items = (const WorkItem*)(b->table + off);
+    L.items = (const WorkItem*)(dev + off);
     L.split = 1;
     size_t run = 0, longest = 0;
     for (int x = 0; x < kNumXcd; ++x) {
       L.xoff[x] = (int)run;
-      ok = ok && put(kind.q[x].data(), kind.q[x].size());
+      put(kind.q[x].data(), kind.q[x].size());
       run += kind.q[x].size();
       longest = std::max(longest, kind.q[x].size());
     }
@@ -241,40 +216,87 @@ hg_status build_tables(hg_batch_s* b, const std::vector<int>& which, const hg_sc
   auto emit_flat = [&](const KindItems& kind, PlanLaunch& pl) {
     off = align256(off);
     Launch L = base;
-    L.items = (const WorkItem*)(b->table + off);
+    L.items = (const WorkItem*)(dev + off);
     L.split = 0;
-    ok = ok && put(kind.flat.data(), kind.flat.size());
+    put(kind.flat.data(), kind.flat.size());
     pl.kernel = kind.kernel;
     pl.grid = (unsigned)kind.flat.size();
     pl.L = L;
   };
-  rp = RoundPlan();
-  cp = CountPlan();
-  for (const KindItems& k : sel) {
-    rp.select.push_back(PlanLaunch());
-    emit_split(k, rp.select.back());
+  if (rp) {
+    *rp = RoundPlan();
+    for (const KindItems& k : sel) {
+      rp->select.push_back(PlanLaunch());
+      emit_split(k, rp->select.back());
+    }
+    if (any_heavy) {
+      rp->heavy.push_back(PlanLaunch());
+      emit_flat(heavy, rp->heavy.back());
+      rp->any_heavy = true;
+    }
+    emit_flat(blocks, rp->blocks);
+    emit_flat(tiles, rp->tiles);
+    emit_flat(approve, rp->approve);
+    for (const KindItems& k : fin) {
+      rp->finalize.push_back(PlanLaunch());
+      emit_split(k, rp->finalize.back());
+    }
+    emit_flat(inst, rp->stats);
   }
-  if (any_heavy) {
-    rp.heavy.push_back(PlanLaunch());
-    emit_flat(heavy, rp.heavy.back());
-    rp.any_heavy = true;
+  if (cp) {
+    *cp = CountPlan();
+    for (const KindItems& k : pc) {
+      cp->pincounts.push_back(PlanLaunch());
+      emit_split(k, cp->pincounts.back());
+    }
+    emit_flat(inst, cp->instances);
+    emit_split(verts, cp->vertices);
   }
-  emit_flat(blocks, rp.blocks);
-  emit_flat(tiles, rp.tiles);
-  emit_flat(approve, rp.approve);
-  for (const KindItems& k : fin) {
-    rp.finalize.push_back(PlanLaunch());
-    emit_split(k, rp.finalize.back());
+  return ok ? off : 0;
+}
+
+}  // namespace hg
+
+struct hg_batch_s {
+  std::vector<hg::BatchMember> members;
+  hg_schedule sched[HG_SIZE_CLASSES];
+  char* table = nullptr;        // device
+  size_t table_bytes = 0;
+  char* host = nullptr;         // pinned staging copy of the table
+  size_t host_bytes = 0;
+  hipEvent_t copied = nullptr;  // the last table copy
+  bool copy_pending = false;
+  hg::RoundPlan round;
+  hg::CountPlan counts;
+  unsigned long long table_gen = 0;
+  void* graph_exec = nullptr;
+  void* cap_stream = nullptr;
+  int graph_rounds = -1;
+  unsigned long long graph_gen = 0;
+};
+
+namespace hg {
+namespace {
+
+std::vector<int> iota_vec(size_t n) {
+  std::vector<int> v(n);
+  for (size_t i = 0; i < n; ++i) v[i] = (int)i;
+  return v;
+}
+
+// Build the tables of members `which` with `sched` and copy them to the
+// batch's device table on `s` (after the previous copy has left the staging
+// buffer).
+hg_status build_tables(hg_batch_s* b, const std::vector<int>& which, const hg_schedule* sched,
+                       hipStream_t s, RoundPlan& rp, CountPlan& cp) {
+  if (b->copy_pending) {
+    HG_TRY(hipEventSynchronize(b->copied), "hipEventSynchronize");
+    b->copy_pending = false;
   }
-  emit_flat(inst, rp.stats);
-  for (const KindItems& k : pc) {
-    cp.pincounts.push_back(PlanLaunch());
-    emit_split(k, cp.pincounts.back());
-  }
-  emit_flat(inst, cp.instances);
-  emit_split(verts, cp.vertices);
-  if (!ok || off > b->table_bytes) return fail(HG_ERR_WORKSPACE, "batch table too small");
-  HG_TRY(hipMemcpyAsync(b->table, b->host, off, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+  const size_t end = build_plans(b->members, which, sched, b->table, b->host, 0,
+                                 std::min(b->host_bytes, b->table_bytes), &rp, &cp);
+  if (end == 0) return fail(HG_ERR_WORKSPACE, "batch table too small");
+  HG_TRY(hipMemcpyAsync(b->table, b->host, end, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
   HG_TRY(hipEventRecord(b->copied, s), "hipEventRecord");
   b->copy_pending = true;
   b->table_gen += 1;
@@ -282,9 +304,7 @@ hg_status build_tables(hg_batch_s* b, const std::vector<int>& which, const hg_sc
 }
 
 hg_status build_all(hg_batch_s* b, hipStream_t s) {
-  std::vector<int> all(b->members.size());
-  for (size_t i = 0; i < all.size(); ++i) all[i] = (int)i;
-  return build_tables(b, all, b->sched, s, b->round, b->counts);
+  return build_tables(b, iota_vec(b->members.size()), b->sched, s, b->round, b->counts);
 }
 
 void drop_graph(hg_batch_s* b) {
@@ -293,14 +313,13 @@ void drop_graph(hg_batch_s* b) {
   b->graph_rounds = -1;
 }
 
-hipError_t enqueue_batch(hg_batch_s* b, const RoundPlan& rp, const CountPlan& cp, int rounds,
-                         hipStream_t s) {
+hipError_t enqueue_batch(const RoundPlan& rp, const CountPlan& cp, int rounds, hipStream_t s) {
   hipError_t e = launch_counts(cp, true, true, s);
   for (int r = 0; r < rounds && e == hipSuccess; ++r) e = launch_round(rp, r, s, nullptr);
   return e;
 }
 
-hg_status check_members(const hg_instance* mem, int count, std::vector<Member>& out) {
+hg_status check_members(const hg_instance* mem, int count, std::vector<BatchMember>& out) {
   if (!mem || count < 1) return fail(HG_ERR_INVALID, "a batch needs at least one member");
   out.resize(count);
   std::vector<const void*> graphs(count);
@@ -308,14 +327,25 @@ hg_status check_members(const hg_instance* mem, int count, std::vector<Member>& 
     const hg_instance& x = mem[i];
     hg_status st = check_k(x.g, x.k);
     if (st != HG_OK) return fail(st, "member %d: %s", i, hg_last_error());
-    if (!(x.eps > 0.0 && x.eps < 1.0)) return fail(HG_ERR_INVALID, "member %d: eps must lie in (0, 1)", i);
+    if (!(x.eps > 0.0 && x.eps < 1.0))
+      return fail(HG_ERR_INVALID, "member %d: eps must lie in (0, 1)", i);
     if (!x.part || !x.phi || !x.netstate || !x.block_w || !x.eligible || !x.stats || !x.km1)
       return fail(HG_ERR_INVALID,
                   "member %d: part, phi, netstate, block_w, eligible, stats and km1 must be "
                   "non-NULL", i);
-    out[i].in = x;
-    out[i].lmax = hg_max_block_weight(x.g, x.k, x.eps);
-    out[i].cls = size_class(x.g->n);
+    BatchMember& M = out[i];
+    M.g = x.g;
+    M.k = x.k;
+    M.cls = size_class(x.g->n);
+    M.round_base = 0;
+    M.lmax = hg_max_block_weight(x.g, x.k, x.eps);
+    M.part = x.part;
+    M.phi = x.phi;
+    M.netstate = x.netstate;
+    M.block_w = (long long*)x.block_w;
+    M.eligible = x.eligible;
+    M.stats = x.stats;
+    M.km1 = (long long*)x.km1;
     graphs[i] = x.g;
   }
   std::sort(graphs.begin(), graphs.end());
@@ -332,9 +362,9 @@ using hg::fail;
 extern "C" {
 
 size_t hg_batch_table_bytes(const hg_instance* members, int32_t count) {
-  std::vector<hg::Member> mem;
+  std::vector<hg::BatchMember> mem;
   if (hg::check_members(members, count, mem) != HG_OK) return 0;
-  return hg::table_bound(mem);
+  return hg::table_bound(mem, hg::iota_vec(mem.size()));
 }
 
 hg_status hg_batch_get_schedule(hg_batch b, hg_schedule* sched) {
@@ -347,14 +377,14 @@ hg_status hg_batch_create(const hg_instance* members, int32_t count, const hg_sc
                           void* table, size_t table_bytes, void* stream, hg_batch* out) {
   if (!out) return fail(HG_ERR_INVALID, "out must be non-NULL");
   *out = nullptr;
-  std::vector<hg::Member> mem;
+  std::vector<hg::BatchMember> mem;
   hg_status st = hg::check_members(members, count, mem);
   if (st != HG_OK) return st;
   if (sched)
     for (int c = 0; c < HG_SIZE_CLASSES; ++c)
       if (!hg::valid_schedule(sched[c]))
         return fail(HG_ERR_INVALID, "schedule of size class %d is out of range", c);
-  const size_t need = hg::table_bound(mem);
+  const size_t need = hg::table_bound(mem, hg::iota_vec(mem.size()));
   if (!table || table_bytes < need)
     return fail(HG_ERR_WORKSPACE, "batch table needs %zu bytes (got %zu)", need, table_bytes);
   hg_batch_s* b = new (std::nothrow) hg_batch_s();
@@ -407,7 +437,7 @@ hg_status hg_batch_refine(hg_batch b, int32_t rounds, int32_t use_graph, void* s
   if (rounds < 0) return fail(HG_ERR_INVALID, "rounds must be >= 0");
   hipStream_t s = (hipStream_t)stream;
   if (!use_graph) {
-    HG_TRY(hg::enqueue_batch(b, b->round, b->counts, rounds, s), "batch refine");
+    HG_TRY(hg::enqueue_batch(b->round, b->counts, rounds, s), "batch refine");
     return HG_OK;
   }
   if (!b->graph_exec || b->graph_rounds != rounds || b->graph_gen != b->table_gen) {
@@ -419,7 +449,7 @@ hg_status hg_batch_refine(hg_batch b, int32_t rounds, int32_t use_graph, void* s
     }
     hipStream_t cs = (hipStream_t)b->cap_stream;
     HG_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-    hipError_t e = hg::enqueue_batch(b, b->round, b->counts, rounds, cs);
+    hipError_t e = hg::enqueue_batch(b->round, b->counts, rounds, cs);
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(cs, &graph);
     if (e != hipSuccess) {
@@ -449,18 +479,18 @@ hg_status hg_batch_autotune(hg_batch b, int32_t* part_save, int64_t save_elems, 
   long long need = 0;
   for (int i = 0; i < cnt; ++i) {
     save_off[i] = need;
-    need += b->members[i].in.g->n;
+    need += b->members[i].g->n;
   }
   if (!part_save || save_elems < need)
     return fail(HG_ERR_WORKSPACE, "part_save needs %lld elements", need);
   for (int i = 0; i < cnt; ++i)
-    HG_TRY(hipMemcpyAsync(part_save + save_off[i], b->members[i].in.part,
-                          sizeof(int32_t) * b->members[i].in.g->n, hipMemcpyDeviceToDevice, s),
+    HG_TRY(hipMemcpyAsync(part_save + save_off[i], b->members[i].part,
+                          sizeof(int32_t) * b->members[i].g->n, hipMemcpyDeviceToDevice, s),
            "hipMemcpyAsync");
   auto restore = [&](const std::vector<int>& which) -> hg_status {
     for (int i : which)
-      HG_TRY(hipMemcpyAsync(b->members[i].in.part, part_save + save_off[i],
-                            sizeof(int32_t) * b->members[i].in.g->n, hipMemcpyDeviceToDevice, s),
+      HG_TRY(hipMemcpyAsync(b->members[i].part, part_save + save_off[i],
+                            sizeof(int32_t) * b->members[i].g->n, hipMemcpyDeviceToDevice, s),
              "hipMemcpyAsync");
     return HG_OK;
   };
@@ -483,7 +513,7 @@ hg_status hg_batch_autotune(hg_batch b, int32_t* part_save, int64_t save_elems, 
     for (int rep = 0; rep < repeats; ++rep) {
       if ((r = restore(which)) != HG_OK) return r;
       HG_TRY(hipEventRecord(ev[0], s), "hipEventRecord");
-      HG_TRY(hg::enqueue_batch(b, rp, cp, 1, s), "tuning trial");
+      HG_TRY(hg::enqueue_batch(rp, cp, 1, s), "tuning trial");
       HG_TRY(hipEventRecord(ev[1], s), "hipEventRecord");
       HG_TRY(hipEventSynchronize(ev[1]), "hipEventSynchronize");
       float ms = 0.0f;
@@ -520,11 +550,7 @@ hg_status hg_batch_autotune(hg_batch b, int32_t* part_save, int64_t save_elems, 
       *slot = best_v;
     }
   }
-  if (st == HG_OK) {
-    std::vector<int> all(cnt);
-    for (int i = 0; i < cnt; ++i) all[i] = i;
-    st = restore(all);
-  }
+  if (st == HG_OK) st = restore(hg::iota_vec(cnt));
   if (st == HG_OK) {
     memcpy(b->sched, cur, sizeof(cur));
     st = hg::build_all(b, s);

@@ -98,6 +98,8 @@ struct InstDesc {
   int cmax, lds_buckets, heavy_count, num_tiles;
   int hist_stride;               // k_max * kBuckets: distance between histogram replicas
   int hist_reps;                 // histogram replicas in use (workgroup b adds to b % hist_reps)
+  int round_base;                // round r's record goes to stats[r - round_base]
+  int pad1;
   long long P, lmax;
   const long long* eptr;
   const int* pins;

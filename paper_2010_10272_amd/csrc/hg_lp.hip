@@ -811,7 +811,7 @@ __global__ __launch_bounds__(kBlock) void k_round_stats(Launch L) {
     st.km1_after = *D.km1 - st.km1_delta;
     st.max_block_weight = m;
     *D.km1 = st.km1_after;
-    D.stats[L.round] = st;
+    D.stats[L.round - D.round_base] = st;
     ctr->any_overflow = 0;
   }
 }

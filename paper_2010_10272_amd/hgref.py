@@ -58,6 +58,31 @@ class HgSchedule(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int32) for f in SCHEDULE_FIELDS]
 
 
+class HgRequest(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("P", ctypes.c_int64),
+                ("eptr", ctypes.c_void_p), ("pins", ctypes.c_void_p), ("vwgt", ctypes.c_void_p),
+                ("ewgt", ctypes.c_void_p), ("part", ctypes.c_void_p), ("k", ctypes.c_int32),
+                ("rounds", ctypes.c_int32), ("eps", ctypes.c_double),
+                ("part_out", ctypes.c_void_p), ("stats_out", ctypes.c_void_p),
+                ("km1_out", ctypes.c_void_p), ("arrival_ms", ctypes.c_double)]
+
+
+class HgRequestInfo(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("arrival_ms", ctypes.c_double), ("admit_ms", ctypes.c_double),
+                ("loaded_ms", ctypes.c_double), ("done_ms", ctypes.c_double),
+                ("footprint", ctypes.c_int64), ("first_step", ctypes.c_int64)]
+
+
+class HgServerStats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in (
+        "submitted", "completed", "failed", "steps", "member_rounds", "pin_rounds",
+        "max_members", "rebuilds", "peak_bytes")]
+
+
+HG_REQ_PENDING, HG_REQ_ADMITTED, HG_REQ_ACTIVE, HG_REQ_DONE = 0, 1, 2, 3
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libhgref.so not built (run __graft_entry__.build() or "
@@ -114,6 +139,22 @@ def _load():
     lib.hg_batch_autotune.restype = i32
     lib.hg_batch_get_schedule.argtypes = [vp, sched_p]
     lib.hg_batch_get_schedule.restype = i32
+    lib.hg_request_bytes.argtypes = [i32, i32, i64, i32, i32, i32, i32]
+    lib.hg_request_bytes.restype = sz
+    lib.hg_server_create.argtypes = [vp, sz, sz, i32, sched_p, ctypes.POINTER(vp)]
+    lib.hg_server_create.restype = i32
+    lib.hg_server_submit.argtypes = [vp, ctypes.POINTER(HgRequest), ctypes.POINTER(i64)]
+    lib.hg_server_submit.restype = i32
+    lib.hg_server_now_ms.argtypes = [vp]
+    lib.hg_server_now_ms.restype = dbl
+    lib.hg_server_info.argtypes = [vp, i64, ctypes.POINTER(HgRequestInfo)]
+    lib.hg_server_info.restype = i32
+    lib.hg_server_drain.argtypes = [vp, dbl, ctypes.POINTER(i64)]
+    lib.hg_server_drain.restype = i32
+    lib.hg_server_get_stats.argtypes = [vp, ctypes.POINTER(HgServerStats)]
+    lib.hg_server_get_stats.restype = i32
+    lib.hg_server_free.argtypes = [vp]
+    lib.hg_server_free.restype = None
     lib.hg_last_error.argtypes = []
     lib.hg_last_error.restype = ctypes.c_char_p
     return lib
@@ -465,3 +506,139 @@ def hg_batch_get_schedule(b=None):
 
 def hg_batch_free(b):
     b.free()
+
+
+# ---------------------------------------------------------------- serving
+
+def hg_request_bytes(n, m, P, k, rounds, weighted_vertices=False, weighted_nets=False):
+    return int(_lib.hg_request_bytes(int(n), int(m), int(P), int(k), int(rounds),
+                                     1 if weighted_vertices else 0, 1 if weighted_nets else 0))
+
+
+def _host(x, dtype):
+    """A contiguous CPU tensor of `dtype` (page-locked if it already is)."""
+    if x is None:
+        return None
+    if isinstance(x, torch.Tensor):
+        t = x.to(dtype=dtype)
+        if t.is_cuda:
+            raise ValueError("request arrays live in host memory")
+        return t.contiguous()
+    return torch.as_tensor(x).to(dtype=dtype).contiguous()
+
+
+class Server:
+    """A request server on an arena tensor it owns (see hg_server_create).
+    Jobs keep their host arrays and page-locked result buffers here until
+    they are done."""
+
+    def __init__(self, arena_bytes, table_bytes=64 << 20, max_active=256, sched=None,
+                 device="cuda"):
+        self.device = torch.device(device)
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(_lib.hg_server_create(_ptr(self.arena), int(arena_bytes), int(table_bytes),
+                                         int(max_active), _schedule_c(sched), ctypes.byref(h)))
+        self._h = h
+        self.jobs = {}
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("server already freed")
+        return self._h
+
+    def free(self, timeout_ms=120000.0):
+        """Wait (up to timeout_ms) for every job, then stop the server.  Raises
+        and keeps the server if jobs are still outstanding."""
+        if self._h is not None:
+            left = hg_server_drain(self, timeout_ms)
+            if left:
+                raise HgError(HG_ERR_DEVICE, "%d jobs still outstanding" % left)
+            _lib.hg_server_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free(timeout_ms=0.0)
+        except Exception:
+            pass
+
+
+def hg_server_create(arena_bytes, table_bytes=64 << 20, max_active=256, sched=None,
+                     device="cuda"):
+    return Server(arena_bytes, table_bytes, max_active, sched, device)
+
+
+def hg_server_submit(srv, n, eptr, pins, part, k, rounds, eps, vwgt=None, ewgt=None,
+                     arrival_ms=None, results=True):
+    """Queue one job; arrays are host arrays or CPU tensors (page-locked ones
+    avoid blocking copies).  With results=True the final partition, round
+    records and km1 come back into page-locked tensors (see hg_server_result).
+    Returns the job id."""
+    eptr = _host(eptr, torch.int64)
+    pins = _host(pins, torch.int32)
+    part = _host(part, torch.int32)
+    vwgt = _host(vwgt, torch.int32)
+    ewgt = _host(ewgt, torch.int32)
+    m = int(eptr.numel() - 1)
+    P = int(pins.numel())
+    out = None
+    if results:
+        out = (torch.empty(int(n), dtype=torch.int32, pin_memory=True),
+               torch.zeros(int(rounds) * STATS_WORDS, dtype=torch.int64, pin_memory=True),
+               torch.zeros(1, dtype=torch.int64, pin_memory=True))
+    ptr = (lambda t: None if t is None else t.data_ptr())
+    req = HgRequest(int(n), m, P, ptr(eptr), ptr(pins), ptr(vwgt), ptr(ewgt), ptr(part), int(k),
+                    int(rounds), float(eps), ptr(out[0]) if out else None,
+                    ptr(out[1]) if out else None, ptr(out[2]) if out else None,
+                    float(arrival_ms) if arrival_ms is not None else hg_server_now_ms(srv))
+    jid = ctypes.c_int64(-1)
+    _check(_lib.hg_server_submit(srv.handle, ctypes.byref(req), ctypes.byref(jid)))
+    srv.jobs[int(jid.value)] = (eptr, pins, part, vwgt, ewgt, out)
+    return int(jid.value)
+
+
+def hg_server_now_ms(srv):
+    return float(_lib.hg_server_now_ms(srv.handle))
+
+
+def hg_server_info(srv, jid):
+    info = HgRequestInfo()
+    rc = _lib.hg_server_info(srv.handle, int(jid), ctypes.byref(info))
+    _check(rc)
+    d = {f: getattr(info, f) for f, _ in HgRequestInfo._fields_}
+    if d["status"] != HG_OK:
+        d["message"] = _lib.hg_last_error().decode(errors="replace")
+    return d
+
+
+def hg_server_result(srv, jid):
+    """(part, round records as dicts, km1) of a finished job (host tensors)."""
+    out = srv.jobs[int(jid)][5]
+    if out is None:
+        return None
+    return out[0], stats_to_dicts(out[1]), int(out[2].item())
+
+
+def hg_server_drain(srv, timeout_ms=-1.0):
+    """Wait for every submitted job; returns how many are still outstanding."""
+    left = ctypes.c_int64(0)
+    _check(_lib.hg_server_drain(srv.handle, float(timeout_ms), ctypes.byref(left)))
+    return int(left.value)
+
+
+def hg_server_get_stats(srv):
+    st = HgServerStats()
+    _check(_lib.hg_server_get_stats(srv.handle, ctypes.byref(st)))
+    return {f: int(getattr(st, f)) for f, _ in HgServerStats._fields_}
+
+
+def hg_server_release(srv, jid):
+    """Drop the host arrays and results kept for a finished job."""
+    srv.jobs.pop(int(jid), None)
+
+
+def hg_server_free(srv):
+    srv.free()
