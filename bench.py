@@ -228,6 +228,144 @@ def batched_leg(args, H, dev):
     return out
 
 
+SERVED_RATE = 200.0
+SERVED_BUDGET = 16 << 30      # job memory of the server (admission binds under bursts)
+SERVED_TABLE = 64 << 20
+
+
+def _sleep_until(clock, due_ms):
+    while True:
+        left = due_ms - clock()
+        if left <= 0:
+            return
+        time.sleep(left / 1e3 if left > 1.0 else 0)
+
+
+def _lat_summary(lat_ms, pin_rounds, t_first, t_last):
+    span = (t_last - t_first) / 1e3
+    return {"requests": len(lat_ms), "p50_ms": percentile(lat_ms, 50),
+            "p99_ms": percentile(lat_ms, 99), "max_ms": max(lat_ms) if lat_ms else None,
+            "mean_ms": sum(lat_ms) / max(1, len(lat_ms)), "makespan_s": span,
+            "value": pin_rounds / span if span > 0 else None, "unit": "pins/s"}
+
+
+def served_leg(args, H, dev):
+    """The served workload: an open-loop Poisson trace (200 requests/s; 95%
+    hypergraphs of the batched size distribution, 5% 2M-cell grid netlists;
+    k in {2,4,8,32,128}; 10 rounds each) against the request server (16 GB of
+    job memory) and against the plain one-at-a-time path (load, hg_refine,
+    copy back, per request in arrival order).  Latency = completion minus
+    scheduled arrival.  Then the same requests all at once (a burst) for the
+    throughput each path sustains.  Every served result is checked against the
+    plain path's."""
+    import numpy as np
+    import torch
+    import synth
+    print("served: generating the request pool ...", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    trace = synth.served_trace(seed=5, rate=SERVED_RATE, seconds=args.served_seconds)
+    small, big = synth.served_pool(seed=5, workers=8)
+    gen_s = time.perf_counter() - t0
+
+    def pinned(a, dt):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(dt).pin_memory()
+
+    hosts = {}
+
+    def host_of(req):
+        key = (req.big, req.pool)
+        if key not in hosts:
+            inst = (big if req.big else small)[req.pool]
+            unit_c = bool(np.all(inst.c == 1))
+            unit_w = bool(np.all(inst.w == 1))
+            hosts[key] = {"inst": inst, "eptr": pinned(inst.eptr, torch.int64),
+                          "pins": pinned(inst.pins, torch.int32),
+                          "vwgt": None if unit_c else pinned(inst.c, torch.int32),
+                          "ewgt": None if unit_w else pinned(inst.w, torch.int32), "parts": {}}
+        h = hosts[key]
+        if req.k not in h["parts"]:
+            h["parts"][req.k] = pinned(synth.with_k(h["inst"], req.k).part, torch.int32)
+        return h
+
+    def outputs(n, rounds):
+        return (torch.empty(n, dtype=torch.int32, pin_memory=True),
+                torch.zeros(rounds * H.STATS_WORDS, dtype=torch.int64, pin_memory=True),
+                torch.zeros(1, dtype=torch.int64, pin_memory=True))
+
+    reqs = [(r, host_of(r)) for r in trace]
+    pin_rounds = sum(h["inst"].P * r.rounds for r, h in reqs)
+    print("served: %d requests (%d big), %.2e pin-rounds" % (
+        len(reqs), sum(r.big for r in trace), pin_rounds), file=sys.stderr, flush=True)
+
+    def run_served(burst):
+        outs = [outputs(h["inst"].n, r.rounds) for r, h in reqs]
+        srv = H.hg_server_create(SERVED_BUDGET + SERVED_TABLE, table_bytes=SERVED_TABLE,
+                                 max_active=256, device=dev)
+        clock = lambda: H.hg_server_now_ms(srv)          # noqa: E731
+        start = clock() + 20.0
+        ids = []
+        for (r, h), out in zip(reqs, outs):
+            due = start if burst else start + r.arrival_s * 1e3
+            if not burst:
+                _sleep_until(clock, due)
+            inst = h["inst"]
+            ids.append(H.hg_server_submit(srv, inst.n, h["eptr"], h["pins"], h["parts"][r.k],
+                                          r.k, r.rounds, r.eps, vwgt=h["vwgt"], ewgt=h["ewgt"],
+                                          arrival_ms=due, results=out))
+        left = H.hg_server_drain(srv, max(120.0, 6 * args.served_seconds) * 1e3)
+        assert left == 0, "server did not finish"
+        infos = [H.hg_server_info(srv, i) for i in ids]
+        assert all(x["status"] == H.HG_OK for x in infos), "a served request failed"
+        lat = [x["done_ms"] - x["arrival_ms"] for x in infos]
+        res = _lat_summary(lat, pin_rounds, start, max(x["done_ms"] for x in infos))
+        res["server"] = H.hg_server_get_stats(srv)
+        srv.free()
+        return res, outs
+
+    def run_plain(burst):
+        outs = [outputs(h["inst"].n, r.rounds) for r, h in reqs]
+        clock = lambda: time.perf_counter() * 1e3        # noqa: E731
+        start = clock() + 20.0
+        lat, t_last = [], start
+        stats = torch.zeros(16 * H.STATS_WORDS, dtype=torch.int64, device=dev)
+        for (r, h), out in zip(reqs, outs):
+            due = start if burst else start + r.arrival_s * 1e3
+            if not burst:
+                _sleep_until(clock, due)
+            inst = h["inst"]
+            g = H.hg_load_csr(inst.n, h["eptr"], h["pins"], h["vwgt"], h["ewgt"], k_max=r.k,
+                              device=dev)
+            st = H.State(g, r.k, h["parts"][r.k])
+            H.hg_refine(g, st, r.eps, r.rounds, stats, use_graph=False)
+            out[0].copy_(st.part, non_blocking=True)
+            out[1].copy_(stats[:r.rounds * H.STATS_WORDS], non_blocking=True)
+            out[2].copy_(st.km1, non_blocking=True)
+            torch.cuda.synchronize()
+            t_last = clock()
+            lat.append(t_last - due)
+            g.free()
+        return _lat_summary(lat, pin_rounds, start, t_last), outs
+
+    res = {"rate_per_s": SERVED_RATE, "seconds": args.served_seconds, "requests": len(reqs),
+           "big_requests": sum(r.big for r in trace), "pin_rounds": pin_rounds,
+           "job_memory_bytes": SERVED_BUDGET, "generate_s": gen_s,
+           "pool": {"small": len(small), "big": len(big)}}
+    for mode in ("open_loop", "burst"):
+        burst = mode == "burst"
+        print("served: %s, server ..." % mode, file=sys.stderr, flush=True)
+        srv_res, srv_out = run_served(burst)
+        print("served: %s, plain one-at-a-time ..." % mode, file=sys.stderr, flush=True)
+        pl_res, pl_out = run_plain(burst)
+        for (r, h), a, b in zip(reqs, srv_out, pl_out):
+            n = h["inst"].n
+            assert torch.equal(a[0][:n], b[0][:n]), "served partition differs from plain"
+            assert torch.equal(a[1], b[1]) and torch.equal(a[2], b[2]), "served stats differ"
+        res[mode] = {"served": srv_res, "plain": pl_res}
+    res["check"] = ("every served request's partition, round records and km1 identical to the "
+                    "plain one-at-a-time path, in both modes")
+    return res
+
+
 def plain_leg(args, H, dev):
     """The plain workload (module docstring): returns the JSON record."""
     import torch
@@ -397,8 +535,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-rounds", type=int, default=4)
     ap.add_argument("--latency-reps", type=int, default=5)
-    ap.add_argument("--legs", default="plain,batched",
-                    help="comma list of plain, batched")
+    ap.add_argument("--legs", default="plain,batched,served",
+                    help="comma list of plain, batched, served")
+    ap.add_argument("--served-seconds", type=float, default=10.0,
+                    help="length of the open-loop request trace")
     ap.add_argument("--batch-count", type=int, default=BATCH_COUNT)
     ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--batch-cpu-s", type=float, default=8.0)
@@ -423,6 +563,9 @@ def main():
     if "batched" in legs:
         torch.cuda.empty_cache()
         out["batched"] = batched_leg(args, H, dev)
+    if "served" in legs:
+        torch.cuda.empty_cache()
+        out["served"] = served_leg(args, H, dev)
     print(json.dumps(out), flush=True)
 
 

@@ -575,8 +575,9 @@ def hg_server_submit(srv, n, eptr, pins, part, k, rounds, eps, vwgt=None, ewgt=N
                      arrival_ms=None, results=True):
     """Queue one job; arrays are host arrays or CPU tensors (page-locked ones
     avoid blocking copies).  With results=True the final partition, round
-    records and km1 come back into page-locked tensors (see hg_server_result).
-    Returns the job id."""
+    records and km1 come back into new page-locked tensors, with a tuple
+    (part, stats, km1) into the caller's (see hg_server_result).  Returns the
+    job id."""
     eptr = _host(eptr, torch.int64)
     pins = _host(pins, torch.int32)
     part = _host(part, torch.int32)
@@ -585,7 +586,12 @@ def hg_server_submit(srv, n, eptr, pins, part, k, rounds, eps, vwgt=None, ewgt=N
     m = int(eptr.numel() - 1)
     P = int(pins.numel())
     out = None
-    if results:
+    if isinstance(results, (tuple, list)):
+        out = tuple(results)          # caller's (part, stats, km1) host tensors
+        if (out[0].numel() < int(n) or out[1].numel() < int(rounds) * STATS_WORDS
+                or out[2].numel() < 1):
+            raise ValueError("result buffers too small")
+    elif results:
         out = (torch.empty(int(n), dtype=torch.int32, pin_memory=True),
                torch.zeros(int(rounds) * STATS_WORDS, dtype=torch.int64, pin_memory=True),
                torch.zeros(1, dtype=torch.int64, pin_memory=True))
@@ -619,7 +625,8 @@ def hg_server_result(srv, jid):
     out = srv.jobs[int(jid)][5]
     if out is None:
         return None
-    return out[0], stats_to_dicts(out[1]), int(out[2].item())
+    n = srv.jobs[int(jid)][2].numel()
+    return out[0][:n], stats_to_dicts(out[1]), int(out[2][0].item())
 
 
 def hg_server_drain(srv, timeout_ms=-1.0):

@@ -114,6 +114,7 @@ def random_power_law(seed, n, m, k, lo=2, hi=64, unit=True, rounds=5, eps=0.03,
     pins = _distinct_within_nets(rng, eptr, lambda r, nets: r.integers(0, n, nets.shape[0]))
     perm = rng.permutation(n)
     part = (perm % k).astype(np.int32)
+    meta = {"seed": seed, "perm": perm}
     if unit:
         c = np.ones(n, np.int32)
         w = np.ones(m, np.int32)
@@ -121,7 +122,7 @@ def random_power_law(seed, n, m, k, lo=2, hi=64, unit=True, rounds=5, eps=0.03,
         c = rng.integers(1, 9, n).astype(np.int32)
         w = rng.integers(1, 5, m).astype(np.int32)
     return Instance(name or "powerlaw-n%d-m%d-k%d" % (n, m, k), n, eptr, pins, c, w, part,
-                    k, eps, rounds, {"seed": seed})
+                    k, eps, rounds, meta)
 
 
 def tiny_plain(seed=1):
@@ -170,10 +171,15 @@ def sparse_matrix(k, seed=2, rows=1_000_000, cols=1_000_000, band=5_000, rounds=
 
 
 def with_k(inst, k):
-    """The same hypergraph with the start partition perm[v] mod k (for the
-    instances whose start is drawn as a random permutation)."""
-    perm = inst.meta["perm"]
-    part = (perm % k).astype(np.int32)
+    """The same hypergraph with its start partition for k blocks: perm[v] mod
+    k for the instances whose start is a random permutation, horizontal
+    strips floor(y * k / height) for the grid netlists."""
+    if "perm" in inst.meta:
+        part = (inst.meta["perm"] % k).astype(np.int32)
+    else:
+        side, height = inst.meta["side"], inst.meta["height"]
+        y = np.arange(inst.n, dtype=np.int64) // side
+        part = (y * k // height).astype(np.int32)
     name = inst.name.rsplit("-k", 1)[0] + "-k%d" % k
     return Instance(name, inst.n, inst.eptr, inst.pins, inst.c, inst.w, part, k, inst.eps,
                     inst.rounds, dict(inst.meta))
@@ -236,7 +242,7 @@ def vlsi_grid(seed=3, side=2000, height=2000, m=4_200_000, k=16, rounds=10):
     y = np.arange(n, dtype=np.int64) // side
     part = (y * k // height).astype(np.int32)
     return Instance("vlsi-%dx%d-m%d-k%d" % (side, height, m, k), n, eptr, pins, c, w, part,
-                    k, 0.03, rounds, {"seed": seed})
+                    k, 0.03, rounds, {"seed": seed, "side": side, "height": height})
 
 
 def _batch_member(args):
@@ -270,6 +276,67 @@ def batch_instances(seed=4, count=512, n_lo=1_000, n_hi=500_000, ks=(2, 4, 8, 32
         with ProcessPoolExecutor(workers, mp_context=mp.get_context("fork")) as ex:
             return list(ex.map(_batch_member, args, chunksize=4))
     return [_batch_member(a) for a in args]
+
+
+@dataclass
+class Request:
+    """One job of a served trace: its scheduled arrival, the pool instance it
+    refines and its k (the start partition is the instance's for that k)."""
+    arrival_s: float
+    big: bool
+    pool: int
+    k: int
+    rounds: int
+    eps: float = 0.03
+
+
+def served_trace(seed=5, rate=200.0, seconds=60.0, big_prob=0.05, ks=(2, 4, 8, 32, 128),
+                 rounds=10, small_pool=256, big_pool=2):
+    """Open-loop request trace: Poisson arrivals at `rate` per second for
+    `seconds`; each request is w.p. `big_prob` a grid netlist with n = 2M
+    (2000 x 1000 cells, m = 2.1M) and otherwise a hypergraph of the batched
+    workload's size distribution; k uniform over `ks`; `rounds` rounds.
+
+    Draw order (one generator seeded with `seed`): inter-arrival gaps
+    Exp(1/rate) until the horizon; then per request a U(0,1) for big-vs-small,
+    a pool index and an index into `ks`.  Requests refine instances from a
+    pool (`small_pool` of the batched distribution, seed + 1; `big_pool`
+    netlists, seeds seed + 2, ...), so a trace of thousands of requests needs
+    only a few hundred distinct hypergraphs; see served_pool.
+    """
+    rng = np.random.default_rng(seed)
+    gaps = []
+    t = 0.0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= seconds:
+            break
+        gaps.append(t)
+    cnt = len(gaps)
+    big = rng.random(cnt) < big_prob
+    small_idx = rng.integers(0, small_pool, cnt)
+    big_idx = rng.integers(0, big_pool, cnt)
+    kidx = rng.integers(0, len(ks), cnt)
+    return [Request(gaps[i], bool(big[i]), int(big_idx[i] if big[i] else small_idx[i]),
+                    int(ks[kidx[i]]), rounds) for i in range(cnt)]
+
+
+def served_pool(seed=5, small_pool=256, big_pool=2, workers=1):
+    """The instances a served trace draws from: (small, big) lists."""
+    small = batch_instances(seed=seed + 1, count=small_pool, rounds=10, workers=workers)
+    seeds = [seed + 2 + i for i in range(big_pool)]
+    if workers > 1 and big_pool > 1:
+        from concurrent.futures import ProcessPoolExecutor
+        import multiprocessing as mp
+        with ProcessPoolExecutor(min(workers, big_pool), mp_context=mp.get_context("fork")) as ex:
+            big = list(ex.map(_big_netlist, seeds))
+    else:
+        big = [_big_netlist(s) for s in seeds]
+    return small, big
+
+
+def _big_netlist(seed):
+    return vlsi_grid(seed=seed, side=2000, height=1000, m=2_100_000, k=16, rounds=10)
 
 
 def describe(inst):
