@@ -48,6 +48,33 @@ def select_bytes(st, n, k):
             16.0 * st["candidates"])
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "plain_sparse_matrix_traffic.md")
+
+
+def measured_select_traffic():
+    """HBM-side bytes per select launch from the committed FETCH_SIZE /
+    WRITE_SIZE profile, or None when the select kernel's sources changed
+    since those counters were taken (their SHA-256 is recorded with them)."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    got = dict(re.findall(r"^(select_[a-z_0-9]+): (.+)$", text, re.M))
+    if "select_traffic_bytes_per_launch" not in got:
+        return None
+    h = hashlib.sha256()
+    for rel in got["select_sources"].split():
+        try:
+            h.update(open(os.path.join(ROOT, rel), "rb").read())
+        except OSError:
+            return None
+    if h.hexdigest() != got.get("select_sources_sha256", "").strip():
+        return None
+    return float(got["select_traffic_bytes_per_launch"])
+
+
 def percentile(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -503,7 +530,9 @@ def plain_leg(args, H, dev):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_select_traffic(),
+            "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated; "
+                            "profiles/plain_sparse_matrix_traffic.md)",
             "avg_launch_us": sel_ms_avg * 1e3,
             "alg_bytes_per_launch": sel_bytes_step / sel_launches_step,
         },
