@@ -139,6 +139,7 @@ WsLayout ws_layout(int n, int m, long long P, int k_max) {
   L.scan = take(sizeof(long long) * (size_t)L.scan_blocks);
   L.flags = take(256);
   L.red = take(sizeof(unsigned long long) * kSlots);
+  L.bw_slots = take(sizeof(long long) * kSlots * (size_t)k_max);
   L.total = off;
   return L;
 }
@@ -188,6 +189,7 @@ InstDesc make_desc(hg_graph_s* g, int k, long long lmax, int* part, int* phi,
   d.ctr = (RoundCounters*)(ws + g->lay.ctr);
   d.err_flags = (int*)(ws + g->lay.flags);
   d.red = (unsigned long long*)(ws + g->lay.red);
+  d.bw_slots = (long long*)(ws + g->lay.bw_slots);
   return d;
 }
 
@@ -278,6 +280,8 @@ hg_status hg_load_csr(int32_t n, int32_t m, int64_t P, const int64_t* eptr, cons
     e = hg::fill_i32((int*)(ws + lay.ctr), 0, sizeof(hg::RoundCounters) / sizeof(int), s);
   if (e == hipSuccess) e = hg::fill_i32((int*)(ws + lay.flags), 0, 64, s);
   if (e == hipSuccess) e = hg::fill_i64((long long*)(ws + lay.red), 0, hg::kSlots, s);
+  if (e == hipSuccess)
+    e = hg::fill_i64((long long*)(ws + lay.bw_slots), 0, (long long)hg::kSlots * k_max, s);
   if (e != hipSuccess) return bail(hip_fail(e, "workspace init"));
   st = read_info(g, s);
   if (st != HG_OK) return bail(st);

@@ -126,6 +126,7 @@ struct InstDesc {
   RoundCounters* ctr;
   int* err_flags;
   unsigned long long* red;
+  long long* bw_slots;           // kSlots x k block-weight deltas of a round's moves
 };
 
 // One workgroup's share of a batched launch: instance, and the units it
@@ -192,6 +193,7 @@ inline Launch single_launch(const InstDesc& d) {
 struct WsLayout {
   size_t cand, touched, heavy, big, hist, overflow, thr, tilesum, ctr, info, scan, flags;
   size_t red;   // kSlots partial sums for whole-array reductions (km1)
+  size_t bw_slots;   // kSlots x k_max block-weight deltas (apply), folded in by the round record
   size_t total;
   int num_tiles;
   int scan_blocks;

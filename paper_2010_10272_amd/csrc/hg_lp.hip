@@ -701,8 +701,12 @@ __global__ __launch_bounds__(kBlock) void k_approve_apply(Launch L) {
     apply_list(D, s_list, s_tgt, count, s_from, s_beg, s_off, s_tmp, s_dW, delta, moved_pins,
                approved);
   __syncthreads();
+  // block-weight deltas go to one of kSlots partial rows (a single row
+  // would serialize one atomic per tile on each of the k addresses); the
+  // round record folds them into block_w
+  long long* my_dw = D.bw_slots + (size_t)(blockIdx.x % kSlots) * k;
   for (int i = threadIdx.x; i < k; i += kBlock)
-    if (s_dW[i]) atomicAdd((unsigned long long*)&D.block_w[i], s_dW[i]);
+    if (s_dW[i]) atomicAdd((unsigned long long*)&my_dw[i], s_dW[i]);
   delta = block_sum64(delta, s_tmp);
   moved_pins = block_sum64(moved_pins, s_tmp);
   approved = block_sum64(approved, s_tmp);
@@ -775,8 +779,9 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Launch L) {
   }
 }
 
-// Unit: one instance.  Sum the counter slots, write the round record, move
-// km1 by the attributed drop, reset the counters for the next round.
+// Unit: one instance.  Fold the apply's block-weight slots into block_w, sum
+// the counter slots, write the round record, move km1 by the attributed drop,
+// reset the slots and counters for the next round.
 __global__ __launch_bounds__(kBlock) void k_round_stats(Launch L) {
   __shared__ long long s_sum[kNumCounters];
   __shared__ long long s_max[kBlock / kWave];
@@ -791,7 +796,17 @@ __global__ __launch_bounds__(kBlock) void k_round_stats(Launch L) {
     ctr->slot[c][lane] = 0;
   }
   long long mx = LLONG_MIN;
-  for (int i = threadIdx.x; i < D.k; i += kBlock) mx = D.block_w[i] > mx ? D.block_w[i] : mx;
+  for (int i = threadIdx.x; i < D.k; i += kBlock) {
+    long long d = 0;
+    for (int sl = 0; sl < kSlots; ++sl) {
+      long long* cell = D.bw_slots + (size_t)sl * D.k + i;
+      d += *cell;
+      *cell = 0;
+    }
+    const long long W = D.block_w[i] + d;
+    D.block_w[i] = W;
+    mx = W > mx ? W : mx;
+  }
   mx = wave_max(mx);
   if (lane == 0) s_max[wv] = mx;
   __syncthreads();

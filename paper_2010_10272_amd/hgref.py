@@ -12,7 +12,8 @@ import os
 import torch  # loads the HIP runtime that libhgref.so binds to
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libhgref.so")
+# HGREF_LIB names another build of the same library (for side-by-side timing)
+LIB_PATH = os.environ.get("HGREF_LIB") or os.path.join(_HERE, "libhgref.so")
 
 HG_OK = 0
 HG_ERR_INVALID = -1

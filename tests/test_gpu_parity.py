@@ -98,6 +98,10 @@ def _cases():
                lambda k=k, weighted=weighted: synth.random_power_law(
                    1000 + k, 9000 + 37 * k, 8500 + 11 * k, k, hi=24, unit=not weighted,
                    rounds=4))
+    # banded row-net matrices (net ids follow vertex ids)
+    for k in (8, 32):
+        yield ("band-k%d" % k, lambda k=k: synth.sparse_matrix(
+            k, seed=40 + k, rows=40000, cols=40000, band=1500, rounds=4))
     yield "hub-k4-u", lambda: _hub_instance(7, 6000, 5000, 4, 300, False)
     yield "hub-k16-w", lambda: _hub_instance(8, 6000, 5000, 16, 400, True)
     yield "hub-k70-w", lambda: _hub_instance(9, 5000, 4000, 70, 500, True)
