@@ -258,6 +258,7 @@ def batched_leg(args, H, dev):
 SERVED_RATE = 200.0
 SERVED_BUDGET = 16 << 30      # job memory of the server (admission binds under bursts)
 SERVED_TABLE = 64 << 20
+SERVED_BIG_PINS = 8_000_000   # jobs this large (the grid netlists) take the server's second lane
 
 
 def _sleep_until(clock, due_ms):
@@ -327,7 +328,7 @@ def served_leg(args, H, dev):
     def run_served(burst):
         outs = [outputs(h["inst"].n, r.rounds) for r, h in reqs]
         srv = H.hg_server_create(SERVED_BUDGET + SERVED_TABLE, table_bytes=SERVED_TABLE,
-                                 max_active=256, device=dev)
+                                 max_active=256, device=dev, big_pins=SERVED_BIG_PINS)
         clock = lambda: H.hg_server_now_ms(srv)          # noqa: E731
         start = clock() + 20.0
         ids = []

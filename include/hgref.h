@@ -411,12 +411,16 @@ size_t hg_request_bytes(int32_t n, int32_t m, int64_t P, int32_t k, int32_t roun
                         int32_t weighted_vertices, int32_t weighted_nets);
 
 /* Start a server on device memory [arena, arena + arena_bytes): the first
- * table_bytes hold the batched work tables (two halves, alternately
- * rebuilt), the rest is the jobs' memory.  At most max_active jobs are
- * admitted at once.  sched: HG_SIZE_CLASSES schedules or NULL (defaults).
- * The current device at the call is the server's device. */
+ * table_bytes hold the batched work tables, the rest is the jobs' memory.  At
+ * most max_active jobs are admitted at once.  big_pins > 0 opens a second
+ * lane (own stream and tables) for jobs of at least big_pins pins, so that
+ * smaller jobs never wait for their rounds; 0 keeps one lane.  Each lane takes
+ * half of the table region, split into two halves rebuilt alternately.
+ * sched: HG_SIZE_CLASSES schedules or NULL (defaults).  The current device at
+ * the call is the server's device. */
 hg_status hg_server_create(void* arena, size_t arena_bytes, size_t table_bytes,
-                           int32_t max_active, const hg_schedule* sched, hg_server* out);
+                           int32_t max_active, int64_t big_pins, const hg_schedule* sched,
+                           hg_server* out);
 
 /* Queue a job (copied; its arrays are read later).  Checks the arguments on
  * the host; a job whose footprint exceeds the job memory ends with

@@ -6,16 +6,22 @@
 // Threads and streams
 //   loader    copies a job's arrays in and runs hg_load_csr on the load
 //             stream (which synchronizes that stream only)
-//   executor  owns the compute stream: per step it rebuilds the work tables
-//             when members joined or left, runs the pin-count pass of the
-//             joiners, one round for every member, and queues the result
-//             copies of members that ran their last round
-// Both streams have the default priority.  A job's memory is released only
+//   executor  drives one or two lanes.  A lane is a set of jobs with its own
+//             stream, work tables and step counter: per step it rebuilds the
+//             tables when members joined or left, runs the pin-count pass of
+//             the joiners, one round for every member, and queues the result
+//             copies of members that ran their last round.  With two lanes,
+//             jobs of at least `big_pins` pins take the second one, so small
+//             jobs never wait for the round of a large one: both lanes' kernels
+//             share the GPU.  The executor never blocks on the GPU; it polls
+//             events and moves on to the other lane.
+// Every stream has the default priority.  A job's memory is released only
 // after the event recorded behind its result copies has completed, so no
 // kernel can still read it.
 //
-// Work tables: two halves of the table region, used alternately; a half is
-// rebuilt only after the last step that read it has completed (its event).
+// Work tables: each lane owns two halves of the table region, used
+// alternately; a half is rebuilt only after the last step that read it has
+// completed (its event).
 #include <string.h>
 
 #include <chrono>
@@ -127,6 +133,7 @@ struct Job {
   char* base = nullptr;          // device address of the slice
   hg_graph_s* g = nullptr;
   long long lmax = 0;
+  int lane = 0;
   int64_t join_step = -1;
   int rounds_done = 0;
   bool finishing = false;
@@ -136,44 +143,57 @@ struct Job {
 
 using Clock = std::chrono::steady_clock;
 
+constexpr int kMaxLanes = 2;
+
+// Jobs advanced together on one stream (see the file comment).
+struct Lane {
+  hipStream_t stream = nullptr;
+  char* table[2] = {nullptr, nullptr};   // device halves
+  char* host[2] = {nullptr, nullptr};    // page-locked staging of each half
+  size_t half_bytes = 0;
+  hipEvent_t half_ev[2] = {nullptr, nullptr};
+  bool half_used[2] = {false, false};
+  int half = 1;
+  RoundPlan rp;
+  CountPlan cp;
+  int64_t step = 0;
+  bool changed = true;                   // membership differs from the current tables
+  std::vector<Job*> active;              // executor-owned
+  std::deque<Job*> ready;                // loaded, waiting to join (under the lock)
+  std::deque<hipEvent_t> in_flight;      // events behind queued steps
+};
+
 }  // namespace
 }  // namespace hg
 
 struct hg_server_s {
   // fixed at creation
   char* arena = nullptr;
-  size_t table_half = 0;
-  char* host_half[2] = {nullptr, nullptr};
-  hipEvent_t half_ev[2] = {nullptr, nullptr};
-  bool half_used[2] = {false, false};
   int device = 0;
   int max_active = 1;
+  int nlanes = 1;
+  long long big_pins = 0;
   hg_schedule sched[HG_SIZE_CLASSES];
-  hipStream_t compute = nullptr, load = nullptr;
+  hipStream_t load = nullptr;
   hipEvent_t epoch_ev = nullptr;
   double epoch_ms = 0;
   hg::Clock::time_point t0;
   std::unique_ptr<hg::RangeAlloc> mem;   // job memory (offsets after the table region)
   char* job_base = nullptr;
+  hg::Lane lanes[hg::kMaxLanes];
 
   std::mutex mu;
   std::condition_variable cv_exec, cv_load, cv_done;
   bool stop = false;
   std::vector<std::unique_ptr<hg::Job>> jobs;
-  std::deque<hg::Job*> pending, to_load, ready;
+  std::deque<hg::Job*> pending, to_load;
   int resident = 0;                     // admitted and not done
   hg_server_stats st{};
   hg_status fatal = HG_OK;
   char fatal_msg[160] = "";
 
   // executor-owned
-  std::vector<hg::Job*> active;
   std::vector<hipEvent_t> step_ev_pool;
-  std::deque<hipEvent_t> in_flight;
-  int half = 1;
-  hg::RoundPlan rp;
-  hg::CountPlan cp;
-  int64_t step = 0;
 
   std::thread exec_thread, load_thread;
 };
@@ -250,7 +270,7 @@ void load_loop(hg_server_s* s) {
     lk.lock();
     if (st == HG_OK) {
       j->loaded_ms = now_ms(s);
-      s->ready.push_back(j);
+      s->lanes[j->lane].ready.push_back(j);
     } else {
       s->mem->give(j->off, j->lay.total);
       s->resident -= 1;
@@ -264,35 +284,38 @@ void load_loop(hg_server_s* s) {
 
 // Jobs whose result copies completed: release memory, record the time.
 void retire(hg_server_s* s) {
-  std::vector<Job*> keep;
-  for (Job* j : s->active) {
-    if (!j->finishing) {
-      keep.push_back(j);
-      continue;
+  for (int li = 0; li < s->nlanes; ++li) {
+    Lane& ln = s->lanes[li];
+    std::vector<Job*> keep;
+    for (Job* j : ln.active) {
+      if (!j->finishing) {
+        keep.push_back(j);
+        continue;
+      }
+      const hipError_t q = hipEventQuery(j->done_ev);
+      if (q == hipErrorNotReady) {
+        keep.push_back(j);
+        continue;
+      }
+      j->done_ms = event_ms(s, j->done_ev);
+      (void)hipEventDestroy(j->done_ev);
+      j->done_ev = nullptr;
+      hg_free(j->g);
+      j->g = nullptr;
+      s->mem->give(j->off, j->lay.total);
+      s->resident -= 1;
+      j->state = HG_REQ_DONE;
+      if (q == hipSuccess) {
+        s->st.completed += 1;
+      } else {
+        j->status = HG_ERR_DEVICE;
+        snprintf(j->msg, sizeof(j->msg), "%s", hipGetErrorString(q));
+        s->st.failed += 1;
+      }
+      s->cv_done.notify_all();
     }
-    const hipError_t q = hipEventQuery(j->done_ev);
-    if (q == hipErrorNotReady) {
-      keep.push_back(j);
-      continue;
-    }
-    j->done_ms = event_ms(s, j->done_ev);
-    (void)hipEventDestroy(j->done_ev);
-    j->done_ev = nullptr;
-    hg_free(j->g);
-    j->g = nullptr;
-    s->mem->give(j->off, j->lay.total);
-    s->resident -= 1;
-    j->state = HG_REQ_DONE;
-    if (q == hipSuccess) {
-      s->st.completed += 1;
-    } else {
-      j->status = HG_ERR_DEVICE;
-      snprintf(j->msg, sizeof(j->msg), "%s", hipGetErrorString(q));
-      s->st.failed += 1;
-    }
-    s->cv_done.notify_all();
+    ln.active.swap(keep);
   }
-  s->active.swap(keep);
 }
 
 // Admit pending jobs in arrival order while memory and slots allow.
@@ -309,6 +332,7 @@ void admit(hg_server_s* s) {
     s->pending.pop_front();
     j->off = off;
     j->base = s->job_base + off;
+    j->lane = s->nlanes > 1 && j->r.P >= s->big_pins ? 1 : 0;
     j->state = HG_REQ_ADMITTED;
     j->admit_ms = now_ms(s);
     s->resident += 1;
@@ -338,17 +362,20 @@ BatchMember member_of(const hg_server_s* s, const Job* j) {
   return M;
 }
 
-// Enqueue one step for the members in `run` (joiners last, `nj` of them);
-// rebuild the tables when `rebuild`.  Returns a HIP error.
-hipError_t enqueue_step(hg_server_s* s, const std::vector<Job*>& run, size_t nj, bool rebuild) {
-  hipStream_t cs = s->compute;
+// True when lane `ln` may rebuild its tables now (the half it would write is
+// no longer read by a queued step).
+bool half_free(const Lane& ln) {
+  const int h = ln.half ^ 1;
+  return !ln.half_used[h] || hipEventQuery(ln.half_ev[h]) != hipErrorNotReady;
+}
+
+// Enqueue one step of lane `ln` for the members in `run` (joiners last, `nj`
+// of them); rebuild the tables when the lane's membership changed.
+hipError_t enqueue_step(hg_server_s* s, Lane& ln, const std::vector<Job*>& run, size_t nj) {
+  hipStream_t cs = ln.stream;
   hipError_t e = hipSuccess;
-  if (rebuild) {
-    const int h = s->half ^ 1;
-    if (s->half_used[h]) {
-      e = hipEventSynchronize(s->half_ev[h]);
-      if (e != hipSuccess) return e;
-    }
+  if (ln.changed) {
+    const int h = ln.half ^ 1;   // free: checked by the caller (half_free)
     std::vector<BatchMember> mem;
     std::vector<int> all, join;
     for (size_t i = 0; i < run.size(); ++i) {
@@ -356,26 +383,26 @@ hipError_t enqueue_step(hg_server_s* s, const std::vector<Job*>& run, size_t nj,
       all.push_back((int)i);
       if (i + nj >= run.size()) join.push_back((int)i);
     }
-    char* dev = s->arena + (size_t)h * s->table_half;
-    size_t end = build_plans(mem, all, s->sched, dev, s->host_half[h], 0, s->table_half, &s->rp,
+    size_t end = build_plans(mem, all, s->sched, ln.table[h], ln.host[h], 0, ln.half_bytes, &ln.rp,
                              nullptr);
     if (end && !join.empty())
-      end = build_plans(mem, join, s->sched, dev, s->host_half[h], end, s->table_half, nullptr,
-                        &s->cp);
+      end = build_plans(mem, join, s->sched, ln.table[h], ln.host[h], end, ln.half_bytes, nullptr,
+                        &ln.cp);
     if (end == 0) return hipErrorOutOfMemory;   // checked by the caller beforehand
-    e = hipMemcpyAsync(dev, s->host_half[h], end, hipMemcpyHostToDevice, cs);
+    e = hipMemcpyAsync(ln.table[h], ln.host[h], end, hipMemcpyHostToDevice, cs);
     if (e != hipSuccess) return e;
-    s->half = h;
+    ln.half = h;
+    ln.changed = false;
     s->st.rebuilds += 1;
   }
   if (nj > 0) {
-    e = launch_counts(s->cp, true, true, cs);
+    e = launch_counts(ln.cp, true, true, cs);
     if (e != hipSuccess) return e;
   }
-  e = launch_round(s->rp, (int)s->step, cs, nullptr);
+  e = launch_round(ln.rp, (int)ln.step, cs, nullptr);
   if (e != hipSuccess) return e;
-  e = hipEventRecord(s->half_ev[s->half], cs);
-  s->half_used[s->half] = true;
+  e = hipEventRecord(ln.half_ev[ln.half], cs);
+  ln.half_used[ln.half] = true;
   return e;
 }
 
@@ -383,7 +410,7 @@ hipError_t enqueue_step(hg_server_s* s, const std::vector<Job*>& run, size_t nj,
 hipError_t enqueue_results(hg_server_s* s, Job* j) {
   const hg_request& r = j->r;
   const JobLayout& L = j->lay;
-  hipStream_t cs = s->compute;
+  hipStream_t cs = s->lanes[j->lane].stream;
   hipError_t e = hipSuccess;
   if (r.part_out)
     e = hipMemcpyAsync(r.part_out, j->base + L.part, sizeof(int) * (size_t)r.n,
@@ -410,129 +437,152 @@ hipEvent_t step_event(hg_server_s* s) {
   return e;
 }
 
-void exec_loop(hg_server_s* s) {
-  (void)hipSetDevice(s->device);
-  std::unique_lock<std::mutex> lk(s->mu);
-  bool changed = true;     // membership differs from the current tables
-  for (;;) {
-    retire(s);
-    admit(s);
-    if (s->fatal != HG_OK) {
-      // after a device error nothing new starts: fail what waits
-      while (!s->pending.empty()) {
-        finish_failed(s, s->pending.front(), s->fatal, s->fatal_msg);
-        s->pending.pop_front();
+// Fail every job that cannot finish after a device error (nothing new is
+// admitted then, so the memory of stuck members is simply abandoned).
+void fail_all(hg_server_s* s) {
+  while (!s->pending.empty()) {
+    finish_failed(s, s->pending.front(), s->fatal, s->fatal_msg);
+    s->pending.pop_front();
+  }
+  for (int li = 0; li < s->nlanes; ++li) {
+    Lane& ln = s->lanes[li];
+    while (!ln.ready.empty()) {
+      Job* j = ln.ready.front();
+      ln.ready.pop_front();
+      hg_free(j->g);
+      j->g = nullptr;
+      s->mem->give(j->off, j->lay.total);
+      s->resident -= 1;
+      finish_failed(s, j, s->fatal, s->fatal_msg);
+    }
+    std::vector<Job*> keep;
+    for (Job* j : ln.active) {
+      if (j->finishing) {
+        keep.push_back(j);
+        continue;
       }
-      while (!s->ready.empty()) {
-        Job* j = s->ready.front();
-        s->ready.pop_front();
+      s->resident -= 1;
+      finish_failed(s, j, s->fatal, s->fatal_msg);
+    }
+    ln.active.swap(keep);
+  }
+}
+
+// The members of lane `ln`'s next step: its running jobs plus as many
+// loaded jobs as its table half can describe (those get join_step set).
+// Returns the number of joiners (appended last to `run`).
+size_t gather_step(hg_server_s* s, Lane& ln, std::vector<Job*>& run) {
+  run.clear();
+  for (Job* j : ln.active)
+    if (!j->finishing) run.push_back(j);
+  size_t nj = 0;
+  while (!ln.ready.empty()) {
+    Job* j = ln.ready.front();
+    std::vector<BatchMember> mem;
+    std::vector<int> all;
+    for (size_t i = 0; i < run.size(); ++i) {
+      mem.push_back(member_of(s, run[i]));
+      all.push_back((int)i);
+    }
+    j->join_step = ln.step;
+    mem.push_back(member_of(s, j));
+    all.push_back((int)run.size());
+    // round tables of everyone plus count tables of the joiners
+    if (table_bound(mem, all) * 2 > ln.half_bytes) {
+      if (run.empty()) {
+        ln.ready.pop_front();
         hg_free(j->g);
         j->g = nullptr;
         s->mem->give(j->off, j->lay.total);
         s->resident -= 1;
-        finish_failed(s, j, s->fatal, s->fatal_msg);
+        finish_failed(s, j, HG_ERR_WORKSPACE, "job too large for the server's table region");
+        continue;
       }
-      // members without queued results never finish; nothing new is admitted
-      // after a device error, so their memory is simply abandoned
-      std::vector<Job*> keep;
-      for (Job* j : s->active) {
-        if (j->finishing) {
-          keep.push_back(j);
-          continue;
-        }
-        s->resident -= 1;
-        finish_failed(s, j, s->fatal, s->fatal_msg);
-      }
-      s->active.swap(keep);
+      break;
     }
+    ln.ready.pop_front();
+    run.push_back(j);
+    ++nj;
+  }
+  return nj;
+}
+
+void exec_loop(hg_server_s* s) {
+  (void)hipSetDevice(s->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  std::vector<Job*> run;
+  for (;;) {
+    retire(s);
+    admit(s);
+    if (s->fatal != HG_OK) fail_all(s);
     if (s->stop && s->resident == 0 && s->pending.empty()) break;
-    // joiners: loaded jobs, as many as the table half can describe
-    std::vector<Job*> run;
-    for (Job* j : s->active)
-      if (!j->finishing) run.push_back(j);
-    size_t nj = 0;
-    while (!s->ready.empty()) {
-      Job* j = s->ready.front();
-      std::vector<BatchMember> mem;
-      std::vector<int> all;
-      for (size_t i = 0; i < run.size(); ++i) {
-        mem.push_back(member_of(s, run[i]));
-        all.push_back((int)i);
+    bool stepped = false;
+    for (int li = 0; li < s->nlanes; ++li) {
+      Lane& ln = s->lanes[li];
+      // at most kInFlightSteps steps of a lane queued ahead of the GPU
+      while (!ln.in_flight.empty() && hipEventQuery(ln.in_flight.front()) != hipErrorNotReady) {
+        s->step_ev_pool.push_back(ln.in_flight.front());
+        ln.in_flight.pop_front();
       }
-      j->join_step = s->step;
-      mem.push_back(member_of(s, j));
-      all.push_back((int)run.size());
-      // round tables of everyone plus count tables of the joiners
-      if (table_bound(mem, all) * 2 > s->table_half) {
-        if (run.empty()) {
-          s->ready.pop_front();
-          hg_free(j->g);
-          j->g = nullptr;
-          s->mem->give(j->off, j->lay.total);
-          s->resident -= 1;
-          finish_failed(s, j, HG_ERR_WORKSPACE, "job too large for the server's table region");
-          continue;
-        }
-        break;
+      if ((int)ln.in_flight.size() >= kInFlightSteps) continue;
+      const bool wants_rebuild = ln.changed || !ln.ready.empty();
+      if (wants_rebuild && !half_free(ln)) continue;
+      const size_t nj = gather_step(s, ln, run);
+      if (run.empty()) continue;
+      if (nj > 0) ln.changed = true;
+      lk.unlock();
+      hipError_t e = enqueue_step(s, ln, run, nj);
+      long long pins = 0;
+      for (Job* j : run) pins += j->r.P;
+      std::vector<Job*> leaving;
+      for (Job* j : run) {
+        j->rounds_done += 1;
+        if (j->rounds_done >= j->r.rounds) leaving.push_back(j);
       }
-      s->ready.pop_front();
-      run.push_back(j);
-      ++nj;
+      for (Job* j : leaving)
+        if (e == hipSuccess) e = enqueue_results(s, j);
+      hipEvent_t se = step_event(s);
+      if (se && e == hipSuccess) {
+        e = hipEventRecord(se, ln.stream);
+        ln.in_flight.push_back(se);
+      }
+      lk.lock();
+      if (e != hipSuccess && s->fatal == HG_OK) {
+        s->fatal = HG_ERR_DEVICE;
+        snprintf(s->fatal_msg, sizeof(s->fatal_msg), "server step: %s", hipGetErrorString(e));
+      }
+      for (size_t i = run.size() - nj; i < run.size(); ++i) {
+        run[i]->state = HG_REQ_ACTIVE;
+        ln.active.push_back(run[i]);
+      }
+      s->st.steps += 1;
+      s->st.member_rounds += (int64_t)run.size();
+      s->st.pin_rounds += pins;
+      s->st.max_members = std::max<int64_t>(s->st.max_members, (int64_t)run.size());
+      ln.step += 1;
+      if (!leaving.empty()) ln.changed = true;
+      stepped = true;
     }
-    if (run.empty()) {
-      // Nothing to run.  Submits and finished loads notify; completions on
-      // the GPU are polled (every 50 us while results are outstanding).
-      if (!s->active.empty())
-        s->cv_exec.wait_for(lk, std::chrono::microseconds(50));
+    if (!stepped) {
+      // Nothing could start.  Submits and finished loads notify; the GPU is
+      // polled (every 20 us while steps or results are outstanding).
+      bool busy = false;
+      for (int li = 0; li < s->nlanes; ++li)
+        busy = busy || !s->lanes[li].active.empty() || !s->lanes[li].in_flight.empty();
+      if (busy)
+        s->cv_exec.wait_for(lk, std::chrono::microseconds(20));
       else
         s->cv_exec.wait_for(lk, std::chrono::milliseconds(1));
-      continue;
     }
-    if (nj > 0) changed = true;
-    lk.unlock();
-    // keep at most kInFlightSteps steps queued ahead of the GPU
-    while ((int)s->in_flight.size() >= kInFlightSteps) {
-      hipEvent_t e = s->in_flight.front();
-      s->in_flight.pop_front();
-      (void)hipEventSynchronize(e);
-      s->step_ev_pool.push_back(e);
-    }
-    hipError_t e = enqueue_step(s, run, nj, changed);
-    long long pins = 0;
-    for (Job* j : run) pins += j->r.P;
-    std::vector<Job*> leaving;
-    for (Job* j : run) {
-      j->rounds_done += 1;
-      if (j->rounds_done >= j->r.rounds) leaving.push_back(j);
-    }
-    for (Job* j : leaving)
-      if (e == hipSuccess) e = enqueue_results(s, j);
-    hipEvent_t se = step_event(s);
-    if (se && e == hipSuccess) {
-      e = hipEventRecord(se, s->compute);
-      s->in_flight.push_back(se);
-    }
-    lk.lock();
-    if (e != hipSuccess && s->fatal == HG_OK) {
-      s->fatal = HG_ERR_DEVICE;
-      snprintf(s->fatal_msg, sizeof(s->fatal_msg), "server step: %s", hipGetErrorString(e));
-    }
-    for (size_t i = run.size() - nj; i < run.size(); ++i) {
-      run[i]->state = HG_REQ_ACTIVE;
-      s->active.push_back(run[i]);
-    }
-    s->st.steps += 1;
-    s->st.member_rounds += (int64_t)run.size();
-    s->st.pin_rounds += pins;
-    s->st.max_members = std::max<int64_t>(s->st.max_members, (int64_t)run.size());
-    s->step += 1;
-    changed = !leaving.empty();
   }
   lk.unlock();
-  while (!s->in_flight.empty()) {
-    (void)hipEventSynchronize(s->in_flight.front());
-    s->step_ev_pool.push_back(s->in_flight.front());
-    s->in_flight.pop_front();
+  for (int li = 0; li < s->nlanes; ++li) {
+    Lane& ln = s->lanes[li];
+    while (!ln.in_flight.empty()) {
+      (void)hipEventSynchronize(ln.in_flight.front());
+      s->step_ev_pool.push_back(ln.in_flight.front());
+      ln.in_flight.pop_front();
+    }
   }
 }
 
@@ -553,14 +603,18 @@ size_t hg_request_bytes(int32_t n, int32_t m, int64_t P, int32_t k, int32_t roun
 }
 
 hg_status hg_server_create(void* arena, size_t arena_bytes, size_t table_bytes,
-                           int32_t max_active, const hg_schedule* sched, hg_server* out) {
+                           int32_t max_active, int64_t big_pins, const hg_schedule* sched,
+                           hg_server* out) {
   if (!out) return fail(HG_ERR_INVALID, "out must be non-NULL");
   *out = nullptr;
   if (!arena) return fail(HG_ERR_INVALID, "arena must be non-NULL");
   if (max_active < 1) return fail(HG_ERR_INVALID, "max_active must be >= 1");
-  table_bytes = table_bytes / 512 * 512;
-  if (table_bytes < 2 * 65536 || table_bytes >= arena_bytes)
-    return fail(HG_ERR_WORKSPACE, "table_bytes must be at least 128 KiB and below arena_bytes");
+  if (big_pins < 0) return fail(HG_ERR_INVALID, "big_pins must be >= 0");
+  const int nlanes = big_pins > 0 ? 2 : 1;
+  const size_t quarter = table_bytes / (2 * nlanes) / 256 * 256;
+  if (quarter < 65536 || table_bytes >= arena_bytes)
+    return fail(HG_ERR_WORKSPACE, "table_bytes must be at least %d KiB and below arena_bytes",
+                nlanes * 128);
   if (sched)
     for (int c = 0; c < HG_SIZE_CLASSES; ++c)
       if (!hg::valid_schedule(sched[c]))
@@ -568,21 +622,27 @@ hg_status hg_server_create(void* arena, size_t arena_bytes, size_t table_bytes,
   hg_server_s* s = new (std::nothrow) hg_server_s();
   if (!s) return fail(HG_ERR_INVALID, "out of host memory");
   s->arena = (char*)arena;
-  s->table_half = table_bytes / 2;
+  s->nlanes = nlanes;
+  s->big_pins = big_pins;
   s->job_base = s->arena + table_bytes;
   s->mem.reset(new hg::RangeAlloc(arena_bytes - table_bytes));
   s->max_active = max_active;
   memcpy(s->sched, sched ? sched : hg::kDefaultSchedule, sizeof(s->sched));
   s->t0 = hg::Clock::now();
   hipError_t e = hipGetDevice(&s->device);
-  for (int h = 0; h < 2 && e == hipSuccess; ++h) {
-    e = hipHostMalloc((void**)&s->host_half[h], s->table_half, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->half_ev[h], hipEventDisableTiming);
+  for (int li = 0; li < nlanes && e == hipSuccess; ++li) {
+    hg::Lane& ln = s->lanes[li];
+    ln.half_bytes = quarter;
+    for (int h = 0; h < 2 && e == hipSuccess; ++h) {
+      ln.table[h] = s->arena + (size_t)(2 * li + h) * quarter;
+      e = hipHostMalloc((void**)&ln.host[h], quarter, hipHostMallocDefault);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&ln.half_ev[h], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking);
   }
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->compute, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->load, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreate(&s->epoch_ev);
-  if (e == hipSuccess) e = hipEventRecord(s->epoch_ev, s->compute);
+  if (e == hipSuccess) e = hipEventRecord(s->epoch_ev, s->lanes[0].stream);
   if (e == hipSuccess) e = hipEventSynchronize(s->epoch_ev);
   if (e != hipSuccess) {
     hg_server_free(s);
@@ -680,14 +740,17 @@ void hg_server_free(hg_server s) {
     if (j->g) hg_free(j->g);
   }
   for (hipEvent_t e : s->step_ev_pool) (void)hipEventDestroy(e);
-  if (s->compute) (void)hipStreamSynchronize(s->compute);
   if (s->load) (void)hipStreamSynchronize(s->load);
-  for (int h = 0; h < 2; ++h) {
-    if (s->half_ev[h]) (void)hipEventDestroy(s->half_ev[h]);
-    if (s->host_half[h]) (void)hipHostFree(s->host_half[h]);
+  for (int li = 0; li < hg::kMaxLanes; ++li) {
+    hg::Lane& ln = s->lanes[li];
+    if (ln.stream) (void)hipStreamSynchronize(ln.stream);
+    for (int h = 0; h < 2; ++h) {
+      if (ln.half_ev[h]) (void)hipEventDestroy(ln.half_ev[h]);
+      if (ln.host[h]) (void)hipHostFree(ln.host[h]);
+    }
+    if (ln.stream) (void)hipStreamDestroy(ln.stream);
   }
   if (s->epoch_ev) (void)hipEventDestroy(s->epoch_ev);
-  if (s->compute) (void)hipStreamDestroy(s->compute);
   if (s->load) (void)hipStreamDestroy(s->load);
   delete s;
 }

@@ -142,7 +142,7 @@ def _load():
     lib.hg_batch_get_schedule.restype = i32
     lib.hg_request_bytes.argtypes = [i32, i32, i64, i32, i32, i32, i32]
     lib.hg_request_bytes.restype = sz
-    lib.hg_server_create.argtypes = [vp, sz, sz, i32, sched_p, ctypes.POINTER(vp)]
+    lib.hg_server_create.argtypes = [vp, sz, sz, i32, i64, sched_p, ctypes.POINTER(vp)]
     lib.hg_server_create.restype = i32
     lib.hg_server_submit.argtypes = [vp, ctypes.POINTER(HgRequest), ctypes.POINTER(i64)]
     lib.hg_server_submit.restype = i32
@@ -534,13 +534,14 @@ class Server:
     they are done."""
 
     def __init__(self, arena_bytes, table_bytes=64 << 20, max_active=256, sched=None,
-                 device="cuda"):
+                 device="cuda", big_pins=0):
         self.device = torch.device(device)
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             _check(_lib.hg_server_create(_ptr(self.arena), int(arena_bytes), int(table_bytes),
-                                         int(max_active), _schedule_c(sched), ctypes.byref(h)))
+                                         int(max_active), int(big_pins), _schedule_c(sched),
+                                         ctypes.byref(h)))
         self._h = h
         self.jobs = {}
 
@@ -568,8 +569,8 @@ class Server:
 
 
 def hg_server_create(arena_bytes, table_bytes=64 << 20, max_active=256, sched=None,
-                     device="cuda"):
-    return Server(arena_bytes, table_bytes, max_active, sched, device)
+                     device="cuda", big_pins=0):
+    return Server(arena_bytes, table_bytes, max_active, sched, device, big_pins)
 
 
 def hg_server_submit(srv, n, eptr, pins, part, k, rounds, eps, vwgt=None, ewgt=None,

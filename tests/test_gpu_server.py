@@ -92,12 +92,15 @@ def test_alone_results_match_oracle(H, jobs, alone):
             assert s == stats_o[r], (inst.name, r)
 
 
-@pytest.mark.parametrize("order", ["given", "reversed", "interleaved"])
-def test_server_mix_equals_alone(H, jobs, alone, order):
+@pytest.mark.parametrize("order,big_pins", [("given", 0), ("reversed", 0), ("interleaved", 0),
+                                             ("given", 100000), ("interleaved", 100000)])
+def test_server_mix_equals_alone(H, jobs, alone, order, big_pins):
     n = len(jobs)
     idx = {"given": list(range(n)), "reversed": list(range(n))[::-1],
            "interleaved": list(range(0, n, 2)) + list(range(1, n, 2))}[order]
-    srv = H.hg_server_create(1 << 30, table_bytes=8 << 20, max_active=64)
+    if big_pins:                                    # both lanes get jobs
+        assert any(x.P >= big_pins for x in jobs) and any(x.P < big_pins for x in jobs)
+    srv = H.hg_server_create(1 << 30, table_bytes=8 << 20, max_active=64, big_pins=big_pins)
     ids = _submit_all(H, srv, jobs, idx)
     assert H.hg_server_drain(srv, DRAIN_MS) == 0
     _check_results(H, srv, jobs, ids, alone)
