@@ -219,10 +219,43 @@ static int cmp_cand(const void* x, const void* y) {
   return (a->u > b->u) - (a->u < b->u);
 }
 
+/* (gain desc, id asc): the order of a round's moves for exact gains */
+static int cmp_gain_id(const void* x, const void* y) {
+  const or_cand* a = (const or_cand*)x;
+  const or_cand* b = (const or_cand*)y;
+  if (a->gain != b->gain) return (a->gain < b->gain) - (a->gain > b->gain); /* desc */
+  return (a->u > b->u) - (a->u < b->u);
+}
+
+static int lp_round_impl(int32_t n, int32_t m, const int64_t* eptr, const int32_t* pins,
+                         const int64_t* vptr, const int32_t* vnets, const int32_t* c,
+                         const int32_t* w, int32_t k, int64_t lmax, int32_t* part,
+                         uint8_t* eligible, uint8_t* moved, or_round_stats* st, int64_t* sgain);
+
+/* One synchronous round; see lp_round_impl below. */
 int or_lp_round(int32_t n, int32_t m, const int64_t* eptr, const int32_t* pins,
                 const int64_t* vptr, const int32_t* vnets, const int32_t* c,
                 const int32_t* w, int32_t k, int64_t lmax, int32_t* part,
                 uint8_t* eligible, uint8_t* moved, or_round_stats* st) {
+  return lp_round_impl(n, m, eptr, pins, vptr, vnets, c, w, k, lmax, part, eligible, moved, st,
+                       NULL);
+}
+
+/* The same round, also reporting the select gain of every approved move
+ * (sgain[u], n entries; other entries untouched). */
+static int or_lp_round_gains(int32_t n, int32_t m, const int64_t* eptr, const int32_t* pins,
+                             const int64_t* vptr, const int32_t* vnets, const int32_t* c,
+                             const int32_t* w, int32_t k, int64_t lmax, int32_t* part,
+                             uint8_t* eligible, uint8_t* moved, or_round_stats* st,
+                             int64_t* sgain) {
+  return lp_round_impl(n, m, eptr, pins, vptr, vnets, c, w, k, lmax, part, eligible, moved, st,
+                       sgain);
+}
+
+static int lp_round_impl(int32_t n, int32_t m, const int64_t* eptr, const int32_t* pins,
+                         const int64_t* vptr, const int32_t* vnets, const int32_t* c,
+                         const int32_t* w, int32_t k, int64_t lmax, int32_t* part,
+                         uint8_t* eligible, uint8_t* moved, or_round_stats* st, int64_t* sgain) {
   int32_t* phi = (int32_t*)malloc(sizeof(int32_t) * (size_t)m * (size_t)k);
   int32_t* lambda = (int32_t*)malloc(sizeof(int32_t) * (size_t)m);
   int64_t* W = (int64_t*)malloc(sizeof(int64_t) * (size_t)k);
@@ -301,6 +334,7 @@ int or_lp_round(int32_t n, int32_t m, const int64_t* eptr, const int32_t* pins,
       if (load + cw(c, cand[i].u) > lmax) break;   /* longest feasible prefix */
       load += cw(c, cand[i].u);
       target[cand[i].u] = t;
+      if (sgain) sgain[cand[i].u] = cand[i].gain;
     }
     i0 = i1;
   }
@@ -369,6 +403,210 @@ int or_refine(int32_t n, int32_t m, const int64_t* eptr, const int32_t* pins,
     or_connectivity(m, k, phi, lambda, conn_bits);
     *km1_out = or_km1(m, w, lambda);
     free(phi); free(lambda); free(conn_bits);
+  }
+  free(vptr); free(vnets); free(eligible); free(moved);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Move sequences (section "Parallel Gain Calculation", subsection "Parallel */
+/* Gain Recalculation"; section "Direct k-way FM": best prefix).             */
+/* ------------------------------------------------------------------------ */
+
+/* Exact gain of every move of a sequence, as if the moves were performed one
+ * after the other in the given order: move j takes vertex mu[j] from its
+ * current block a to block mt[j] = b, and its gain is
+ *   w({e in I(u) : Phi(e, a) = 1}) - w({e in I(u) : Phi(e, b) = 0})
+ * on the pin counts left by moves 0..j-1 (the km1 decrease of that move).
+ * Done literally: Phi is built from `part` and updated move by move.  part is
+ * the partition before the sequence and is not changed.  Returns
+ * OR_ERR_INVALID if a vertex moves twice, a target lies outside [0,k) or a
+ * move targets the block its vertex is in. */
+int or_move_gains(int32_t n, int32_t m, const int64_t* eptr, const int32_t* pins,
+                  const int64_t* vptr, const int32_t* vnets, const int32_t* w, int32_t k,
+                  const int32_t* part, int32_t t, const int32_t* mu, const int32_t* mt,
+                  int64_t* gains) {
+  int32_t* phi = (int32_t*)malloc(sizeof(int32_t) * (size_t)m * (size_t)k);
+  int32_t* cur = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  uint8_t* seen = (uint8_t*)calloc((size_t)n, 1);
+  if (!phi || !cur || !seen) return OR_ERR_INVALID;
+  or_pin_counts(m, eptr, pins, part, k, phi);
+  memcpy(cur, part, sizeof(int32_t) * (size_t)n);
+  int rc = OR_OK;
+  for (int32_t j = 0; j < t && rc == OR_OK; ++j) {
+    const int32_t u = mu[j], b = mt[j];
+    if (u < 0 || u >= n || seen[u] || b < 0 || b >= k || cur[u] == b) {
+      rc = OR_ERR_INVALID;
+      break;
+    }
+    seen[u] = 1;
+    const int32_t a = cur[u];
+    int64_t g = 0;
+    for (int64_t q = vptr[u]; q < vptr[u + 1]; ++q) {
+      const int32_t e = vnets[q];
+      if (phi[(int64_t)e * k + a] == 1) g += ww(w, e);
+      if (phi[(int64_t)e * k + b] == 0) g -= ww(w, e);
+    }
+    gains[j] = g;
+    for (int64_t q = vptr[u]; q < vptr[u + 1]; ++q) {
+      const int32_t e = vnets[q];
+      phi[(int64_t)e * k + a] -= 1;
+      phi[(int64_t)e * k + b] += 1;
+    }
+    cur[u] = b;
+  }
+  free(phi); free(cur); free(seen);
+  return rc;
+}
+
+/* Best prefix of a move sequence: the length p in [0, t] with the largest
+ * total gain gains[0] + ... + gains[p-1] among the prefixes after which every
+ * block weight is at most lmax; the empty prefix always qualifies; ties go to
+ * the longer prefix.  Block weights are followed move by move from `part`. */
+void or_best_prefix(int32_t n, const int32_t* c, int32_t k, int64_t lmax, const int32_t* part,
+                    int32_t t, const int32_t* mu, const int32_t* mt, const int64_t* gains,
+                    int32_t* best_len, int64_t* best_gain) {
+  int64_t* W = (int64_t*)malloc(sizeof(int64_t) * (size_t)k);
+  int32_t* cur = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  or_block_weights(n, c, part, k, W);
+  memcpy(cur, part, sizeof(int32_t) * (size_t)n);
+  int64_t over = 0, total = 0;
+  for (int32_t i = 0; i < k; ++i) over += W[i] > lmax;
+  *best_len = 0;
+  *best_gain = 0;
+  for (int32_t j = 0; j < t; ++j) {
+    const int32_t u = mu[j], a = cur[u], b = mt[j];
+    over -= (W[a] > lmax) + (W[b] > lmax);
+    W[a] -= cw(c, u);
+    W[b] += cw(c, u);
+    over += (W[a] > lmax) + (W[b] > lmax);
+    cur[u] = b;
+    total += gains[j];
+    if (over == 0 && total >= *best_gain) {
+      *best_len = j + 1;
+      *best_gain = total;
+    }
+  }
+  free(W); free(cur);
+}
+
+/* One monotone label-propagation round: candidates and approval exactly as in
+ * or_lp_round; the approved moves, ordered by (select gain desc, vertex id
+ * asc), get their exact gains in that order (or_move_gains) and only the
+ * prefix with the largest total gain is applied (or_best_prefix, ties to the
+ * longer prefix; every prefix of approved moves respects L_max, because the
+ * approval already budgets each target block for all of its moves and moves
+ * out of a block only lower its weight).  km1 never increases.  The stats are
+ * those of or_lp_round with `approved` = the prefix length; the approved set
+ * before the cut is returned in *n_approved when non-NULL. */
+int or_lp_round_exact(int32_t n, int32_t m, const int64_t* eptr, const int32_t* pins,
+                      const int64_t* vptr, const int32_t* vnets, const int32_t* c,
+                      const int32_t* w, int32_t k, int64_t lmax, int32_t* part,
+                      uint8_t* eligible, uint8_t* moved, or_round_stats* st,
+                      int64_t* n_approved) {
+  /* a plain round on copies gives the approved set and its select gains */
+  int32_t* part2 = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  uint8_t* elig2 = (uint8_t*)malloc((size_t)n);
+  int64_t* sgain = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  or_cand* seq = (or_cand*)malloc(sizeof(or_cand) * (size_t)n);
+  int32_t* mu = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t* mt = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  int64_t* gains = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  uint8_t* touched = (uint8_t*)malloc((size_t)m);
+  if (!part2 || !elig2 || !sgain || !seq || !mu || !mt || !gains || !touched)
+    return OR_ERR_INVALID;
+  memcpy(part2, part, sizeof(int32_t) * (size_t)n);
+  memcpy(elig2, eligible, (size_t)n);
+  or_round_stats plain;
+  int rc = or_lp_round_gains(n, m, eptr, pins, vptr, vnets, c, w, k, lmax, part2, elig2, moved,
+                             &plain, sgain);
+  if (rc != OR_OK) return rc;
+  /* the approved moves in (gain desc, id asc) order */
+  int64_t t = 0;
+  for (int32_t u = 0; u < n; ++u) {
+    if (!moved[u]) continue;
+    seq[t].gain = sgain[u];
+    seq[t].u = u;
+    seq[t].t = part2[u];
+    t += 1;
+  }
+  qsort(seq, (size_t)t, sizeof(or_cand), cmp_gain_id);
+  for (int64_t j = 0; j < t; ++j) {
+    mu[j] = seq[j].u;
+    mt[j] = seq[j].t;
+  }
+  rc = or_move_gains(n, m, eptr, pins, vptr, vnets, w, k, part, (int32_t)t, mu, mt, gains);
+  if (rc != OR_OK) return rc;
+  int32_t p = 0;
+  int64_t best = 0;
+  /* lmax = INT64_MAX: the prefixes are feasible by construction (see above) */
+  or_best_prefix(n, c, k, INT64_MAX, part, (int32_t)t, mu, mt, gains, &p, &best);
+  if (n_approved) *n_approved = t;
+
+  /* apply the prefix, then the round record as in or_lp_round */
+  *st = plain;
+  st->approved = p;
+  st->moved_pins = 0;
+  st->touched_nets = 0;
+  int32_t* phi = (int32_t*)malloc(sizeof(int32_t) * (size_t)m * (size_t)k);
+  int32_t* lambda = (int32_t*)malloc(sizeof(int32_t) * (size_t)m);
+  uint32_t* bits = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)m * (size_t)((k + 31) / 32));
+  int64_t* W = (int64_t*)malloc(sizeof(int64_t) * (size_t)k);
+  or_pin_counts(m, eptr, pins, part, k, phi);
+  or_connectivity(m, k, phi, lambda, bits);
+  const int64_t km1_before = or_km1(m, w, lambda);
+  memset(moved, 0, (size_t)n);
+  memset(touched, 0, (size_t)m);
+  for (int32_t j = 0; j < p; ++j) {
+    const int32_t u = mu[j];
+    part[u] = mt[j];
+    moved[u] = 1;
+    st->moved_pins += vptr[u + 1] - vptr[u];
+    for (int64_t q = vptr[u]; q < vptr[u + 1]; ++q) touched[vnets[q]] = 1;
+  }
+  memset(eligible, 0, (size_t)n);
+  for (int32_t e = 0; e < m; ++e) {
+    if (!touched[e]) continue;
+    st->touched_nets += 1;
+    for (int64_t q = eptr[e]; q < eptr[e + 1]; ++q) eligible[pins[q]] = 1;
+  }
+  or_pin_counts(m, eptr, pins, part, k, phi);
+  or_connectivity(m, k, phi, lambda, bits);
+  or_block_weights(n, c, part, k, W);
+  st->km1_after = or_km1(m, w, lambda);
+  st->km1_delta = km1_before - st->km1_after;
+  st->max_block_weight = W[0];
+  for (int32_t i = 1; i < k; ++i) if (W[i] > st->max_block_weight) st->max_block_weight = W[i];
+  free(part2); free(elig2); free(sgain); free(seq); free(mu); free(mt); free(gains);
+  free(touched); free(phi); free(lambda); free(bits); free(W);
+  return OR_OK;
+}
+
+/* Refinement driver of the monotone variant: as or_refine with
+ * or_lp_round_exact in place of or_lp_round. */
+int or_refine_exact(int32_t n, int32_t m, const int64_t* eptr, const int32_t* pins,
+                    const int32_t* c, const int32_t* w, int32_t k, int64_t lmax,
+                    int32_t rounds, int32_t* part, or_round_stats* stats, int64_t* km1_out) {
+  int64_t* vptr = (int64_t*)malloc(sizeof(int64_t) * ((size_t)n + 1));
+  int64_t P = eptr[m];
+  int32_t* vnets = (int32_t*)malloc(sizeof(int32_t) * (size_t)P);
+  uint8_t* eligible = (uint8_t*)malloc((size_t)n);
+  uint8_t* moved = (uint8_t*)malloc((size_t)n);
+  if (!vptr || !vnets || !eligible || !moved) return OR_ERR_INVALID;
+  or_incidence(n, m, eptr, pins, vptr, vnets);
+  memset(eligible, 1, (size_t)n);
+  int rc = OR_OK;
+  for (int32_t r = 0; r < rounds && rc == OR_OK; ++r)
+    rc = or_lp_round_exact(n, m, eptr, pins, vptr, vnets, c, w, k, lmax, part, eligible, moved,
+                           &stats[r], NULL);
+  if (rc == OR_OK) {
+    int32_t* phi = (int32_t*)malloc(sizeof(int32_t) * (size_t)m * (size_t)k);
+    int32_t* lambda = (int32_t*)malloc(sizeof(int32_t) * (size_t)m);
+    uint32_t* bits = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)m * (size_t)((k + 31) / 32));
+    or_pin_counts(m, eptr, pins, part, k, phi);
+    or_connectivity(m, k, phi, lambda, bits);
+    *km1_out = or_km1(m, w, lambda);
+    free(phi); free(lambda); free(bits);
   }
   free(vptr); free(vnets); free(eligible); free(moved);
   return rc;

@@ -67,6 +67,17 @@ def _load():
         _lib.or_refine.argtypes = [i32, i32, vp, vp, vp, vp, i32, i64, i32, vp,
                                    ctypes.POINTER(RoundStats), ctypes.POINTER(i64)]
         _lib.or_refine.restype = ctypes.c_int
+        _lib.or_move_gains.argtypes = [i32, i32, vp, vp, vp, vp, vp, i32, vp, i32, vp, vp, vp]
+        _lib.or_move_gains.restype = ctypes.c_int
+        _lib.or_best_prefix.argtypes = [i32, vp, i32, i64, vp, i32, vp, vp, vp,
+                                        ctypes.POINTER(i32), ctypes.POINTER(i64)]
+        _lib.or_best_prefix.restype = None
+        _lib.or_lp_round_exact.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, i32, i64, vp, vp,
+                                           vp, ctypes.POINTER(RoundStats), ctypes.POINTER(i64)]
+        _lib.or_lp_round_exact.restype = ctypes.c_int
+        _lib.or_refine_exact.argtypes = [i32, i32, vp, vp, vp, vp, i32, i64, i32, vp,
+                                         ctypes.POINTER(RoundStats), ctypes.POINTER(i64)]
+        _lib.or_refine_exact.restype = ctypes.c_int
     return _lib
 
 
@@ -187,4 +198,62 @@ def refine(h, k, lmax_value, rounds, part):
                            int(lmax_value), rounds, _p(part), stats, ctypes.byref(km))
     if rc != OR_OK:
         raise RuntimeError("oracle refine failed: %d" % rc)
+    return part, [stats[r].as_dict() for r in range(rounds)], int(km.value)
+
+
+def move_gains(h, k, part, move_u, move_to):
+    """Exact gains of the move sequence (move j: move_u[j] -> move_to[j]) as
+    if applied in order, from the partition `part` before the sequence."""
+    part = _c(part, np.int32)
+    mu = _c(move_u, np.int32)
+    mt = _c(move_to, np.int32)
+    t = int(mu.shape[0])
+    g = np.empty(max(t, 1), np.int64)
+    vptr, vnets = h.incidence()
+    rc = _load().or_move_gains(h.n, h.m, _p(h.eptr), _p(h.pins), _p(vptr), _p(vnets), _p(h.w),
+                               k, _p(part), t, _p(mu), _p(mt), _p(g))
+    if rc != OR_OK:
+        raise ValueError("invalid move sequence")
+    return g[:t]
+
+
+def best_prefix(h, k, lmax_value, part, move_u, move_to, gains):
+    """(length, total gain) of the best balanced prefix (ties: longer)."""
+    part = _c(part, np.int32)
+    mu = _c(move_u, np.int32)
+    mt = _c(move_to, np.int32)
+    g = _c(gains, np.int64)
+    ln = ctypes.c_int32(0)
+    bg = ctypes.c_int64(0)
+    _load().or_best_prefix(h.n, _p(h.c), k, int(lmax_value), _p(part), int(mu.shape[0]),
+                           _p(mu), _p(mt), _p(g), ctypes.byref(ln), ctypes.byref(bg))
+    return int(ln.value), int(bg.value)
+
+
+def lp_round_exact(h, k, lmax_value, part, eligible):
+    """One monotone LP round.  Returns (new_part, next_eligible, moved, stats,
+    number of approved moves before the prefix cut)."""
+    part = np.array(part, dtype=np.int32, copy=True)
+    elig = np.array(eligible, dtype=np.uint8, copy=True)
+    moved = np.empty(h.n, np.uint8)
+    st = RoundStats()
+    napp = ctypes.c_int64(0)
+    vptr, vnets = h.incidence()
+    rc = _load().or_lp_round_exact(h.n, h.m, _p(h.eptr), _p(h.pins), _p(vptr), _p(vnets),
+                                   _p(h.c), _p(h.w), k, int(lmax_value), _p(part), _p(elig),
+                                   _p(moved), ctypes.byref(st), ctypes.byref(napp))
+    if rc != OR_OK:
+        raise RuntimeError("oracle lp_round_exact failed: %d" % rc)
+    return part, elig, moved, st.as_dict(), int(napp.value)
+
+
+def refine_exact(h, k, lmax_value, rounds, part):
+    """R monotone rounds.  Returns (final_part, [stats per round], km1)."""
+    part = np.array(part, dtype=np.int32, copy=True)
+    stats = (RoundStats * max(1, rounds))()
+    km = ctypes.c_int64(0)
+    rc = _load().or_refine_exact(h.n, h.m, _p(h.eptr), _p(h.pins), _p(h.c), _p(h.w), k,
+                                 int(lmax_value), rounds, _p(part), stats, ctypes.byref(km))
+    if rc != OR_OK:
+        raise RuntimeError("oracle refine_exact failed: %d" % rc)
     return part, [stats[r].as_dict() for r in range(rounds)], int(km.value)
