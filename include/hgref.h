@@ -342,6 +342,61 @@ hg_status hg_batch_autotune(hg_batch b, int32_t* part_save, int64_t save_elems,
  * the built-in defaults. */
 hg_status hg_batch_get_schedule(hg_batch b, hg_schedule* sched);
 
+/* ------------------------------------------------------------ move sequences
+ * Exact gains of an ordered sequence of moves (section "Parallel Gain
+ * Calculation", subsection "Parallel Gain Recalculation" and its Lemma): the
+ * km1 decrease of each move as if the moves were performed one after the
+ * other in the given order, computed in parallel from, per (net, block), the
+ * largest index of a move out of the block, the smallest index of a move into
+ * it and the number of moves out of it.  The best prefix of such a sequence
+ * (section "Direct k-way FM": a prefix sum and a reduction).  And the
+ * monotone label-propagation round built from both.  Each vertex may appear
+ * at most once in a sequence (as in one FM round). */
+
+/* Bytes of the workspace of the calls below for a graph with n vertices and
+ * m nets at k blocks: three int32 per (net, block) cell, sort and scan
+ * buffers.  0 for unsupported arguments.  Any contents are fine on entry. */
+size_t hg_moves_workspace_size(int32_t n, int32_t m, int32_t k);
+
+/* gains[j] (int64, device) = km1 before move j minus km1 after it, when the
+ * moves 0..j are applied in order to the partition `part` whose pin counts
+ * are `phi` (the state BEFORE the sequence; neither is changed).  Move j
+ * takes vertex move_u[j] from part[move_u[j]] to block move_to[j].  A vertex
+ * twice, a target outside [0,k) or equal to the vertex's block raises the
+ * device flag that hg_sync_status reports (such moves contribute nothing). */
+hg_status hg_move_gains(hg_graph g, int32_t k, const int32_t* part, const int32_t* phi,
+                        int32_t t, const int32_t* move_u, const int32_t* move_to,
+                        int64_t* gains, void* workspace, size_t ws_bytes, void* stream);
+
+/* The best prefix of a move sequence: the length p in [0, t] with the largest
+ * total gains[0] + ... + gains[p-1] among the prefixes after which every block
+ * weight (block_w, the weights before the sequence, plus the moves' vertex
+ * weights) is at most max_block_w; the empty prefix always qualifies; ties go
+ * to the longer prefix.  best_len[0] (int32) and best_gain[0] (int64) are
+ * device outputs.  One workgroup; k <= 256. */
+hg_status hg_best_prefix(hg_graph g, int32_t k, int64_t max_block_w, const int32_t* part,
+                         const int64_t* block_w, int32_t t, const int32_t* move_u,
+                         const int32_t* move_to, const int64_t* gains, int32_t* best_len,
+                         int64_t* best_gain, void* workspace, size_t ws_bytes, void* stream);
+
+/* One monotone label-propagation round: candidates and approval as in
+ * hg_lp_round, then the approved moves, ordered by (select gain desc, vertex
+ * id asc), get their exact gains in that order (hg_move_gains) and only the
+ * prefix with the largest total gain is applied (ties: the longer).  Every
+ * prefix of approved moves respects L_max, so km1 never increases; the round
+ * record's `approved` is the applied prefix and km1_delta its total exact
+ * gain.  Arguments as hg_lp_round plus the move workspace. */
+hg_status hg_lp_round_exact(hg_graph g, int32_t k, int64_t max_block_w, int32_t* part,
+                            int32_t* phi, uint32_t* netstate, int64_t* block_w, uint8_t* eligible,
+                            uint8_t* moved, int64_t* km1, hg_round_stats* stats, void* workspace,
+                            size_t ws_bytes, void* stream);
+
+/* hg_refine with monotone rounds (direct launches). */
+hg_status hg_refine_exact(hg_graph g, int32_t k, double eps, int32_t rounds, int32_t* part,
+                          int32_t* phi, uint32_t* netstate, int64_t* block_w, uint8_t* eligible,
+                          hg_round_stats* stats, int64_t* km1_out, void* workspace,
+                          size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------------------ serving
  * A request server.  Refinement jobs arrive over time.  Each is admitted
  * into a caller-provided device arena once its exact footprint

@@ -37,6 +37,7 @@ enum : int {
   kErrDuplicate = 8,   // a vertex twice in one net
   kErrPart = 16,       // partition id outside [0,k)
   kErrNetWeight = 32,  // total net weight >= 2^31
+  kErrMoves = 64,      // a move sequence names a vertex twice, a bad target or its own block
 };
 
 // Same-address global atomics serialize (tens of ns each), so every
@@ -56,6 +57,7 @@ enum CounterId : int {
   kCtrDeltaCheck,
   kCtrActivePins,
   kCtrTouched,
+  kCtrMarked,       // approved moves marked for a monotone round (before the prefix cut)
   kNumCounters
 };
 
@@ -127,6 +129,7 @@ struct InstDesc {
   int* err_flags;
   unsigned long long* red;
   long long* bw_slots;           // kSlots x k block-weight deltas of a round's moves
+  unsigned char* appr;           // monotone rounds: approve marks moves here instead of applying
 };
 
 // One workgroup's share of a batched launch: instance, and the units it
@@ -278,6 +281,7 @@ namespace hg {
 
 // ---- error reporting (hg_last_error) ----
 hg_status fail(hg_status code, const char* fmt, ...);
+size_t moves_workspace_size(long long n, long long m, int k);
 hg_status hip_fail(hipError_t e, const char* what);
 hg_status check_k(hg_graph_s* g, int k);
 

@@ -51,6 +51,9 @@ int group_lanes(int k);
 
 // Enqueue one round; the round record goes to stats[round] of every instance.
 hipError_t launch_round(const RoundPlan& plan, int round, hipStream_t s, hipEvent_t* marks);
+// Its two halves: select .. approve (+ apply), then finalize and the record.
+hipError_t launch_round_front(const RoundPlan& plan, hipStream_t s, hipEvent_t* marks);
+hipError_t launch_round_back(const RoundPlan& plan, int round, hipStream_t s, hipEvent_t* marks);
 void single_round_plan(const InstDesc& d, RoundPlan& plan);
 
 // Pin counts, block weights and (want_km1) km1 of every instance; with

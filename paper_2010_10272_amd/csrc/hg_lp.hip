@@ -697,9 +697,15 @@ __global__ __launch_bounds__(kBlock) void k_approve_apply(Launch L) {
   __syncthreads();
   const int count = (int)s_count;
   long long delta = 0, moved_pins = 0, approved = 0;
-  if (count > 0)
+  if (count > 0 && D.appr) {
+    // monotone round: only mark; the moves are ordered, re-gained and cut later
+    for (int i = threadIdx.x; i < count; i += kBlock) D.appr[s_list[i]] = 1;
+    if (threadIdx.x == 0)
+      atomicAdd(&D.ctr->slot[kCtrMarked][blockIdx.x % kSlots], (unsigned long long)count);
+  } else if (count > 0) {
     apply_list(D, s_list, s_tgt, count, s_from, s_beg, s_off, s_tmp, s_dW, delta, moved_pins,
                approved);
+  }
   __syncthreads();
   // block-weight deltas go to one of kSlots partial rows (a single row
   // would serialize one atomic per tile on each of the k addresses); the
@@ -865,6 +871,14 @@ FinalizeKernel finalize_kernel_g(int G) {
 // Launch one round of every kernel for a batch (items per kernel kind) or a
 // single instance (L.descs == nullptr).
 hipError_t launch_round(const RoundPlan& plan, int round, hipStream_t s, hipEvent_t* marks) {
+  hipError_t e = launch_round_front(plan, s, marks);
+  if (e != hipSuccess) return e;
+  return launch_round_back(plan, round, s, marks);
+}
+
+// Select, thresholds, tiles and approve (+ apply unless the descriptor asks
+// for marks only).
+hipError_t launch_round_front(const RoundPlan& plan, hipStream_t s, hipEvent_t* marks) {
   if (marks) (void)hipEventRecord(marks[0], s);
   for (const PlanLaunch& pl : plan.select)
     hipLaunchKernelGGL((SelectKernel)pl.kernel, dim3(pl.grid), dim3(kBlock), 0, s, pl.L);
@@ -879,6 +893,11 @@ hipError_t launch_round(const RoundPlan& plan, int round, hipStream_t s, hipEven
   hipLaunchKernelGGL(k_tilescan, dim3(plan.blocks.grid), dim3(kBlock), 0, s, plan.blocks.L);
   hipLaunchKernelGGL(k_approve_apply, dim3(plan.approve.grid), dim3(kBlock), 0, s,
                      plan.approve.L);
+  return hipGetLastError();
+}
+
+// Finalize (touched nets, next eligible set) and the round record.
+hipError_t launch_round_back(const RoundPlan& plan, int round, hipStream_t s, hipEvent_t* marks) {
   if (marks) (void)hipEventRecord(marks[2], s);
   for (const PlanLaunch& pl : plan.finalize)
     hipLaunchKernelGGL((FinalizeKernel)pl.kernel, dim3(pl.grid), dim3(kBlock), 0, s, pl.L);

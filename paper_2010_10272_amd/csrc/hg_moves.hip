@@ -1,0 +1,869 @@
+// hg_moves.hip -- move sequences: exact gains of an ordered sequence of moves
+// (section "Parallel Gain Calculation", subsection "Parallel Gain
+// Recalculation" and its Lemma), the best prefix of such a sequence (section
+// "Direct k-way FM", second phase), and the monotone label-propagation round
+// built from them.
+//
+// Exact gains.  Move j (1-based index J) takes u_j from block a to block b.
+// For every (net, block) cell touched by the sequence the kernels gather
+//   out_max(e, i)  the largest J moving a pin of e out of i   (0 if none)
+//   in_min(e, i)   the smallest J moving a pin of e into i     (INT_MAX if none)
+//   out_cnt(e, i)  how many moves take a pin of e out of i
+// with integer atomics (max, min, add: order-independent), and then, per move
+// and incident net e, Psi(e, i) = Phi(e, i) - out_cnt(e, i) and the Lemma:
+//   Phi(e, a) = 1 just before move J  iff  Psi(e,a) = 0, out_max(e,a) = J,
+//                                          in_min(e,a) > J
+//   Phi(e, b) = 0 just before move J  iff  Psi(e,b) = 0, in_min(e,b) = J,
+//                                          out_max(e,b) < J
+// so gain_J = w({e : first}) - w({e : second}).  Only cells of nets incident
+// to a mover are written (an init pass sets them first), so the m x k arrays
+// never need a full clear.
+//
+// Monotone round.  Select and approval run as in a plain round, but approve
+// only marks the approved moves.  A stable radix sort orders them by (select
+// gain desc, vertex id asc) -- the keys of all n vertices, unmarked ones last
+// -- their exact gains in that order come from the kernels above, a prefix
+// scan picks the prefix with the largest total (ties: the longer), and only
+// that prefix is applied; finalize and the round record follow as usual.
+// Every prefix of approved moves respects L_max (the approval budgets each
+// target for all of its moves; moves out of a block only lower it), so the
+// cut needs no balance test, and km1 never increases.
+#include <limits.h>
+#include <string.h>
+
+#include "hg_device.h"
+#include "hg_internal.h"
+#include "hg_lp.h"
+
+namespace hg {
+namespace {
+
+constexpr int kSortTile = kTile;            // items per radix-sort workgroup (4 per thread)
+constexpr int kDigits = 256;                // 8-bit digits
+constexpr int kPrefixChunk = kTile;         // moves per prefix-scan workgroup
+
+// Layout of the caller's move-sequence workspace.
+struct MovesLayout {
+  size_t out_max, in_min, out_cnt, seen, appr, key[2], val[2], hist, dtot, gains, csum, coff,
+      cbest_v, cbest_i, best, total;
+  int sort_tiles, chunks;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+MovesLayout moves_layout(long long n, long long m, int k) {
+  MovesLayout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off = align256(off + bytes);
+    return at;
+  };
+  const size_t cells = (size_t)m * (size_t)k;
+  L.sort_tiles = (int)((n + kSortTile - 1) / kSortTile);
+  L.chunks = (int)((n + kPrefixChunk - 1) / kPrefixChunk);
+  L.out_max = take(sizeof(int) * cells);
+  L.in_min = take(sizeof(int) * cells);
+  L.out_cnt = take(sizeof(int) * cells);
+  L.seen = take(sizeof(int) * (size_t)n);
+  L.appr = take((size_t)n);
+  for (int i = 0; i < 2; ++i) {
+    L.key[i] = take(sizeof(unsigned) * (size_t)n);
+    L.val[i] = take(sizeof(int) * (size_t)n);
+  }
+  L.hist = take(sizeof(unsigned) * (size_t)kDigits * L.sort_tiles);
+  L.dtot = take(sizeof(unsigned) * kDigits);
+  L.gains = take(sizeof(long long) * (size_t)n);
+  L.csum = take(sizeof(long long) * (size_t)L.chunks);
+  L.coff = take(sizeof(long long) * (size_t)L.chunks);
+  L.cbest_v = take(sizeof(long long) * (size_t)L.chunks);
+  L.cbest_i = take(sizeof(int) * (size_t)L.chunks);
+  L.best = take(sizeof(long long) * 2);
+  L.total = off;
+  return L;
+}
+
+// A move sequence as the kernels read it.  Move j (0-based) moves u = mu[j]
+// from part[u] to mt[j], or -- sorted monotone rounds -- to the target in
+// cand[u].  The length is t, or the sum of the kCtrMarked slots when
+// t_slots is set (known only on the device).
+struct Seq {
+  const int* mu;
+  const int* mt;                 // null: target from cand
+  const long long* cand;
+  int t;
+  const unsigned long long* t_slots;
+  const int* part;
+  const int* phi;
+  const long long* vptr;
+  const int* vnets;
+  const int* ewgt;
+  const int* vwgt;
+  int n, k;
+  int* out_max;
+  int* in_min;
+  int* out_cnt;
+  int* seen;
+  int* err_flags;
+};
+
+__device__ __forceinline__ int seq_len(const Seq& S) {
+  if (!S.t_slots) return S.t;
+  // the sum of the kSlots partial counts (every thread reads them; small)
+  long long t = 0;
+  for (int i = 0; i < kSlots; ++i) t += (long long)S.t_slots[i];
+  return (int)t;
+}
+
+// Source and target of move j, or false for a move the checks reject.
+__device__ __forceinline__ bool seq_move(const Seq& S, int j, int& u, int& a, int& b) {
+  u = S.mu[j];
+  if ((unsigned)u >= (unsigned)S.n) return false;
+  b = S.mt ? S.mt[j] : (int)(S.cand[u] & 0xffffffffLL);
+  a = S.part[u];
+  return (unsigned)b < (unsigned)S.k && (unsigned)a < (unsigned)S.k && a != b;
+}
+
+// Every incidence (move j, net e) of the workgroup's kBlock moves, spread
+// over all threads (prefix sum of the movers' degrees, owner by binary
+// search in LDS).  f(j, u, a, b, e) is called once per incidence.
+template <typename F>
+__device__ void for_incidences(const Seq& S, int t, F f) {
+  __shared__ long long s_beg[kBlock];
+  __shared__ int s_off[kBlock + 1];
+  __shared__ int s_u[kBlock], s_a[kBlock], s_b[kBlock];
+  __shared__ long long s_tmp[kBlock / kWave];
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  int u = -1, a = 0, b = 0;
+  long long len = 0, beg = 0;
+  if (j < t && seq_move(S, j, u, a, b)) {
+    beg = S.vptr[u];
+    len = S.vptr[u + 1] - beg;
+  } else {
+    u = -1;
+  }
+  long long total;
+  const long long off = block_excl_scan64(len, s_tmp, &total);
+  s_off[threadIdx.x] = (int)off;
+  s_beg[threadIdx.x] = beg;
+  s_u[threadIdx.x] = u;
+  s_a[threadIdx.x] = a;
+  s_b[threadIdx.x] = b;
+  __syncthreads();
+  for (long long x = threadIdx.x; x < total; x += kBlock) {
+    int lo = 0, hi = kBlock - 1;   // owner: last slot with s_off <= x
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_off[mid] <= x) lo = mid; else hi = mid - 1;
+    }
+    // slots without a move have length 0, so the owner always holds one
+    const int e = S.vnets[s_beg[lo] + (x - s_off[lo])];
+    f(blockIdx.x * kBlock + lo, s_u[lo], s_a[lo], s_b[lo], e);
+  }
+}
+
+// Checks of an explicit sequence: vertex and target in range, target !=
+// source, no vertex twice (seen[u] claims u for its first move).
+__global__ __launch_bounds__(kBlock) void k_seq_check(Seq S) {
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= S.t) return;
+  int u, a, b;
+  if (!seq_move(S, j, u, a, b)) {
+    atomicOr(S.err_flags, kErrMoves);
+    return;
+  }
+  if (atomicCAS(&S.seen[u], 0, j + 1) != 0) atomicOr(S.err_flags, kErrMoves);
+}
+
+__global__ __launch_bounds__(kBlock) void k_seq_clear(Seq S) {
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= S.t) return;
+  const int u = S.mu[j];
+  if ((unsigned)u < (unsigned)S.n) S.seen[u] = 0;
+}
+
+// Cells (e, a) and (e, b) of every incidence start empty.
+__global__ __launch_bounds__(kBlock) void k_seq_init(Seq S) {
+  const int t = seq_len(S);
+  if ((int)(blockIdx.x * kBlock) >= t) return;
+  for_incidences(S, t, [&](int, int, int a, int b, int e) {
+    const size_t ca = (size_t)e * S.k + a, cb = (size_t)e * S.k + b;
+    S.out_max[ca] = 0;
+    S.in_min[ca] = INT_MAX;
+    S.out_cnt[ca] = 0;
+    S.out_max[cb] = 0;
+    S.in_min[cb] = INT_MAX;
+    S.out_cnt[cb] = 0;
+  });
+}
+
+__global__ __launch_bounds__(kBlock) void k_seq_collect(Seq S) {
+  const int t = seq_len(S);
+  if ((int)(blockIdx.x * kBlock) >= t) return;
+  for_incidences(S, t, [&](int j, int, int a, int b, int e) {
+    const size_t ca = (size_t)e * S.k + a, cb = (size_t)e * S.k + b;
+    atomicMax(&S.out_max[ca], j + 1);
+    atomicAdd(&S.out_cnt[ca], 1);
+    atomicMin(&S.in_min[cb], j + 1);
+  });
+}
+
+// gains[j] = exact gain of move j (the Lemma).
+__global__ __launch_bounds__(kBlock) void k_seq_gains(Seq S, long long* gains) {
+  __shared__ long long s_gain[kBlock];
+  const int t = seq_len(S);
+  if ((int)(blockIdx.x * kBlock) >= t) return;
+  s_gain[threadIdx.x] = 0;
+  __syncthreads();
+  for_incidences(S, t, [&](int j, int, int a, int b, int e) {
+    const int J = j + 1;
+    const size_t ca = (size_t)e * S.k + a, cb = (size_t)e * S.k + b;
+    const bool last_out = S.phi[ca] - S.out_cnt[ca] == 0 && S.out_max[ca] == J &&
+                          S.in_min[ca] > J;
+    const bool first_in = S.phi[cb] - S.out_cnt[cb] == 0 && S.in_min[cb] == J &&
+                          S.out_max[cb] < J;
+    if (last_out != first_in) {
+      const long long w = S.ewgt ? S.ewgt[e] : 1;
+      atomicAdd((unsigned long long*)&s_gain[j - blockIdx.x * kBlock],
+                (unsigned long long)(last_out ? w : -w));
+    }
+  });
+  __syncthreads();
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j < t) gains[j] = s_gain[threadIdx.x];
+}
+
+// ------------------------------------------------------------ radix sort
+// Stable LSD radix sort of (key, value) pairs, 8 bits per pass.
+
+struct SortPass {
+  const unsigned* key_in;
+  const int* val_in;
+  unsigned* key_out;
+  int* val_out;
+  unsigned* hist;   // [kDigits][tiles], digit-major
+  unsigned* dtot;   // [kDigits]
+  int n, tiles, shift;
+};
+
+// Pass input of a monotone round: key = ~gain for marked vertices (so that
+// ascending keys are descending gains), all-ones for the rest; value = id.
+// The marks are cleared for the next round.
+__global__ __launch_bounds__(kBlock) void k_sort_keys(int n, const long long* cand,
+                                                      unsigned char* appr, unsigned* key,
+                                                      int* val) {
+  const long long u = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (u >= n) return;
+  unsigned k = 0xffffffffu;
+  if (appr[u]) {
+    const int g = (int)(cand[u] >> 32);   // select gain, >= 0
+    k = 0x7fffffffu - (unsigned)g;
+    appr[u] = 0;
+  }
+  key[u] = k;
+  val[u] = (int)u;
+}
+
+__device__ __forceinline__ unsigned digit_of(unsigned key, int shift) {
+  return (key >> shift) & (kDigits - 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_sort_hist(SortPass P) {
+  __shared__ unsigned s_h[kDigits];
+  s_h[threadIdx.x] = 0;
+  __syncthreads();
+  const long long base = (long long)blockIdx.x * kSortTile;
+  for (int r = 0; r < kSortTile / kBlock; ++r) {
+    const long long i = base + r * kBlock + threadIdx.x;
+    if (i < P.n) atomicAdd(&s_h[digit_of(P.key_in[i], P.shift)], 1u);
+  }
+  __syncthreads();
+  P.hist[(size_t)threadIdx.x * P.tiles + blockIdx.x] = s_h[threadIdx.x];
+}
+
+// One workgroup per digit: exclusive scan of its per-tile counts; total.
+__global__ __launch_bounds__(kBlock) void k_sort_scan(SortPass P) {
+  __shared__ long long s_tmp[kBlock / kWave];
+  unsigned* row = P.hist + (size_t)blockIdx.x * P.tiles;
+  long long carry = 0;
+  for (int b = 0; b < P.tiles; b += kBlock) {
+    const int i = b + threadIdx.x;
+    const long long v = i < P.tiles ? row[i] : 0;
+    long long tot;
+    const long long ex = block_excl_scan64(v, s_tmp, &tot);
+    if (i < P.tiles) row[i] = (unsigned)(carry + ex);
+    carry += tot;
+  }
+  if (threadIdx.x == 0) P.dtot[blockIdx.x] = (unsigned)carry;
+}
+
+// Stable scatter of one tile: items r*kBlock + threadIdx.x for r = 0..3 in
+// order; ranks among equal digits by wave ballots, waves and rounds in order.
+__global__ __launch_bounds__(kBlock) void k_sort_scatter(SortPass P) {
+  __shared__ unsigned s_base[kDigits];
+  __shared__ unsigned s_wcnt[kBlock / kWave][kDigits];
+  __shared__ long long s_tmp[kBlock / kWave];
+  // digit bases: digits below d in full, plus this digit in earlier tiles
+  long long tot;
+  const long long below = block_excl_scan64(P.dtot[threadIdx.x], s_tmp, &tot);
+  s_base[threadIdx.x] = (unsigned)below + P.hist[(size_t)threadIdx.x * P.tiles + blockIdx.x];
+  for (int w = 0; w < kBlock / kWave; ++w) s_wcnt[w][threadIdx.x] = 0;
+  __syncthreads();
+  const int lane = lane_id(), wv = threadIdx.x / kWave;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  const long long base = (long long)blockIdx.x * kSortTile;
+  for (int r = 0; r < kSortTile / kBlock; ++r) {
+    const long long i = base + r * kBlock + threadIdx.x;
+    const bool live = i < P.n;
+    unsigned key = 0;
+    int val = 0;
+    unsigned d = 0;
+    if (live) {
+      key = P.key_in[i];
+      val = P.val_in[i];
+      d = digit_of(key, P.shift);
+    }
+    // lanes of this wave with the same digit
+    unsigned long long peers = __ballot(live);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const unsigned long long ones = __ballot(live && ((d >> bit) & 1u));
+      peers &= ((d >> bit) & 1u) ? ones : ~ones;
+    }
+    const unsigned rank = (unsigned)__popcll(peers & lt);
+    if (live && rank == 0) s_wcnt[wv][d] = (unsigned)__popcll(peers);
+    __syncthreads();
+    if (live) {
+      unsigned pos = s_base[d] + rank;
+      for (int w = 0; w < wv; ++w) pos += s_wcnt[w][d];
+      P.key_out[pos] = key;
+      P.val_out[pos] = val;
+    }
+    __syncthreads();
+    unsigned add = 0;
+    for (int w = 0; w < kBlock / kWave; ++w) {
+      add += s_wcnt[w][threadIdx.x];
+      s_wcnt[w][threadIdx.x] = 0;
+    }
+    s_base[threadIdx.x] += add;
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ best prefix
+
+// Per chunk of moves: sum of the exact gains.
+__global__ __launch_bounds__(kBlock) void k_prefix_sums(Seq S, const long long* gains,
+                                                        long long* csum) {
+  __shared__ long long s_tmp[kBlock / kWave];
+  const int t = seq_len(S);
+  const long long base = (long long)blockIdx.x * kPrefixChunk;
+  long long v = 0;
+  for (int r = 0; r < kPrefixChunk / kBlock; ++r) {
+    const long long j = base + r * kBlock + threadIdx.x;
+    if (j < t) v += gains[j];
+  }
+  v = block_sum64(v, s_tmp);
+  if (threadIdx.x == 0) csum[blockIdx.x] = v;
+}
+
+// One workgroup: exclusive scan of the chunk sums.
+__global__ __launch_bounds__(kBlock) void k_prefix_top(const long long* csum, long long* coff,
+                                                       int chunks) {
+  __shared__ long long s_tmp[kBlock / kWave];
+  long long carry = 0;
+  for (int b = 0; b < chunks; b += kBlock) {
+    const int i = b + threadIdx.x;
+    const long long v = i < chunks ? csum[i] : 0;
+    long long tot;
+    const long long ex = block_excl_scan64(v, s_tmp, &tot);
+    if (i < chunks) coff[i] = carry + ex;
+    carry += tot;
+  }
+}
+
+// Best (total, length) of the prefixes ending in a chunk; ties to the longer.
+__device__ __forceinline__ bool better(long long v, int p, long long bv, int bp) {
+  return v > bv || (v == bv && p > bp);
+}
+
+__global__ __launch_bounds__(kBlock) void k_prefix_best(Seq S, const long long* gains,
+                                                        const long long* coff,
+                                                        long long* cbest_v, int* cbest_i) {
+  __shared__ long long s_tmp[kBlock / kWave];
+  __shared__ long long s_bv[kBlock / kWave];
+  __shared__ int s_bp[kBlock / kWave];
+  const int t = seq_len(S);
+  const long long base = (long long)blockIdx.x * kPrefixChunk;
+  long long carry = coff[blockIdx.x];
+  long long bv = LLONG_MIN;
+  int bp = -1;
+  for (int r = 0; r < kPrefixChunk / kBlock; ++r) {
+    const long long j = base + r * kBlock + threadIdx.x;
+    const long long g = j < t ? gains[j] : 0;
+    long long tot;
+    const long long incl = block_excl_scan64(g, s_tmp, &tot) + g;
+    if (j < t && better(carry + incl, (int)j + 1, bv, bp)) {
+      bv = carry + incl;
+      bp = (int)j + 1;
+    }
+    carry += tot;
+  }
+  // workgroup argmax
+  const int lane = lane_id(), wv = threadIdx.x / kWave;
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    const long long ov = __shfl_xor(bv, o);
+    const int op = __shfl_xor(bp, o);
+    if (better(ov, op, bv, bp)) {
+      bv = ov;
+      bp = op;
+    }
+  }
+  if (lane == 0) {
+    s_bv[wv] = bv;
+    s_bp[wv] = bp;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kBlock / kWave; ++w)
+      if (better(s_bv[w], s_bp[w], bv, bp)) {
+        bv = s_bv[w];
+        bp = s_bp[w];
+      }
+    cbest_v[blockIdx.x] = bv;
+    cbest_i[blockIdx.x] = bp;
+  }
+}
+
+// One workgroup: the best over all chunks and the empty prefix -> best[0]
+// (total), best[1] (length).
+__global__ __launch_bounds__(kBlock) void k_prefix_final(const long long* cbest_v,
+                                                         const int* cbest_i, int chunks,
+                                                         long long* best) {
+  __shared__ long long s_bv[kBlock / kWave];
+  __shared__ int s_bp[kBlock / kWave];
+  long long bv = 0;
+  int bp = 0;   // the empty prefix
+  for (int i = threadIdx.x; i < chunks; i += kBlock)
+    if (cbest_i[i] > 0 && better(cbest_v[i], cbest_i[i], bv, bp)) {
+      bv = cbest_v[i];
+      bp = cbest_i[i];
+    }
+  const int lane = lane_id(), wv = threadIdx.x / kWave;
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    const long long ov = __shfl_xor(bv, o);
+    const int op = __shfl_xor(bp, o);
+    if (better(ov, op, bv, bp)) {
+      bv = ov;
+      bp = op;
+    }
+  }
+  if (lane == 0) {
+    s_bv[wv] = bv;
+    s_bp[wv] = bp;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kBlock / kWave; ++w)
+      if (better(s_bv[w], s_bp[w], bv, bp)) {
+        bv = s_bv[w];
+        bp = s_bp[w];
+      }
+    best[0] = bv;
+    best[1] = bp;
+  }
+}
+
+// Apply moves [0, best[1]) of a sorted monotone-round sequence: part, moved,
+// Phi (integer atomics; their old values give the attributed km1 change),
+// touched nets, block-weight deltas (slots), counters.
+__global__ __launch_bounds__(kBlock) void k_apply_prefix(Seq S, const long long* best,
+                                                         InstDesc D) {
+  __shared__ unsigned long long s_dW[HG_MAX_K];
+  __shared__ long long s_tmp2[kBlock / kWave];
+  const int p = (int)best[1];
+  if ((int)(blockIdx.x * kBlock) >= p) return;
+  const int k = D.k;
+  for (int i = threadIdx.x; i < k; i += kBlock) s_dW[i] = 0;
+  __syncthreads();
+  long long delta = 0, moved_pins = 0, approved = 0;
+  {
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    int u, a, b;
+    if (j < p && seq_move(S, j, u, a, b)) {
+      const long long cu = D.vwgt ? D.vwgt[u] : 1;
+      atomicAdd(&s_dW[b], (unsigned long long)cu);
+      atomicAdd(&s_dW[a], (unsigned long long)(-cu));
+      approved = 1;
+      moved_pins = D.vptr[u + 1] - D.vptr[u];
+      if (D.moved) D.moved[u] = 1;
+    }
+  }
+  // part is read by for_incidences (source blocks): update it only after
+  for_incidences(S, p, [&](int, int, int a, int b, int e) {
+    const int oa = atomicSub(&D.phi[(long long)e * k + a], 1);
+    const int ot = atomicAdd(&D.phi[(long long)e * k + b], 1);
+    if (oa == 1 || ot == 0) {
+      const int w = D.ewgt ? D.ewgt[e] : 1;
+      if (oa == 1) delta += w;
+      if (ot == 0) delta -= w;
+    }
+    D.touched[e] = 1;
+  });
+  __syncthreads();
+  {
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    int u, a, b;
+    if (j < p && seq_move(S, j, u, a, b)) D.part[u] = b;
+  }
+  long long* my_dw = D.bw_slots + (size_t)(blockIdx.x % kSlots) * k;
+  for (int i = threadIdx.x; i < k; i += kBlock)
+    if (s_dW[i]) atomicAdd((unsigned long long*)&my_dw[i], s_dW[i]);
+  delta = block_sum64(delta, s_tmp2);
+  moved_pins = block_sum64(moved_pins, s_tmp2);
+  approved = block_sum64(approved, s_tmp2);
+  if (threadIdx.x == 0) {
+    const int sl = blockIdx.x % kSlots;
+    if (delta) atomicAdd(&D.ctr->slot[kCtrDeltaAttr][sl], (unsigned long long)delta);
+    if (moved_pins) atomicAdd(&D.ctr->slot[kCtrMovedPins][sl], (unsigned long long)moved_pins);
+    if (approved) atomicAdd(&D.ctr->slot[kCtrApproved][sl], (unsigned long long)approved);
+  }
+}
+
+// Best balanced prefix of an explicit sequence (one workgroup, k <= 256):
+// tiles of kBlock moves; thread i follows the weight of block i through the
+// tile's moves in order and records when it crosses L_max; scans of those
+// crossings and of the gains give, per prefix, the number of overloaded
+// blocks and the total gain.  out[0] = total, out[1] = length.
+__global__ __launch_bounds__(kBlock) void k_best_prefix_balanced(Seq S, long long lmax,
+                                                                 const long long* block_w,
+                                                                 const long long* gains,
+                                                                 long long* out) {
+  __shared__ int s_a[kBlock], s_b[kBlock], s_tr[kBlock];
+  __shared__ long long s_c[kBlock];
+  __shared__ long long s_tmp[kBlock / kWave];
+  __shared__ long long s_bv[kBlock / kWave];
+  __shared__ int s_bp[kBlock / kWave];
+  const int k = S.k, t = S.t, i = threadIdx.x;
+  long long W = i < k ? block_w[i] : 0;
+  long long over0, tmp;
+  over0 = block_excl_scan64(i < k && W > lmax ? 1 : 0, s_tmp, &tmp);
+  over0 = tmp;
+  long long over = over0, total = 0, bv = 0;
+  int bp = 0;
+  for (int base = 0; base < t; base += kBlock) {
+    const int j = base + i;
+    int u = 0, a = -1, b = -1;
+    long long c = 0;
+    if (j < t && seq_move(S, j, u, a, b)) c = S.vwgt ? S.vwgt[u] : 1;
+    s_a[i] = a;
+    s_b[i] = b;
+    s_c[i] = c;
+    s_tr[i] = 0;
+    __syncthreads();
+    const int cnt = t - base < kBlock ? t - base : kBlock;
+    if (i < k) {
+      for (int q = 0; q < cnt; ++q) {
+        if (s_a[q] == i) {
+          const bool was = W > lmax;
+          W -= s_c[q];
+          if (was != (W > lmax)) atomicAdd(&s_tr[q], was ? -1 : 1);
+        }
+        if (s_b[q] == i) {
+          const bool was = W > lmax;
+          W += s_c[q];
+          if (was != (W > lmax)) atomicAdd(&s_tr[q], was ? -1 : 1);
+        }
+      }
+    }
+    __syncthreads();
+    const long long g = j < t ? gains[j] : 0;
+    long long tg, tt;
+    const long long gi = block_excl_scan64(g, s_tmp, &tg) + g;
+    const long long oi = block_excl_scan64(s_tr[i], s_tmp, &tt) + s_tr[i];
+    long long mv = LLONG_MIN;
+    int mp = -1;
+    if (j < t && over + oi == 0) {
+      mv = total + gi;
+      mp = j + 1;
+    }
+    // workgroup argmax of this tile
+    const int lane = lane_id(), wv = i / kWave;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+      const long long ov = __shfl_xor(mv, o);
+      const int op = __shfl_xor(mp, o);
+      if (better(ov, op, mv, mp)) {
+        mv = ov;
+        mp = op;
+      }
+    }
+    if (lane == 0) {
+      s_bv[wv] = mv;
+      s_bp[wv] = mp;
+    }
+    __syncthreads();
+    for (int w = 0; w < kBlock / kWave; ++w)
+      if (s_bp[w] > 0 && better(s_bv[w], s_bp[w], bv, bp)) {
+        bv = s_bv[w];
+        bp = s_bp[w];
+      }
+    total += tg;
+    over += tt;
+    __syncthreads();
+  }
+  if (i == 0) {
+    out[0] = bv;
+    out[1] = bp;
+  }
+}
+
+__global__ void k_copy_best(const long long* best, int* best_len, long long* best_gain) {
+  if (threadIdx.x == 0) {
+    if (best_len) *best_len = (int)best[1];
+    if (best_gain) *best_gain = best[0];
+  }
+}
+
+}  // namespace
+
+struct MovesLayoutBest {
+  size_t best;
+};
+
+// ------------------------------------------------------------ host side
+
+size_t moves_workspace_size(long long n, long long m, int k) { return moves_layout(n, m, k).total; }
+
+MovesLayoutBest moves_best_slot(long long n, long long m, int k) {
+  MovesLayoutBest b;
+  b.best = moves_layout(n, m, k).best;
+  return b;
+}
+
+static Seq make_seq(hg_graph_s* g, int k, char* ws, const MovesLayout& L, const int* part,
+                    const int* phi, const int* mu, const int* mt, int t) {
+  Seq S;
+  memset(&S, 0, sizeof(S));
+  S.mu = mu;
+  S.mt = mt;
+  S.t = t;
+  S.part = part;
+  S.phi = phi;
+  S.vptr = g->vptr;
+  S.vnets = g->vnets;
+  S.ewgt = g->ewgt;
+  S.vwgt = g->vwgt;
+  S.n = g->n;
+  S.k = k;
+  S.out_max = (int*)(ws + L.out_max);
+  S.in_min = (int*)(ws + L.in_min);
+  S.out_cnt = (int*)(ws + L.out_cnt);
+  S.seen = (int*)(ws + L.seen);
+  S.err_flags = (int*)(g->ws + g->lay.flags);
+  return S;
+}
+
+static unsigned grid_of(long long items, int per) {
+  long long b = (items + per - 1) / per;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+hipError_t launch_move_gains(hg_graph_s* g, int k, const int* part, const int* phi, int t,
+                             const int* mu, const int* mt, long long* gains, char* ws,
+                             hipStream_t s) {
+  const MovesLayout L = moves_layout(g->n, g->m, k);
+  Seq S = make_seq(g, k, ws, L, part, phi, mu, mt, t);
+  const unsigned grid = grid_of(t, kBlock);
+  // seen[] of the sequence's vertices starts at zero (the workspace may hold
+  // anything), then the checks claim each vertex once
+  hipLaunchKernelGGL(k_seq_clear, dim3(grid), dim3(kBlock), 0, s, S);
+  hipLaunchKernelGGL(k_seq_check, dim3(grid), dim3(kBlock), 0, s, S);
+  hipLaunchKernelGGL(k_seq_init, dim3(grid), dim3(kBlock), 0, s, S);
+  hipLaunchKernelGGL(k_seq_collect, dim3(grid), dim3(kBlock), 0, s, S);
+  hipLaunchKernelGGL(k_seq_gains, dim3(grid), dim3(kBlock), 0, s, S, gains);
+  hipLaunchKernelGGL(k_seq_clear, dim3(grid), dim3(kBlock), 0, s, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_best_prefix(hg_graph_s* g, int k, long long lmax, const int* part,
+                              const long long* block_w, int t, const int* mu, const int* mt,
+                              const long long* gains, long long* out2, int* best_len,
+                              long long* best_gain, hipStream_t s) {
+  MovesLayout L;
+  memset(&L, 0, sizeof(L));
+  Seq S = make_seq(g, k, nullptr, L, part, nullptr, mu, mt, t);
+  S.out_max = S.in_min = S.out_cnt = S.seen = nullptr;
+  hipLaunchKernelGGL(k_best_prefix_balanced, dim3(1), dim3(kBlock), 0, s, S, lmax, block_w, gains,
+                     out2);
+  hipLaunchKernelGGL(k_copy_best, dim3(1), dim3(kWave), 0, s, out2, best_len, best_gain);
+  return hipGetLastError();
+}
+
+// One monotone round of a single instance (see the file comment).
+hipError_t launch_round_exact(hg_graph_s* g, InstDesc d, int round, char* ws, hipStream_t s) {
+  const MovesLayout L = moves_layout(g->n, g->m, d.k);
+  d.appr = (unsigned char*)(ws + L.appr);
+  RoundPlan plan;
+  single_round_plan(d, plan);
+  hipError_t e = fill_u8(d.appr, 0, g->n, s);   // approval marks start cleared
+  if (e == hipSuccess) e = launch_round_front(plan, s, nullptr);
+  if (e != hipSuccess) return e;
+  // order the marked moves: keys of all n vertices, 8-bit passes over the
+  // bits a gain can occupy (gains are at most the largest incident weight)
+  const int n = g->n;
+  hipLaunchKernelGGL(k_sort_keys, dim3(grid_of(n, kBlock)), dim3(kBlock), 0, s, n, d.cand,
+                     d.appr, (unsigned*)(ws + L.key[0]), (int*)(ws + L.val[0]));
+  int bits = 1;
+  while (bits < 31 && (1ll << bits) <= (long long)g->info.max_incident_weight) ++bits;
+  // keys 0x7fffffff - g differ from 0x7fffffff only in the low `bits` bits,
+  // unmarked keys (all ones) in bit 31: sort the low bits, then bit 31
+  int cur = 0;
+  auto pass = [&](int shift) {
+    SortPass P;
+    P.key_in = (const unsigned*)(ws + L.key[cur]);
+    P.val_in = (const int*)(ws + L.val[cur]);
+    P.key_out = (unsigned*)(ws + L.key[cur ^ 1]);
+    P.val_out = (int*)(ws + L.val[cur ^ 1]);
+    P.hist = (unsigned*)(ws + L.hist);
+    P.dtot = (unsigned*)(ws + L.dtot);
+    P.n = n;
+    P.tiles = L.sort_tiles;
+    P.shift = shift;
+    hipLaunchKernelGGL(k_sort_hist, dim3(L.sort_tiles), dim3(kBlock), 0, s, P);
+    hipLaunchKernelGGL(k_sort_scan, dim3(kDigits), dim3(kBlock), 0, s, P);
+    hipLaunchKernelGGL(k_sort_scatter, dim3(L.sort_tiles), dim3(kBlock), 0, s, P);
+    cur ^= 1;
+  };
+  for (int shift = 0; shift < bits; shift += 8) pass(shift);
+  pass(24);   // bit 31 (with bits 24..30): marked before unmarked
+  // exact gains of the sorted sequence, best prefix, apply it
+  Seq S = make_seq(g, d.k, ws, L, d.part, d.phi, (const int*)(ws + L.val[cur]), nullptr, 0);
+  S.cand = d.cand;
+  S.t_slots = d.ctr->slot[kCtrMarked];
+  long long* gains = (long long*)(ws + L.gains);
+  const unsigned grid = grid_of(n, kBlock);
+  hipLaunchKernelGGL(k_seq_init, dim3(grid), dim3(kBlock), 0, s, S);
+  hipLaunchKernelGGL(k_seq_collect, dim3(grid), dim3(kBlock), 0, s, S);
+  hipLaunchKernelGGL(k_seq_gains, dim3(grid), dim3(kBlock), 0, s, S, gains);
+  long long* csum = (long long*)(ws + L.csum);
+  long long* coff = (long long*)(ws + L.coff);
+  long long* cbv = (long long*)(ws + L.cbest_v);
+  int* cbi = (int*)(ws + L.cbest_i);
+  long long* best = (long long*)(ws + L.best);
+  hipLaunchKernelGGL(k_prefix_sums, dim3(L.chunks), dim3(kBlock), 0, s, S, gains, csum);
+  hipLaunchKernelGGL(k_prefix_top, dim3(1), dim3(kBlock), 0, s, csum, coff, L.chunks);
+  hipLaunchKernelGGL(k_prefix_best, dim3(L.chunks), dim3(kBlock), 0, s, S, gains, coff, cbv, cbi);
+  hipLaunchKernelGGL(k_prefix_final, dim3(1), dim3(kBlock), 0, s, cbv, cbi, L.chunks, best);
+  hipLaunchKernelGGL(k_apply_prefix, dim3(grid), dim3(kBlock), 0, s, S, best, d);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_round_back(plan, round, s, nullptr);
+}
+
+}  // namespace hg
+
+using hg::check_k;
+using hg::fail;
+
+extern "C" {
+
+size_t hg_moves_workspace_size(int32_t n, int32_t m, int32_t k) {
+  if (n < 1 || m < 1 || k < 2 || k > HG_MAX_K) return 0;
+  return hg::moves_workspace_size(n, m, k);
+}
+
+static hg_status check_moves_ws(hg_graph g, int k, void* ws, size_t ws_bytes) {
+  const size_t need = hg::moves_workspace_size(g->n, g->m, k);
+  if (!ws || ws_bytes < need)
+    return fail(HG_ERR_WORKSPACE, "move workspace needs %zu bytes (got %zu)", need, ws_bytes);
+  return HG_OK;
+}
+
+hg_status hg_move_gains(hg_graph g, int32_t k, const int32_t* part, const int32_t* phi,
+                        int32_t t, const int32_t* move_u, const int32_t* move_to,
+                        int64_t* gains, void* workspace, size_t ws_bytes, void* stream) {
+  hg_status st = check_k(g, k);
+  if (st != HG_OK) return st;
+  if (t < 0 || t > g->n) return fail(HG_ERR_INVALID, "t must lie in [0, n]");
+  if (t == 0) return HG_OK;
+  if (!part || !phi || !move_u || !move_to || !gains)
+    return fail(HG_ERR_INVALID, "part, phi, move_u, move_to and gains must be non-NULL");
+  st = check_moves_ws(g, k, workspace, ws_bytes);
+  if (st != HG_OK) return st;
+  HG_TRY(hg::launch_move_gains(g, k, part, phi, t, move_u, move_to, (long long*)gains,
+                               (char*)workspace, (hipStream_t)stream),
+         "move gains");
+  return HG_OK;
+}
+
+hg_status hg_best_prefix(hg_graph g, int32_t k, int64_t max_block_w, const int32_t* part,
+                         const int64_t* block_w, int32_t t, const int32_t* move_u,
+                         const int32_t* move_to, const int64_t* gains, int32_t* best_len,
+                         int64_t* best_gain, void* workspace, size_t ws_bytes, void* stream) {
+  hg_status st = check_k(g, k);
+  if (st != HG_OK) return st;
+  if (t < 0 || t > g->n) return fail(HG_ERR_INVALID, "t must lie in [0, n]");
+  if (!part || !block_w || (t > 0 && (!move_u || !move_to || !gains)) || !best_len || !best_gain)
+    return fail(HG_ERR_INVALID, "part, block_w, the moves, gains, best_len and best_gain must be "
+                                "non-NULL");
+  st = check_moves_ws(g, k, workspace, ws_bytes);
+  if (st != HG_OK) return st;
+  const hg::MovesLayoutBest lb = hg::moves_best_slot(g->n, g->m, k);
+  HG_TRY(hg::launch_best_prefix(g, k, max_block_w, part, (const long long*)block_w, t, move_u,
+                                move_to, (const long long*)gains,
+                                (long long*)((char*)workspace + lb.best), best_len,
+                                (long long*)best_gain, (hipStream_t)stream),
+         "best prefix");
+  return HG_OK;
+}
+
+hg_status hg_lp_round_exact(hg_graph g, int32_t k, int64_t max_block_w, int32_t* part,
+                            int32_t* phi, uint32_t* netstate, int64_t* block_w, uint8_t* eligible,
+                            uint8_t* moved, int64_t* km1, hg_round_stats* stats, void* workspace,
+                            size_t ws_bytes, void* stream) {
+  hg_status st = check_k(g, k);
+  if (st != HG_OK) return st;
+  if (!part || !phi || !netstate || !block_w || !eligible || !km1 || !stats)
+    return fail(HG_ERR_INVALID,
+                "part, phi, netstate, block_w, eligible, km1 and stats must be non-NULL");
+  if (max_block_w < 0) return fail(HG_ERR_INVALID, "max_block_w must be >= 0");
+  st = check_moves_ws(g, k, workspace, ws_bytes);
+  if (st != HG_OK) return st;
+  hg::InstDesc d = hg::make_desc(g, k, max_block_w, part, phi, netstate, (long long*)block_w,
+                                 eligible, moved, (long long*)km1, stats);
+  HG_TRY(hg::launch_round_exact(g, d, 0, (char*)workspace, (hipStream_t)stream),
+         "monotone round");
+  return HG_OK;
+}
+
+hg_status hg_refine_exact(hg_graph g, int32_t k, double eps, int32_t rounds, int32_t* part,
+                          int32_t* phi, uint32_t* netstate, int64_t* block_w, uint8_t* eligible,
+                          hg_round_stats* stats, int64_t* km1_out, void* workspace,
+                          size_t ws_bytes, void* stream) {
+  hg_status st = check_k(g, k);
+  if (st != HG_OK) return st;
+  if (!(eps > 0.0 && eps < 1.0)) return fail(HG_ERR_INVALID, "eps must lie in (0, 1)");
+  if (rounds < 0) return fail(HG_ERR_INVALID, "rounds must be >= 0");
+  if (!part || !phi || !netstate || !block_w || !eligible || !km1_out || (rounds > 0 && !stats))
+    return fail(HG_ERR_INVALID, "part, phi, netstate, block_w, eligible, stats and km1_out must "
+                                "be non-NULL");
+  st = check_moves_ws(g, k, workspace, ws_bytes);
+  if (st != HG_OK) return st;
+  const long long lmax = hg_max_block_weight(g, k, eps);
+  hipStream_t s = (hipStream_t)stream;
+  hg::InstDesc d = hg::make_desc(g, k, lmax, part, phi, netstate, (long long*)block_w, eligible,
+                                 nullptr, (long long*)km1_out, stats);
+  hg::CountPlan cplan;
+  hg::single_count_plan(d, cplan);
+  HG_TRY(hg::launch_counts(cplan, true, true, s), "pin counts");
+  for (int r = 0; r < rounds; ++r) {
+    d.stats = stats + r;
+    HG_TRY(hg::launch_round_exact(g, d, 0, (char*)workspace, s), "monotone round");
+  }
+  return HG_OK;
+}
+
+}  // extern "C"

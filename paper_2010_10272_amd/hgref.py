@@ -156,6 +156,16 @@ def _load():
     lib.hg_server_get_stats.restype = i32
     lib.hg_server_free.argtypes = [vp]
     lib.hg_server_free.restype = None
+    lib.hg_moves_workspace_size.argtypes = [i32, i32, i32]
+    lib.hg_moves_workspace_size.restype = sz
+    lib.hg_move_gains.argtypes = [vp, i32, vp, vp, i32, vp, vp, vp, vp, sz, vp]
+    lib.hg_move_gains.restype = i32
+    lib.hg_best_prefix.argtypes = [vp, i32, i64, vp, vp, i32, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.hg_best_prefix.restype = i32
+    lib.hg_lp_round_exact.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.hg_lp_round_exact.restype = i32
+    lib.hg_refine_exact.argtypes = [vp, i32, dbl, i32, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.hg_refine_exact.restype = i32
     lib.hg_last_error.argtypes = []
     lib.hg_last_error.restype = ctypes.c_char_p
     return lib
@@ -651,3 +661,59 @@ def hg_server_release(srv, jid):
 
 def hg_server_free(srv):
     srv.free()
+
+
+# ---------------------------------------------------------------- move sequences
+
+def hg_moves_workspace_size(n, m, k):
+    return int(_lib.hg_moves_workspace_size(int(n), int(m), int(k)))
+
+
+def moves_workspace(g, k):
+    """A device workspace tensor for the move-sequence calls on graph g."""
+    nbytes = hg_moves_workspace_size(g.n, g.m, k)
+    if nbytes == 0:
+        raise HgError(HG_ERR_UNSUPPORTED, "unsupported sizes")
+    return torch.empty(nbytes, dtype=torch.uint8, device=g.device)
+
+
+def hg_move_gains(g, k, part, phi, move_u, move_to, ws, gains=None, stream=None):
+    dev = g.device
+    move_u = _dev(move_u, torch.int32, dev)
+    move_to = _dev(move_to, torch.int32, dev)
+    t = int(move_u.numel())
+    if gains is None:
+        gains = torch.empty(max(t, 1), dtype=torch.int64, device=dev)
+    _check(_lib.hg_move_gains(g.handle, int(k), _ptr(part), _ptr(phi), t, _ptr(move_u),
+                              _ptr(move_to), _ptr(gains), _ptr(ws), ws.numel(), _stream(stream)))
+    return gains[:t]
+
+
+def hg_best_prefix(g, k, max_block_w, part, block_w, move_u, move_to, gains, ws, stream=None):
+    """(best_len, best_gain) as device tensors of one element."""
+    dev = g.device
+    move_u = _dev(move_u, torch.int32, dev)
+    move_to = _dev(move_to, torch.int32, dev)
+    gains = _dev(gains, torch.int64, dev)
+    t = int(move_u.numel())
+    blen = torch.zeros(1, dtype=torch.int32, device=dev)
+    bgain = torch.zeros(1, dtype=torch.int64, device=dev)
+    _check(_lib.hg_best_prefix(g.handle, int(k), int(max_block_w), _ptr(part), _ptr(block_w), t,
+                               _ptr(move_u) if t else None, _ptr(move_to) if t else None,
+                               _ptr(gains) if t else None, _ptr(blen), _ptr(bgain), _ptr(ws),
+                               ws.numel(), _stream(stream)))
+    return blen, bgain
+
+
+def hg_lp_round_exact(g, st, max_block_w, stats, ws, moved=True, stream=None):
+    _check(_lib.hg_lp_round_exact(g.handle, st.k, int(max_block_w), _ptr(st.part), _ptr(st.phi),
+                                  _ptr(st.netstate), _ptr(st.block_w), _ptr(st.eligible),
+                                  _ptr(st.moved) if moved else None, _ptr(st.km1), _ptr(stats),
+                                  _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def hg_refine_exact(g, st, eps, rounds, stats, ws, stream=None):
+    _check(_lib.hg_refine_exact(g.handle, st.k, float(eps), int(rounds), _ptr(st.part),
+                                _ptr(st.phi), _ptr(st.netstate), _ptr(st.block_w),
+                                _ptr(st.eligible), _ptr(stats), _ptr(st.km1), _ptr(ws),
+                                ws.numel(), _stream(stream)))
