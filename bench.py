@@ -394,12 +394,88 @@ def served_leg(args, H, dev):
     return res
 
 
+_SPARSE = {}
+
+
+def sparse_instance():
+    """The sparse-matrix workload (generated once per run)."""
+    import synth
+    if "inst" not in _SPARSE:
+        _SPARSE["inst"] = synth.sparse_matrix(KS[0])
+    return _SPARSE["inst"]
+
+
+def monotone_leg(args, H, dev):
+    """Monotone rounds (exact gains of each round's approved moves in (gain
+    desc, id asc) order, best prefix applied) on the sparse-matrix workload at
+    k = 8 and 64, 10 rounds, beside plain rounds on the same start; and the
+    exact gains of a 100,000-move sequence on their own."""
+    import numpy as np
+    import torch
+    import synth
+    inst = sparse_instance()
+    out = {}
+    for k in KS:
+        ik = synth.with_k(inst, k)
+        g = H.hg_load_csr(inst.n, inst.eptr, inst.pins, inst.c, inst.w, k_max=k, device=dev)
+        st = H.State(g, k, ik.part)
+        ws = H.moves_workspace(g, k)
+        stats = torch.zeros(ROUNDS * H.STATS_WORDS, dtype=torch.int64, device=dev)
+        part0 = st.part.clone()
+        res = {}
+        for mode in ("plain", "monotone"):
+            xs = []
+            for rep in range(args.mono_reps + 1):
+                st.part.copy_(part0)
+                a, b = _events(torch)
+                a.record()
+                if mode == "plain":
+                    H.hg_refine(g, st, inst.eps, ROUNDS, stats, use_graph=False)
+                else:
+                    H.hg_refine_exact(g, st, inst.eps, ROUNDS, stats, ws)
+                b.record()
+                b.synchronize()
+                if rep:
+                    xs.append(a.elapsed_time(b))
+            recs = H.stats_to_dicts(stats)
+            kms = [r["km1_after"] for r in recs]
+            res[mode] = {"refine_ms": percentile(xs, 50), "round_ms": percentile(xs, 50) / ROUNDS,
+                         "km1_after_rounds": kms, "moves": sum(r["approved"] for r in recs),
+                         "pins_per_s": inst.P * ROUNDS / (percentile(xs, 50) / 1e3)}
+            if mode == "monotone":
+                assert all(b <= a for a, b in zip(kms, kms[1:])), "monotone km1 increased"
+        # exact gains of one explicit sequence: 100,000 random moves
+        rng = np.random.default_rng(9)
+        t = min(100_000, inst.n)
+        mu = torch.as_tensor(rng.permutation(inst.n)[:t].astype(np.int32), device=dev)
+        mt = ((part0[mu.long()] + 1 + torch.as_tensor(rng.integers(0, k - 1, t), device=dev))
+              % k).to(torch.int32)
+        st.part.copy_(part0)
+        H.hg_compute_pincounts(g, st)
+        gains = torch.empty(t, dtype=torch.int64, device=dev)
+        xs = []
+        for rep in range(args.mono_reps + 1):
+            a, b = _events(torch)
+            a.record()
+            H.hg_move_gains(g, k, st.part, st.phi, mu, mt, ws, gains=gains)
+            b.record()
+            b.synchronize()
+            if rep:
+                xs.append(a.elapsed_time(b))
+        deg = (g.vptr[1:] - g.vptr[:-1])[mu.long()].sum().item()
+        res["move_gains"] = {"moves": t, "incidences": int(deg), "ms": percentile(xs, 50),
+                             "incidences_per_s": deg / (percentile(xs, 50) / 1e3)}
+        out["k%d" % k] = res
+        g.free()
+    return out
+
+
 def plain_leg(args, H, dev):
     """The plain workload (module docstring): returns the JSON record."""
     import torch
     import synth
     print("generating workload ...", file=sys.stderr, flush=True)
-    inst = synth.sparse_matrix(KS[0])
+    inst = sparse_instance()
     n, m, P = inst.n, inst.m, inst.P
     parts = {k: torch.as_tensor(synth.with_k(inst, k).part).to(dev) for k in KS}
     eptr = torch.as_tensor(inst.eptr).to(dev)
@@ -565,8 +641,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-rounds", type=int, default=4)
     ap.add_argument("--latency-reps", type=int, default=5)
-    ap.add_argument("--legs", default="plain,batched,served",
-                    help="comma list of plain, batched, served")
+    ap.add_argument("--legs", default="plain,batched,served,monotone",
+                    help="comma list of plain, batched, served, monotone")
+    ap.add_argument("--mono-reps", type=int, default=3)
     ap.add_argument("--served-seconds", type=float, default=10.0,
                     help="length of the open-loop request trace")
     ap.add_argument("--batch-count", type=int, default=BATCH_COUNT)
@@ -596,6 +673,10 @@ def main():
     if "served" in legs:
         torch.cuda.empty_cache()
         out["served"] = served_leg(args, H, dev)
+    if "monotone" in legs:
+        torch.cuda.empty_cache()
+        print("monotone rounds ...", file=sys.stderr, flush=True)
+        out["monotone"] = monotone_leg(args, H, dev)
     print(json.dumps(out), flush=True)
 
 

@@ -45,7 +45,7 @@ constexpr int kPrefixChunk = kTile;         // moves per prefix-scan workgroup
 // Layout of the caller's move-sequence workspace.
 struct MovesLayout {
   size_t out_max, in_min, out_cnt, seen, appr, key[2], val[2], hist, dtot, gains, csum, coff,
-      cbest_v, cbest_i, best, total;
+      cbest_v, cbest_i, best, tdev, total;
   int sort_tiles, chunks;
 };
 
@@ -79,20 +79,21 @@ MovesLayout moves_layout(long long n, long long m, int k) {
   L.cbest_v = take(sizeof(long long) * (size_t)L.chunks);
   L.cbest_i = take(sizeof(int) * (size_t)L.chunks);
   L.best = take(sizeof(long long) * 2);
+  L.tdev = take(sizeof(int));
   L.total = off;
   return L;
 }
 
 // A move sequence as the kernels read it.  Move j (0-based) moves u = mu[j]
 // from part[u] to mt[j], or -- sorted monotone rounds -- to the target in
-// cand[u].  The length is t, or the sum of the kCtrMarked slots when
-// t_slots is set (known only on the device).
+// cand[u].  The length is t, or *t_dev when that is set (known only on the
+// device).
 struct Seq {
   const int* mu;
   const int* mt;                 // null: target from cand
   const long long* cand;
   int t;
-  const unsigned long long* t_slots;
+  const int* t_dev;              // length known only on the device (monotone rounds)
   const int* part;
   const int* phi;
   const long long* vptr;
@@ -107,12 +108,14 @@ struct Seq {
   int* err_flags;
 };
 
-__device__ __forceinline__ int seq_len(const Seq& S) {
-  if (!S.t_slots) return S.t;
-  // the sum of the kSlots partial counts (every thread reads them; small)
-  long long t = 0;
-  for (int i = 0; i < kSlots; ++i) t += (long long)S.t_slots[i];
-  return (int)t;
+__device__ __forceinline__ int seq_len(const Seq& S) { return S.t_dev ? *S.t_dev : S.t; }
+
+// The number of marked moves (sum of the kCtrMarked slots) -> *t.
+__global__ void k_count_marked(const unsigned long long* slots, int* t) {
+  const int lane = lane_id();
+  long long v = (long long)slots[lane];
+  v = wave_sum(v);
+  if (lane == 0) *t = (int)v;
 }
 
 // Source and target of move j, or false for a move the checks reject.
@@ -246,18 +249,20 @@ struct SortPass {
   int n, tiles, shift;
 };
 
-// Pass input of a monotone round: key = ~gain for marked vertices (so that
-// ascending keys are descending gains), all-ones for the rest; value = id.
-// The marks are cleared for the next round.
+// Pass input of a monotone round: key = top - gain for marked vertices (so
+// that ascending keys are descending gains) and `none` for the rest; value =
+// id.  With every gain <= top < 255, top = 254 and none = 255 make one 8-bit
+// pass enough; otherwise top = 0x7fffffff, none = 0xffffffff.  The marks are
+// cleared for the next round.
 __global__ __launch_bounds__(kBlock) void k_sort_keys(int n, const long long* cand,
-                                                      unsigned char* appr, unsigned* key,
-                                                      int* val) {
+                                                      unsigned char* appr, unsigned top,
+                                                      unsigned none, unsigned* key, int* val) {
   const long long u = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (u >= n) return;
-  unsigned k = 0xffffffffu;
+  unsigned k = none;
   if (appr[u]) {
-    const int g = (int)(cand[u] >> 32);   // select gain, >= 0
-    k = 0x7fffffffu - (unsigned)g;
+    const int g = (int)(cand[u] >> 32);   // select gain, 0 <= g <= top
+    k = top - (unsigned)g;
     appr[u] = 0;
   }
   key[u] = k;
@@ -714,12 +719,13 @@ hipError_t launch_round_exact(hg_graph_s* g, InstDesc d, int round, char* ws, hi
   // order the marked moves: keys of all n vertices, 8-bit passes over the
   // bits a gain can occupy (gains are at most the largest incident weight)
   const int n = g->n;
+  const long long maxw = g->info.max_incident_weight;   // bounds every gain
+  const bool one_pass = maxw < 255;
   hipLaunchKernelGGL(k_sort_keys, dim3(grid_of(n, kBlock)), dim3(kBlock), 0, s, n, d.cand,
-                     d.appr, (unsigned*)(ws + L.key[0]), (int*)(ws + L.val[0]));
+                     d.appr, one_pass ? 254u : 0x7fffffffu, one_pass ? 255u : 0xffffffffu,
+                     (unsigned*)(ws + L.key[0]), (int*)(ws + L.val[0]));
   int bits = 1;
-  while (bits < 31 && (1ll << bits) <= (long long)g->info.max_incident_weight) ++bits;
-  // keys 0x7fffffff - g differ from 0x7fffffff only in the low `bits` bits,
-  // unmarked keys (all ones) in bit 31: sort the low bits, then bit 31
+  while (bits < 31 && (1ll << bits) <= maxw) ++bits;
   int cur = 0;
   auto pass = [&](int shift) {
     SortPass P;
@@ -737,12 +743,20 @@ hipError_t launch_round_exact(hg_graph_s* g, InstDesc d, int round, char* ws, hi
     hipLaunchKernelGGL(k_sort_scatter, dim3(L.sort_tiles), dim3(kBlock), 0, s, P);
     cur ^= 1;
   };
-  for (int shift = 0; shift < bits; shift += 8) pass(shift);
-  pass(24);   // bit 31 (with bits 24..30): marked before unmarked
+  if (one_pass) {
+    pass(0);
+  } else {
+    // keys 0x7fffffff - g differ from 0x7fffffff only in the low `bits`
+    // bits, unmarked keys (all ones) in bit 31: the low bits, then bit 31
+    for (int shift = 0; shift < bits; shift += 8) pass(shift);
+    pass(24);
+  }
   // exact gains of the sorted sequence, best prefix, apply it
   Seq S = make_seq(g, d.k, ws, L, d.part, d.phi, (const int*)(ws + L.val[cur]), nullptr, 0);
   S.cand = d.cand;
-  S.t_slots = d.ctr->slot[kCtrMarked];
+  int* tdev = (int*)(ws + L.tdev);
+  S.t_dev = tdev;
+  hipLaunchKernelGGL(k_count_marked, dim3(1), dim3(kWave), 0, s, d.ctr->slot[kCtrMarked], tdev);
   long long* gains = (long long*)(ws + L.gains);
   const unsigned grid = grid_of(n, kBlock);
   hipLaunchKernelGGL(k_seq_init, dim3(grid), dim3(kBlock), 0, s, S);
