@@ -193,6 +193,34 @@ void or_gains(int32_t n, const int64_t* vptr, const int32_t* vnets, const int32_
 }
 
 /* ------------------------------------------------------------------------ */
+/* Gain cache contents (subsection "Gain Caching"): the terms kept apart so  */
+/* that a gain is b(u) - p_i(u), for every vertex u                          */
+/*   benefit[u]    = b(u)   = w({e in I(u) : Phi(e, Pi(u)) = 1})             */
+/*   incident[u]   = w(I(u))                                                 */
+/*   penalty[u*k+i]= p_i(u) = w({e in I(u) : Phi(e, i) = 0})   (all i,       */
+/*                   so p_{Pi(u)}(u) = 0)                                    */
+/* ------------------------------------------------------------------------ */
+void or_gain_cache(int32_t n, const int64_t* vptr, const int32_t* vnets, const int32_t* w,
+                   const int32_t* part, int32_t k, const int32_t* phi, int64_t* benefit,
+                   int64_t* incident, int64_t* penalty) {
+  for (int32_t u = 0; u < n; ++u) {
+    int32_t a = part[u];
+    int64_t b = 0, tot = 0;
+    int64_t* p = penalty + (int64_t)u * k;
+    for (int32_t i = 0; i < k; ++i) p[i] = 0;
+    for (int64_t j = vptr[u]; j < vptr[u + 1]; ++j) {
+      int32_t e = vnets[j];
+      tot += ww(w, e);
+      if (phi[(int64_t)e * k + a] == 1) b += ww(w, e);
+      for (int32_t i = 0; i < k; ++i)
+        if (phi[(int64_t)e * k + i] == 0) p[i] += ww(w, e);
+    }
+    benefit[u] = b;
+    incident[u] = tot;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
 /* One synchronous label-propagation round (section "Label Propagation"),   */
 /* re-specified for synchronous execution:                                   */
 /*  1. eligible set E (given), active set A = eligible boundary vertices;    */

@@ -61,6 +61,7 @@ def _load():
         _lib.or_lmax.argtypes = [i64, i32, dbl]
         _lib.or_lmax.restype = i64
         _lib.or_gains.argtypes = [i32, vp, vp, vp, vp, i32, vp, vp, vp]
+        _lib.or_gain_cache.argtypes = [i32, vp, vp, vp, vp, i32, vp, vp, vp, vp]
         _lib.or_lp_round.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, i32, i64, vp, vp,
                                      vp, ctypes.POINTER(RoundStats)]
         _lib.or_lp_round.restype = ctypes.c_int
@@ -172,6 +173,21 @@ def gains(h, part, k, phi=None):
     b = np.empty(h.n, np.int64)
     _load().or_gains(h.n, _p(vptr), _p(vnets), _p(h.w), _p(part), k, _p(phi), _p(g), _p(b))
     return g.reshape(h.n, k), b
+
+
+def gain_cache(h, part, k, phi=None):
+    """The gain cache by definition: (b[n], w(I)[n], p[n, k]), all int64."""
+    part = _c(part, np.int32)
+    if phi is None:
+        phi = pin_counts(h, part, k)
+    phi = _c(phi, np.int32)
+    vptr, vnets = h.incidence()
+    b = np.empty(h.n, np.int64)
+    wi = np.empty(h.n, np.int64)
+    p = np.empty(h.n * k, np.int64)
+    _load().or_gain_cache(h.n, _p(vptr), _p(vnets), _p(h.w), _p(part), k, _p(phi), _p(b),
+                          _p(wi), _p(p))
+    return b, wi, p.reshape(h.n, k)
 
 
 def lp_round(h, k, lmax_value, part, eligible):
