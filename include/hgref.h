@@ -228,6 +228,51 @@ hg_status hg_refine(hg_graph g, int32_t k, double eps, int32_t rounds, int32_t* 
                     hg_round_stats* stats, int64_t* km1_out, int32_t use_graph,
                     void* stream);
 
+/* ------------------------------------------------------------------------
+ * Gain cache (subsection "Gain Caching").  Instead of the k gains of every
+ * vertex the cache keeps their two terms apart, so that a round's moves
+ * change few entries:
+ *   int32 cache[0 .. n)           b(u) = w({e in I(u) : Phi(e, Pi(u)) = 1})
+ *   int32 cache[n .. 2n)          w(I(u))
+ *   int32 cache[pb + u*ks + i]    p_i(u) = w({e in I(u) : Phi(e, i) = 0}),
+ *                                 pb = 2n rounded up to a multiple of 4,
+ *                                 ks = k rounded up to a multiple of 4
+ * and g_i(u) = b(u) - p_i(u) for i != Pi(u).  The buffer is the caller's
+ * (device, 16-byte aligned, hg_gain_cache_bytes bytes) and belongs to one
+ * (graph, k, state) at a time.  A cached round makes the same decisions as
+ * hg_lp_round on the same state (every output bit-identical) and leaves the
+ * cache equal to the cache of the new partition: the finalize step applies
+ * the paper's four update rules summed over the round's moves (for every pin
+ * v of a net e that held a mover: p_i(v) -/+ w(e) where block i entered/left
+ * Lambda(e); b(v) of a pin that did not move -/+ w(e) where its block
+ * left/entered the set of blocks with exactly one pin of e), then b(u) is
+ * recomputed for every moved vertex.  Entries padding a row are never read.
+ * ------------------------------------------------------------------------ */
+
+/* Bytes of the gain cache of n vertices at k blocks; -1 on bad arguments. */
+int64_t hg_gain_cache_bytes(int32_t n, int32_t k);
+
+/* Fill the cache from a partition and its net state (hg_compute_pincounts
+ * or earlier rounds); same requirements as hg_gains. */
+hg_status hg_gain_cache_init(hg_graph g, int32_t k, const int32_t* part, const uint32_t* netstate,
+                             int32_t* cache, void* stream);
+
+/* hg_lp_round reading the gains from `cache` and updating it.  `moved` is
+ * required (the update reads it); `cache` must hold the cache of the current
+ * partition (hg_gain_cache_init, or the previous cached round). */
+hg_status hg_lp_round_cached(hg_graph g, int32_t k, int64_t max_block_w, int32_t* part,
+                             int32_t* phi, uint32_t* netstate, int64_t* block_w,
+                             uint8_t* eligible, uint8_t* moved, int64_t* km1,
+                             hg_round_stats* stats, int32_t* cache, void* stream);
+
+/* hg_refine (without a graph) through the cache: pin counts from part, every
+ * vertex eligible, hg_gain_cache_init, then `rounds` cached rounds.  Outputs
+ * are bit-identical to hg_refine. */
+hg_status hg_refine_cached(hg_graph g, int32_t k, double eps, int32_t rounds, int32_t* part,
+                           int32_t* phi, uint32_t* netstate, int64_t* block_w, uint8_t* eligible,
+                           uint8_t* moved, hg_round_stats* stats, int64_t* km1_out,
+                           int32_t* cache, void* stream);
+
 /* Per-phase timing of label-propagation rounds, off by default.  While on,
  * every round enqueued outside a stream capture (hg_lp_round, and hg_refine
  * with use_graph = 0) records four HIP events on its own stream around the

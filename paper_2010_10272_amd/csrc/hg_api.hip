@@ -455,6 +455,83 @@ hg_status hg_refine(hg_graph g, int32_t k, double eps, int32_t rounds, int32_t* 
   return HG_OK;
 }
 
+// ------------------------------------------------------------ gain cache
+
+int64_t hg_gain_cache_bytes(int32_t n, int32_t k) {
+  if (n < 1 || k < 2 || k > HG_MAX_K) return -1;
+  return 4 * (hg::cache_pbase(n) + (int64_t)n * hg::cache_stride(k));
+}
+
+hg_status hg_gain_cache_init(hg_graph g, int32_t k, const int32_t* part, const uint32_t* netstate,
+                             int32_t* cache, void* stream) {
+  hg_status st = check_k(g, k);
+  if (st != HG_OK) return st;
+  if (!part || !netstate || !cache)
+    return fail(HG_ERR_INVALID, "part, netstate and cache must be non-NULL");
+  if (((uintptr_t)cache & 15) != 0) return fail(HG_ERR_INVALID, "cache must be 16-byte aligned");
+  hg::InstDesc d = hg::make_desc(g, k, 0, (int*)part, nullptr, (unsigned*)netstate, nullptr,
+                                 nullptr, nullptr, nullptr, nullptr);
+  HG_TRY(hg::launch_gains(g, d, nullptr, nullptr, (hipStream_t)stream, cache), "gain cache");
+  return HG_OK;
+}
+
+hg_status hg_lp_round_cached(hg_graph g, int32_t k, int64_t max_block_w, int32_t* part,
+                             int32_t* phi, uint32_t* netstate, int64_t* block_w,
+                             uint8_t* eligible, uint8_t* moved, int64_t* km1,
+                             hg_round_stats* stats, int32_t* cache, void* stream) {
+  hg_status st = check_k(g, k);
+  if (st != HG_OK) return st;
+  if (!part || !phi || !netstate || !block_w || !eligible || !moved || !km1 || !stats || !cache)
+    return fail(HG_ERR_INVALID, "part, phi, netstate, block_w, eligible, moved, km1, stats and "
+                                "cache must be non-NULL");
+  if (((uintptr_t)cache & 15) != 0) return fail(HG_ERR_INVALID, "cache must be 16-byte aligned");
+  if (max_block_w < 0) return fail(HG_ERR_INVALID, "max_block_w must be >= 0");
+  hipEvent_t* marks = nullptr;
+  st = timing_marks(g, (hipStream_t)stream, &marks);
+  if (st != HG_OK) return st;
+  hg::InstDesc d = hg::make_desc(g, k, max_block_w, part, phi, netstate, (long long*)block_w,
+                                 eligible, moved, (long long*)km1, stats);
+  d.cache = cache;
+  hg::RoundPlan plan;
+  hg::cached_round_plan(d, plan);
+  HG_TRY(hg::launch_cached_round(plan, 0, (hipStream_t)stream, marks), "cached round");
+  return HG_OK;
+}
+
+hg_status hg_refine_cached(hg_graph g, int32_t k, double eps, int32_t rounds, int32_t* part,
+                           int32_t* phi, uint32_t* netstate, int64_t* block_w, uint8_t* eligible,
+                           uint8_t* moved, hg_round_stats* stats, int64_t* km1_out,
+                           int32_t* cache, void* stream) {
+  hg_status st = check_k(g, k);
+  if (st != HG_OK) return st;
+  if (!(eps > 0.0 && eps < 1.0)) return fail(HG_ERR_INVALID, "eps must lie in (0, 1)");
+  if (rounds < 0) return fail(HG_ERR_INVALID, "rounds must be >= 0");
+  if (!part || !phi || !netstate || !block_w || !eligible || !moved || !km1_out || !cache ||
+      (rounds > 0 && !stats))
+    return fail(HG_ERR_INVALID, "part, phi, netstate, block_w, eligible, moved, stats, km1_out "
+                                "and cache must be non-NULL");
+  if (((uintptr_t)cache & 15) != 0) return fail(HG_ERR_INVALID, "cache must be 16-byte aligned");
+  const long long lmax = hg_max_block_weight(g, k, eps);
+  hipStream_t s = (hipStream_t)stream;
+  hg::InstDesc d = hg::make_desc(g, k, lmax, part, phi, netstate, (long long*)block_w, eligible,
+                                 moved, (long long*)km1_out, stats);
+  hg::CountPlan cplan;
+  hg::single_count_plan(d, cplan);
+  HG_TRY(hg::launch_counts(cplan, true, true, s), "pin counts");
+  HG_TRY(hg::launch_gains(g, d, nullptr, nullptr, s, cache), "gain cache");
+  d.cache = cache;
+  hg::RoundPlan plan;
+  for (int r = 0; r < rounds; ++r) {
+    hipEvent_t* marks = nullptr;
+    st = timing_marks(g, s, &marks);
+    if (st != HG_OK) return st;
+    d.stats = stats + r;
+    hg::cached_round_plan(d, plan);
+    HG_TRY(hg::launch_cached_round(plan, 0, s, marks), "cached round");
+  }
+  return HG_OK;
+}
+
 hg_status hg_timing_enable(hg_graph g, int32_t enable) {
   if (!g) return fail(HG_ERR_INVALID, "graph handle is NULL");
   g->timing = enable ? 1 : 0;

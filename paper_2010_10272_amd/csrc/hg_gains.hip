@@ -16,9 +16,13 @@ namespace hg {
 
 // Unit: a chunk of 256 vertices (single instance: blockIdx, XCD-remapped).
 // Row u of `gains` (k int64) and benefit[u] are written.
+// With `cache` set, the sweeps fill a gain cache instead (subsection "Gain
+// Caching"): b(u), w(I(u)) and the row p_i(u) = w(I(u)) - conn_i (0 for the
+// own block), laid out as cache_pbase / cache_stride say.
 template <int WK, int VIEW>
 __global__ __launch_bounds__(kBlock) void k_gains_light(Launch L, long long* __restrict__ gains,
-                                                        long long* __restrict__ benefit) {
+                                                        long long* __restrict__ benefit,
+                                                        int* __restrict__ cache) {
   WorkItem fb;
   fb.inst = 0;
   fb.first = (int)xcd_remap(blockIdx.x, gridDim.x);
@@ -33,6 +37,7 @@ __global__ __launch_bounds__(kBlock) void k_gains_light(Launch L, long long* __r
   long long* row = gains + u * k;
   if ((unsigned)a >= (unsigned)k) {
     atomicOr(D.err_flags, kErrPart);
+    if (cache) return;
     for (int i = 0; i < k; ++i) row[i] = 0;
     if (benefit) benefit[u] = 0;
     return;
@@ -71,6 +76,20 @@ __global__ __launch_bounds__(kBlock) void k_gains_light(Launch L, long long* __r
     for (int q = 0; q < kUnroll; ++q)
       if (w[q]) C.add(Lb[q], w[q]);
   }
+  if (cache) {
+    const long long n = D.n;
+    cache[u] = ben;
+    cache[n + u] = tot;
+    int* prow = cache + cache_pbase(n) + (long long)u * cache_stride(k);
+#pragma unroll
+    for (int w = 0; w < WK; ++w)
+      for (int b = 0; b < 32; ++b) {
+        const int i = w * 32 + b;
+        if (i >= k) break;
+        prow[i] = tot - (int)C.value(w, b);
+      }
+    return;
+  }
   const long long base = (long long)ben - tot;
 #pragma unroll
   for (int w = 0; w < WK; ++w) {
@@ -96,7 +115,8 @@ __global__ __launch_bounds__(kBlock) void k_gains_light(Launch L, long long* __r
 
 // Unit: 4 consecutive heavy-list entries (one per wavefront).
 __global__ __launch_bounds__(kBlock) void k_gains_heavy(Launch L, long long* __restrict__ gains,
-                                                        long long* __restrict__ benefit) {
+                                                        long long* __restrict__ benefit,
+                                                        int* __restrict__ cache) {
   __shared__ int s_conn[kBlock / kWave][HG_MAX_K];
   WorkItem fb;
   fb.inst = 0;
@@ -135,6 +155,16 @@ __global__ __launch_bounds__(kBlock) void k_gains_heavy(Launch L, long long* __r
   wave_lds_sync();
   tot = wave_sum(tot);
   ben = wave_sum(ben);
+  if (cache) {
+    const long long n = D.n;
+    int* prow = cache + cache_pbase(n) + (long long)u * cache_stride(k);
+    for (int i = lane; i < k; i += kWave) prow[i] = tot - conn[i];
+    if (lane == 0) {
+      cache[u] = ben;
+      cache[n + u] = tot;
+    }
+    return;
+  }
   long long* row = gains + (long long)u * k;
   for (int i = lane; i < k; i += kWave)
     row[i] = i == a ? 0 : (long long)ben - tot + conn[i];
@@ -142,7 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_gains_heavy(Launch L, long long* __r
 }
 
 GainsKernel gains_kernel(int k, int view) {
-  typedef void (*K)(Launch, long long*, long long*);
+  typedef void (*K)(Launch, long long*, long long*, int*);
   K kern;
   switch (view) {
     case kView16: kern = k_gains_light<1, kView16>; break;
@@ -160,15 +190,15 @@ GainsKernel gains_kernel(int k, int view) {
 }
 
 hipError_t launch_gains(hg_graph_s* g, const InstDesc& d, long long* gains, long long* benefit,
-                        hipStream_t s) {
-  typedef void (*K)(Launch, long long*, long long*);
+                        hipStream_t s, int* cache) {
+  typedef void (*K)(Launch, long long*, long long*, int*);
   const Launch L = single_launch(d);
   unsigned grid = (unsigned)(((long long)d.n + kBlock - 1) / kBlock);
   hipLaunchKernelGGL((K)(void*)gains_kernel(d.k, d.view), dim3(grid), dim3(kBlock), 0, s, L,
-                     gains, benefit);
+                     gains, benefit, cache);
   if (d.heavy_count > 0) {
     unsigned hg = (unsigned)((d.heavy_count + (kBlock / kWave) - 1) / (kBlock / kWave));
-    hipLaunchKernelGGL(k_gains_heavy, dim3(hg), dim3(kBlock), 0, s, L, gains, benefit);
+    hipLaunchKernelGGL(k_gains_heavy, dim3(hg), dim3(kBlock), 0, s, L, gains, benefit, cache);
   }
   (void)g;
   return hipGetLastError();

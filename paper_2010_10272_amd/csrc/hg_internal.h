@@ -130,6 +130,7 @@ struct InstDesc {
   unsigned long long* red;
   long long* bw_slots;           // kSlots x k block-weight deltas of a round's moves
   unsigned char* appr;           // monotone rounds: approve marks moves here instead of applying
+  int* cache;                    // gain cache (b[n], w(I)[n], p[n*k]); null: none
 };
 
 // One workgroup's share of a batched launch: instance, and the units it
@@ -298,6 +299,12 @@ hipError_t fill_i32(int* p, int v, long long count, hipStream_t s);
 
 hipError_t load_check(hg_graph_s* g, hipStream_t s);
 hipError_t load_build(hg_graph_s* g, hipStream_t s);
+
+// Gain cache (int32): b(u) at [u], w(I(u)) at [n + u], and the penalty row
+// p_0(u) .. p_{k-1}(u) at [cache_pbase(n) + u * cache_stride(k)], rows padded
+// to whole 16-byte quads.
+__host__ __device__ inline long long cache_pbase(long long n) { return (2 * n + 3) & ~3LL; }
+__host__ __device__ inline int cache_stride(int k) { return (k + 3) & ~3; }
 
 // Gain-histogram buckets kept in LDS per target block by the select sweep.
 inline int lds_buckets(int k) {

@@ -54,15 +54,25 @@ hipError_t launch_round(const RoundPlan& plan, int round, hipStream_t s, hipEven
 // Its two halves: select .. approve (+ apply), then finalize and the record.
 hipError_t launch_round_front(const RoundPlan& plan, hipStream_t s, hipEvent_t* marks);
 hipError_t launch_round_back(const RoundPlan& plan, int round, hipStream_t s, hipEvent_t* marks);
+// launch_round_back in two steps: finalize, then the round record.
+hipError_t launch_round_finalize(const RoundPlan& plan, hipStream_t s, hipEvent_t* marks);
+hipError_t launch_round_stats(const RoundPlan& plan, int round, hipStream_t s, hipEvent_t* marks);
 void single_round_plan(const InstDesc& d, RoundPlan& plan);
+// Gain-cache rounds (single instance, d.cache and d.moved set): the plan and
+// its launch (front, finalize with cache deltas, movers' b, record).
+SelectKernel select_cached_kernel(int k);
+void cached_round_plan(const InstDesc& d, RoundPlan& plan);
+hipError_t launch_cached_round(const RoundPlan& plan, int round, hipStream_t s,
+                               hipEvent_t* marks);
 
 // Pin counts, block weights and (want_km1) km1 of every instance; with
 // mark_eligible every vertex is made eligible as well.
 hipError_t launch_counts(const CountPlan& plan, bool want_km1, bool mark_eligible, hipStream_t s);
 void single_count_plan(const InstDesc& d, CountPlan& plan);
 
+// All gains (or, with `cache`, a gain cache: b, w(I), p rows; see hgref.h).
 hipError_t launch_gains(hg_graph_s* g, const InstDesc& d, long long* gains, long long* benefit,
-                        hipStream_t s);
+                        hipStream_t s, int* cache = nullptr);
 hipError_t launch_km1(hg_graph_s* g, int k, const unsigned* netstate, long long* km1,
                       hipStream_t s);
 

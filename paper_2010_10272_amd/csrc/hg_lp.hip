@@ -367,6 +367,193 @@ __global__ __launch_bounds__(kBlock) void k_select_heavy(Launch L) {
   }
 }
 
+// Select from a gain cache (subsection "Gain Caching"): the same decisions
+// as k_select_light / k_select_heavy, read from b(u), w(I(u)) and the
+// penalty row instead of the incident nets.  Block i neighbours u iff
+// conn_i = w(I(u)) - p_i(u) > 0, and then g_i(u) = b(u) - w(I(u)) + conn_i.
+// G lanes share a vertex, each reading 16-byte quads of its row, so one
+// wavefront reads 64 / G consecutive rows.  Unit: a chunk of 256 vertices;
+// every vertex, light or heavy, is handled here.
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_select_cached(Launch L) {
+  __shared__ long long s_W[HG_MAX_K];
+  __shared__ unsigned long long s_hist[kLdsHistEntries];
+  __shared__ long long s_tmp[kBlock / kWave];
+  const InstDesc D0 = L.one;
+  const WorkItem wi = work_item(L, xcd_sweep((D0.n + kBlock - 1) / kBlock));
+  if (wi.count == 0) return;
+  const InstDesc D = inst_desc(L, wi.inst);
+  const int k = D.k, B = D.lds_buckets, n = D.n;
+  const long long lmax = D.lmax;
+  for (int i = threadIdx.x; i < k * B; i += kBlock) s_hist[i] = 0;
+  for (int i = threadIdx.x; i < k; i += kBlock) s_W[i] = D.block_w[i];
+  __syncthreads();
+  unsigned long long* my_hist = D.hist + (size_t)(blockIdx.x % D.hist_reps) * D.hist_stride;
+  long long n_elig = 0, n_bnd = 0, n_cand = 0, n_apins = 0;
+  const int gl = threadIdx.x % G;
+  constexpr int kPer = kBlock / G;
+  const int Q = cache_stride(k) / 4;
+  const int* __restrict__ cb = D.cache;
+  const int4* __restrict__ rows = (const int4*)(D.cache + cache_pbase(n));
+  for (int it = 0; it < wi.count; ++it) {
+    const long long c = (long long)wi.first + (long long)it * wi.stride;
+    for (int sub = 0; sub < G; ++sub) {
+      // every lane of a group has the same u, so control flow below is
+      // uniform within the group
+      const long long u = c * kBlock + sub * kPer + threadIdx.x / G;
+      if (u >= n) continue;
+      if (gl == 0 && D.moved) D.moved[u] = 0;
+      const unsigned char el = D.eligible[u];
+      if (!el) {
+        if (gl == 0) D.cand[u] = -1;
+        continue;
+      }
+      const int a = D.part[u];
+      if ((unsigned)a >= (unsigned)k) {
+        if (gl == 0) {
+          atomicOr(D.err_flags, kErrPart);
+          D.cand[u] = -1;
+          D.eligible[u] = 0;
+        }
+        continue;
+      }
+      const int ben = cb[u], tot = cb[n + u];
+      const long long cu = D.vwgt ? D.vwgt[u] : 1;
+      bool bnd = false;
+      int bc = -1, bi = -1;
+      long long bw = 0;
+      for (int q = gl; q < Q; q += G) {
+        const int4 p4 = rows[u * Q + q];
+        const int pv[4] = {p4.x, p4.y, p4.z, p4.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int i = q * 4 + j;
+          const int ci = tot - pv[j];
+          if (i >= k || i == a || ci <= 0) continue;
+          bnd = true;
+          const long long Wi = s_W[i];
+          if (Wi + cu > lmax) continue;
+          if (bi < 0 || ci > bc || (ci == bc && Wi < bw)) {
+            bc = ci;
+            bi = i;
+            bw = Wi;
+          }
+        }
+      }
+#pragma unroll
+      for (int o = G / 2; o > 0; o >>= 1) {
+        const int oc = __shfl_xor(bc, o, G), oi = __shfl_xor(bi, o, G);
+        const long long ow = __shfl_xor(bw, o, G);
+        bnd |= __shfl_xor((int)bnd, o, G) != 0;
+        const bool take =
+            oi >= 0 && (bi < 0 || oc > bc || (oc == bc && (ow < bw || (ow == bw && oi < bi))));
+        if (take) {
+          bc = oc;
+          bi = oi;
+          bw = ow;
+        }
+      }
+      if (gl != 0) continue;
+      D.eligible[u] = 0;
+      n_elig += 1;
+      long long out = -1;
+      if (bnd) {
+        n_bnd += 1;
+        n_apins += D.vptr[u + 1] - D.vptr[u];
+        if (bi >= 0) {
+          const int g = ben - tot + bc;
+          if (g > 0 || (g == 0 && bw + cu < s_W[a])) {
+            out = pack_cand(g, bi);
+            n_cand += 1;
+            if (g < B) {
+              atomicAdd(&s_hist[bi * B + g], (unsigned long long)cu);
+            } else {
+              atomicAdd(&my_hist[bi * kBuckets + (g < kBuckets ? g : kBuckets - 1)],
+                        (unsigned long long)cu);
+              if (g > kBuckets - 1) atomicOr(&D.overflow[bi], 1);
+            }
+          }
+        }
+      }
+      D.cand[u] = out;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < k * B; i += kBlock) {
+    const unsigned long long v = s_hist[i];
+    if (v) atomicAdd(&my_hist[(i / B) * kBuckets + (i % B)], v);
+  }
+  n_elig = block_sum64(n_elig, s_tmp);
+  n_bnd = block_sum64(n_bnd, s_tmp);
+  n_cand = block_sum64(n_cand, s_tmp);
+  n_apins = block_sum64(n_apins, s_tmp);
+  if (threadIdx.x == 0) {
+    const int sl = blockIdx.x % kSlots;
+    RoundCounters* ctr = D.ctr;
+    if (n_apins) atomicAdd(&ctr->slot[kCtrActivePins][sl], (unsigned long long)n_apins);
+    if (n_elig) atomicAdd(&ctr->slot[kCtrEligible][sl], (unsigned long long)n_elig);
+    if (n_bnd) atomicAdd(&ctr->slot[kCtrBoundary][sl], (unsigned long long)n_bnd);
+    if (n_cand) atomicAdd(&ctr->slot[kCtrCandidates][sl], (unsigned long long)n_cand);
+  }
+}
+
+// b(u) of every vertex that moved this round, from the finalized net records
+// (the nets where u is the only pin of its new block).  Unit: one vertex.
+__global__ __launch_bounds__(kBlock) void k_cache_movers(Launch L) {
+  const InstDesc D = L.one;
+  const long long u = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (u >= D.n || !D.moved[u]) return;
+  const int a = D.part[u];
+  const int wk = bit_words(D.k);
+  const int sw = 2 + wk + (a >> 5);
+  const unsigned bit = 1u << (a & 31);
+  int ben = 0;
+  for (long long j = D.vptr[u]; j < D.vptr[u + 1]; ++j) {
+    const unsigned* r = D.netstate + (long long)D.vnets[j] * D.rw;
+    if (r[sw] & bit) ben += (int)r[0];
+  }
+  D.cache[u] = ben;
+}
+
+int cached_group(int k) {
+  const int q = cache_stride(k) / 4;
+  int G = 1;
+  while (G < q && G < kWave) G <<= 1;
+  return G;
+}
+
+SelectKernel select_cached_kernel(int k) {
+  switch (cached_group(k)) {
+    case 1: return k_select_cached<1>;
+    case 2: return k_select_cached<2>;
+    case 4: return k_select_cached<4>;
+    case 8: return k_select_cached<8>;
+    case 16: return k_select_cached<16>;
+    case 32: return k_select_cached<32>;
+    default: return k_select_cached<64>;
+  }
+}
+
+// A single-instance round that reads and updates the gain cache d.cache:
+// cached select in place of the light and heavy sweeps, the finalize that
+// applies the net deltas, and the movers' b before the round record.
+void cached_round_plan(const InstDesc& d, RoundPlan& plan) {
+  single_round_plan(d, plan);
+  plan.select[0].kernel = (void*)select_cached_kernel(d.k);
+  plan.heavy.clear();   // any_heavy stays: heavy vertices can still overflow the buckets
+}
+
+hipError_t launch_cached_round(const RoundPlan& plan, int round, hipStream_t s,
+                               hipEvent_t* marks) {
+  hipError_t e = launch_round_front(plan, s, marks);
+  if (e == hipSuccess) e = launch_round_finalize(plan, s, marks);
+  if (e != hipSuccess) return e;
+  const InstDesc& d = plan.stats.L.one;
+  hipLaunchKernelGGL(k_cache_movers, dim3((unsigned)((d.n + kBlock - 1) / kBlock)), dim3(kBlock),
+                     0, s, plan.stats.L);
+  return launch_round_stats(plan, round, s, marks);
+}
+
 // --------------------------------------------------------------- threshold
 
 // Unit: one target block t.  Thread j looks at gain bucket 255 - j (summed
@@ -734,6 +921,59 @@ __global__ __launch_bounds__(kBlock) void k_approve_apply(Launch L) {
 // lambda(e) reads the old value first, so the drop (lambda_old - lambda_new)
 // * w(e) summed over touched nets checks the attributed total.  Single
 // instance: contiguous XCD-aware runs of chunks.
+// Gain cache update of one touched net e (subsection "Gain Caching"): the
+// four update rules, summed over all moves of the round, change p_i(v) for
+// every pin v by +w(e) when block i lost its last pin of e and by -w(e)
+// when it gained its first, and b(v) of a pin that did not move (block c)
+// by +w(e) when c now holds exactly one pin of e and by -w(e) when it no
+// longer does.  Moved vertices get b recomputed after the round.  Every lane
+// of the group calls this with its record word before (old_w) and after
+// (new_w) the round; the pins are also made eligible.
+template <int G>
+__device__ void cache_net_delta(const InstDesc& D, long long e, int wk, int gl, unsigned old_w,
+                                unsigned new_w, long long b, long long t) {
+  const int base = lane_id() - gl;
+  unsigned lo[8], ln[8], so[8], sn[8];
+#pragma unroll
+  for (int x = 0; x < 8; ++x) {
+    const int lam = 2 + (x < wk ? x : 0), sgl = 2 + wk + (x < wk ? x : 0);
+    lo[x] = __shfl(old_w, base + lam);
+    ln[x] = __shfl(new_w, base + lam);
+    so[x] = __shfl(old_w, base + sgl);
+    sn[x] = __shfl(new_w, base + sgl);
+  }
+  const int w = D.ewgt ? D.ewgt[e] : 1;
+  const int ks = cache_stride(D.k);
+  int* cb = D.cache;
+  int* cp = D.cache + cache_pbase(D.n);
+  for (long long p = b + gl; p < t; p += G) {
+    const int v = D.pins[p];
+    D.eligible[v] = 1;
+#pragma unroll
+    for (int x = 0; x < 8; ++x) {
+      if (x >= wk) break;
+      unsigned d = lo[x] ^ ln[x];
+      while (d) {
+        const int bit = __ffs(d) - 1;
+        d &= d - 1;
+        atomicAdd(&cp[(long long)v * ks + x * 32 + bit], ((lo[x] >> bit) & 1u) ? w : -w);
+      }
+    }
+    if (!D.moved[v]) {
+      const int c = D.part[v];
+      unsigned dso = 0, dsn = 0;
+#pragma unroll
+      for (int x = 0; x < 8; ++x)
+        if (x == (c >> 5)) {
+          dso = so[x];
+          dsn = sn[x];
+        }
+      const int bit = c & 31;
+      if (((dso ^ dsn) >> bit) & 1u) atomicAdd(&cb[v], ((dsn >> bit) & 1u) ? w : -w);
+    }
+  }
+}
+
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_finalize(Launch L) {
   __shared__ int s_list[kFinalChunk];
@@ -767,13 +1007,19 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Launch L) {
         lam_old = (int)rec[1];
         w = (int)rec[0];
       }
+      // gain cache: the record's Lambda / S words before this round
+      const unsigned old_word = D.cache && gl >= 2 && gl < 2 + 2 * wk ? rec[gl] : 0u;
       NetBits nb = net_bits<G>(k, gl, [&](int i2) { return row[i2]; }, [&](int, int) {});
       if (gl >= 1 && gl < 2 + 2 * wk) rec[gl] = nb.word;
       if (D.view != kViewFull) write_view(D.view_ptr, e, D.view, gl, nb);
       if (gl == 1) dcheck += (long long)(lam_old - nb.lambda) * w;
       if (gl == 0) D.touched[e] = 0;
       const long long b = D.eptr[e], t = D.eptr[e + 1];
-      for (long long p = b + gl; p < t; p += G) D.eligible[D.pins[p]] = 1;
+      if (D.cache) {
+        cache_net_delta<G>(D, e, wk, gl, old_word, nb.word, b, t);
+      } else {
+        for (long long p = b + gl; p < t; p += G) D.eligible[D.pins[p]] = 1;
+      }
     }
     __syncthreads();
   }
@@ -898,9 +1144,19 @@ hipError_t launch_round_front(const RoundPlan& plan, hipStream_t s, hipEvent_t* 
 
 // Finalize (touched nets, next eligible set) and the round record.
 hipError_t launch_round_back(const RoundPlan& plan, int round, hipStream_t s, hipEvent_t* marks) {
+  hipError_t e = launch_round_finalize(plan, s, marks);
+  if (e != hipSuccess) return e;
+  return launch_round_stats(plan, round, s, marks);
+}
+
+hipError_t launch_round_finalize(const RoundPlan& plan, hipStream_t s, hipEvent_t* marks) {
   if (marks) (void)hipEventRecord(marks[2], s);
   for (const PlanLaunch& pl : plan.finalize)
     hipLaunchKernelGGL((FinalizeKernel)pl.kernel, dim3(pl.grid), dim3(kBlock), 0, s, pl.L);
+  return hipGetLastError();
+}
+
+hipError_t launch_round_stats(const RoundPlan& plan, int round, hipStream_t s, hipEvent_t* marks) {
   Launch ls = plan.stats.L;
   ls.round = round;
   hipLaunchKernelGGL(k_round_stats, dim3(plan.stats.grid), dim3(kBlock), 0, s, ls);

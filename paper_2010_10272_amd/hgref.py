@@ -166,6 +166,14 @@ def _load():
     lib.hg_lp_round_exact.restype = i32
     lib.hg_refine_exact.argtypes = [vp, i32, dbl, i32, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.hg_refine_exact.restype = i32
+    lib.hg_gain_cache_bytes.argtypes = [i32, i32]
+    lib.hg_gain_cache_bytes.restype = i64
+    lib.hg_gain_cache_init.argtypes = [vp, i32, vp, vp, vp, vp]
+    lib.hg_gain_cache_init.restype = i32
+    lib.hg_lp_round_cached.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.hg_lp_round_cached.restype = i32
+    lib.hg_refine_cached.argtypes = [vp, i32, dbl, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.hg_refine_cached.restype = i32
     lib.hg_last_error.argtypes = []
     lib.hg_last_error.restype = ctypes.c_char_p
     return lib
@@ -717,3 +725,41 @@ def hg_refine_exact(g, st, eps, rounds, stats, ws, stream=None):
                                 _ptr(st.phi), _ptr(st.netstate), _ptr(st.block_w),
                                 _ptr(st.eligible), _ptr(stats), _ptr(st.km1), _ptr(ws),
                                 ws.numel(), _stream(stream)))
+
+
+# ---------------------------------------------------------------- gain cache
+
+def gain_cache(g, k):
+    """A device buffer for the gain cache of g at k blocks (int32, 16-byte
+    aligned as every torch allocation is)."""
+    nbytes = int(_lib.hg_gain_cache_bytes(g.n, int(k)))
+    if nbytes < 0:
+        raise ValueError("bad n or k for a gain cache")
+    return torch.empty(nbytes // 4, dtype=torch.int32, device=g.device)
+
+
+def cache_views(g, k, cache):
+    """(b[n], w(I)[n], p[n, k]) views of a gain-cache buffer."""
+    n, k = g.n, int(k)
+    pbase = (2 * n + 3) & ~3
+    ks = (k + 3) & ~3
+    return cache[:n], cache[n:2 * n], cache[pbase:pbase + n * ks].view(n, ks)[:, :k]
+
+
+def hg_gain_cache_init(g, k, part, netstate, cache, stream=None):
+    _check(_lib.hg_gain_cache_init(g.handle, int(k), _ptr(part), _ptr(netstate), _ptr(cache),
+                                   _stream(stream)))
+
+
+def hg_lp_round_cached(g, st, max_block_w, stats, cache, stream=None):
+    _check(_lib.hg_lp_round_cached(g.handle, st.k, int(max_block_w), _ptr(st.part),
+                                   _ptr(st.phi), _ptr(st.netstate), _ptr(st.block_w),
+                                   _ptr(st.eligible), _ptr(st.moved), _ptr(st.km1), _ptr(stats),
+                                   _ptr(cache), _stream(stream)))
+
+
+def hg_refine_cached(g, st, eps, rounds, stats, cache, stream=None):
+    _check(_lib.hg_refine_cached(g.handle, st.k, float(eps), int(rounds), _ptr(st.part),
+                                 _ptr(st.phi), _ptr(st.netstate), _ptr(st.block_w),
+                                 _ptr(st.eligible), _ptr(st.moved), _ptr(stats), _ptr(st.km1),
+                                 _ptr(cache), _stream(stream)))
