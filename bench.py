@@ -470,6 +470,59 @@ def monotone_leg(args, H, dev):
     return out
 
 
+def cached_leg(args, H, dev):
+    """Gain-cache rounds (select reads b, w(I) and the penalty rows; the
+    finalize applies the round's net deltas) beside plain rounds on the
+    sparse-matrix workload at k = 8 and 64, 10 rounds from the same start;
+    both must give the same partition and round records.  Per-phase times
+    come from the library's own event timing."""
+    import torch
+    import synth
+    inst = sparse_instance()
+    out = {}
+    for k in KS:
+        ik = synth.with_k(inst, k)
+        g = H.hg_load_csr(inst.n, inst.eptr, inst.pins, inst.c, inst.w, k_max=k, device=dev)
+        st = H.State(g, k, ik.part)
+        cache = H.gain_cache(g, k)
+        stats = torch.zeros(ROUNDS * H.STATS_WORDS, dtype=torch.int64, device=dev)
+        part0 = st.part.clone()
+        res, finals = {}, {}
+        for mode in ("plain", "cached"):
+            xs = []
+            phases = {p: 0.0 for p in H.HG_PHASES}
+            timed = 0
+            for rep in range(args.mono_reps + 2):
+                st.part.copy_(part0)
+                profile = rep == args.mono_reps + 1
+                H.hg_timing_enable(g, profile)
+                a, b = _events(torch)
+                a.record()
+                if mode == "plain":
+                    H.hg_refine(g, st, inst.eps, ROUNDS, stats, use_graph=False)
+                else:
+                    H.hg_refine_cached(g, st, inst.eps, ROUNDS, stats, cache)
+                b.record()
+                b.synchronize()
+                if profile:
+                    ph, timed = H.hg_timing_collect(g)
+                    phases = {p: v / max(timed, 1) for p, v in ph.items()}
+                    H.hg_timing_enable(g, False)
+                elif rep:
+                    xs.append(a.elapsed_time(b))
+            finals[mode] = (st.part.clone(), stats.clone())
+            res[mode] = {"refine_ms": percentile(xs, 50),
+                         "round_ms": percentile(xs, 50) / ROUNDS,
+                         "phase_ms_per_round": phases,
+                         "pins_per_s": inst.P * ROUNDS / (percentile(xs, 50) / 1e3)}
+        assert torch.equal(finals["plain"][0], finals["cached"][0]), "cached rounds differ"
+        assert torch.equal(finals["plain"][1], finals["cached"][1]), "cached records differ"
+        res["cache_bytes"] = cache.numel() * 4
+        out["k%d" % k] = res
+        g.free()
+    return out
+
+
 def plain_leg(args, H, dev):
     """The plain workload (module docstring): returns the JSON record."""
     import torch
@@ -641,8 +694,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-rounds", type=int, default=4)
     ap.add_argument("--latency-reps", type=int, default=5)
-    ap.add_argument("--legs", default="plain,batched,served,monotone",
-                    help="comma list of plain, batched, served, monotone")
+    ap.add_argument("--legs", default="plain,batched,served,monotone,cached",
+                    help="comma list of plain, batched, served, monotone, cached")
     ap.add_argument("--mono-reps", type=int, default=3)
     ap.add_argument("--served-seconds", type=float, default=10.0,
                     help="length of the open-loop request trace")
@@ -677,6 +730,10 @@ def main():
         torch.cuda.empty_cache()
         print("monotone rounds ...", file=sys.stderr, flush=True)
         out["monotone"] = monotone_leg(args, H, dev)
+    if "cached" in legs:
+        torch.cuda.empty_cache()
+        print("gain-cache rounds ...", file=sys.stderr, flush=True)
+        out["cached"] = cached_leg(args, H, dev)
     print(json.dumps(out), flush=True)
 
 

@@ -946,20 +946,28 @@ __device__ void cache_net_delta(const InstDesc& D, long long e, int wk, int gl, 
   const int ks = cache_stride(D.k);
   int* cb = D.cache;
   int* cp = D.cache + cache_pbase(D.n);
+  unsigned dl = 0, ds = 0;
+#pragma unroll
+  for (int x = 0; x < 8; ++x) {
+    dl |= lo[x] ^ ln[x];
+    ds |= so[x] ^ sn[x];
+  }
   for (long long p = b + gl; p < t; p += G) {
     const int v = D.pins[p];
     D.eligible[v] = 1;
+    if (dl) {
 #pragma unroll
-    for (int x = 0; x < 8; ++x) {
-      if (x >= wk) break;
-      unsigned d = lo[x] ^ ln[x];
-      while (d) {
-        const int bit = __ffs(d) - 1;
-        d &= d - 1;
-        atomicAdd(&cp[(long long)v * ks + x * 32 + bit], ((lo[x] >> bit) & 1u) ? w : -w);
+      for (int x = 0; x < 8; ++x) {
+        if (x >= wk) break;
+        unsigned d = lo[x] ^ ln[x];
+        while (d) {
+          const int bit = __ffs(d) - 1;
+          d &= d - 1;
+          atomicAdd(&cp[(long long)v * ks + x * 32 + bit], ((lo[x] >> bit) & 1u) ? w : -w);
+        }
       }
     }
-    if (!D.moved[v]) {
+    if (ds && !D.moved[v]) {
       const int c = D.part[v];
       unsigned dso = 0, dsn = 0;
 #pragma unroll
