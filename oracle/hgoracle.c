@@ -639,3 +639,177 @@ int or_refine_exact(int32_t n, int32_t m, const int64_t* eptr, const int32_t* pi
   free(vptr); free(vnets); free(eligible); free(moved);
   return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Rebalancing (section "Rebalancing"), one synchronous deterministic round. */
+/* The paper moves vertices out of overloaded blocks, non-negative gains     */
+/* first (at once) and then the least-loss moves from priority queues, while */
+/* the block is still overloaded.  Read for a synchronous round:             */
+/*  1. overloaded blocks O = {a : c(V_a) > L_max}; every vertex u of a block */
+/*     in O is considered;                                                   */
+/*  2. its target is the best block i != Pi(u) with c(V_i) + c(u) <= L_max  */
+/*     -- any block, not only neighbouring ones -- by (g_i(u) desc, c(V_i)  */
+/*     asc, i asc), g_i(u) = b(u) - p_i(u) of any sign; none: no candidate;  */
+/*  3. per source block a, candidates in (gain desc, id asc) order: the      */
+/*     shortest prefix whose weight reaches the excess c(V_a) - L_max is     */
+/*     proposed (all of them if the total falls short) -- gain order puts    */
+/*     the non-negative moves first and then the smallest losses;            */
+/*  4. per target block t, proposed moves in (gain desc, id asc) order: the  */
+/*     longest prefix with c(V_t) + prefix weight <= L_max is approved;      */
+/*  5. approved moves are applied at once; pins of nets holding a moved      */
+/*     vertex become eligible (for label propagation afterwards).            */
+/* All decisions read the round-start state.  The record: eligible = vertices*/
+/* considered, boundary = moves proposed, candidates = vertices with a       */
+/* target, approved = moves applied, active_pins = sum of d(u) over the      */
+/* considered vertices; the other fields as in a label-propagation round.    */
+/* A balanced partition is left unchanged (an empty record).                  */
+/* ------------------------------------------------------------------------ */
+
+typedef struct { int64_t gain; int32_t u; int32_t a; int32_t t; int32_t c; } or_rb_cand;
+
+static int cmp_rb_source(const void* x, const void* y) {
+  const or_rb_cand* a = (const or_rb_cand*)x;
+  const or_rb_cand* b = (const or_rb_cand*)y;
+  if (a->a != b->a) return a->a < b->a ? -1 : 1;
+  if (a->gain != b->gain) return a->gain > b->gain ? -1 : 1;
+  return (a->u > b->u) - (a->u < b->u);
+}
+
+static int cmp_rb_target(const void* x, const void* y) {
+  const or_rb_cand* a = (const or_rb_cand*)x;
+  const or_rb_cand* b = (const or_rb_cand*)y;
+  if (a->t != b->t) return a->t < b->t ? -1 : 1;
+  if (a->gain != b->gain) return a->gain > b->gain ? -1 : 1;
+  return (a->u > b->u) - (a->u < b->u);
+}
+
+int or_rebalance_round(int32_t n, int32_t m, const int64_t* eptr, const int32_t* pins,
+                       const int64_t* vptr, const int32_t* vnets, const int32_t* c,
+                       const int32_t* w, int32_t k, int64_t lmax, int32_t* part,
+                       uint8_t* eligible, uint8_t* moved, or_round_stats* st) {
+  int32_t* phi = (int32_t*)malloc(sizeof(int32_t) * (size_t)m * (size_t)k);
+  int32_t* lambda = (int32_t*)malloc(sizeof(int32_t) * (size_t)m);
+  uint32_t* bits = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)m * (size_t)((k + 31) / 32));
+  int64_t* W = (int64_t*)malloc(sizeof(int64_t) * (size_t)k);
+  int64_t* acc = (int64_t*)malloc(sizeof(int64_t) * (size_t)k);
+  int64_t* gains = (int64_t*)malloc(sizeof(int64_t) * (size_t)k);
+  or_rb_cand* cand = (or_rb_cand*)malloc(sizeof(or_rb_cand) * (size_t)n + 1);
+  uint8_t* touched = (uint8_t*)malloc((size_t)m);
+  if (!phi || !lambda || !bits || !W || !acc || !gains || !cand || !touched) return OR_ERR_INVALID;
+  memset(st, 0, sizeof(*st));
+  or_pin_counts(m, eptr, pins, part, k, phi);
+  or_connectivity(m, k, phi, lambda, bits);
+  const int64_t km1_before = or_km1(m, w, lambda);
+  or_block_weights(n, c, part, k, W);
+
+  /* steps 1-2: candidates of the overloaded blocks */
+  int32_t nc = 0;
+  for (int32_t u = 0; u < n; ++u) {
+    moved[u] = 0;
+    const int32_t a = part[u];
+    if (W[a] <= lmax) continue;
+    st->eligible += 1;
+    st->active_pins += vptr[u + 1] - vptr[u];
+    /* g_i(u) = b(u) - p_i(u) for every block, from the pin counts */
+    int64_t b = 0;
+    for (int32_t i = 0; i < k; ++i) gains[i] = 0;
+    for (int64_t j = vptr[u]; j < vptr[u + 1]; ++j) {
+      const int32_t e = vnets[j];
+      if (phi[(int64_t)e * k + a] == 1) b += ww(w, e);
+      for (int32_t i = 0; i < k; ++i)
+        if (phi[(int64_t)e * k + i] == 0) gains[i] -= ww(w, e);
+    }
+    int32_t t = -1;
+    for (int32_t i = 0; i < k; ++i) {
+      if (i == a || W[i] + cw(c, u) > lmax) continue;
+      const int64_t g = b + gains[i];
+      if (t < 0 || g > b + gains[t] || (g == b + gains[t] && (W[i] < W[t] ||
+                                                              (W[i] == W[t] && i < t))))
+        t = i;
+    }
+    if (t < 0) continue;
+    cand[nc].gain = b + gains[t];
+    cand[nc].u = u;
+    cand[nc].a = a;
+    cand[nc].t = t;
+    cand[nc].c = (int32_t)cw(c, u);
+    ++nc;
+  }
+  st->candidates = nc;
+
+  /* step 3: shortest prefix per source reaching its excess */
+  qsort(cand, (size_t)nc, sizeof(or_rb_cand), cmp_rb_source);
+  for (int32_t i = 0; i < k; ++i) acc[i] = 0;
+  int32_t np = 0;
+  for (int32_t j = 0; j < nc; ++j) {
+    const int32_t a = cand[j].a;
+    if (acc[a] < W[a] - lmax) {
+      acc[a] += cand[j].c;
+      cand[np++] = cand[j];
+    }
+  }
+  st->boundary = np;
+
+  /* step 4: longest prefix per target that fits */
+  qsort(cand, (size_t)np, sizeof(or_rb_cand), cmp_rb_target);
+  for (int32_t i = 0; i < k; ++i) acc[i] = 0;
+  int32_t closed_t = -1;
+  memset(touched, 0, (size_t)m);
+  for (int32_t j = 0; j < np; ++j) {
+    const int32_t t = cand[j].t, u = cand[j].u;
+    if (t == closed_t) continue;
+    if (W[t] + acc[t] + cand[j].c > lmax) {
+      closed_t = t;            /* the prefix of this target ends here */
+      continue;
+    }
+    acc[t] += cand[j].c;
+    /* step 5 (applied below, after every decision is taken) */
+    moved[u] = 1;
+    st->approved += 1;
+    st->moved_pins += vptr[u + 1] - vptr[u];
+  }
+  for (int32_t j = 0; j < np; ++j)
+    if (moved[cand[j].u]) part[cand[j].u] = cand[j].t;
+  for (int32_t u = 0; u < n; ++u)
+    if (moved[u])
+      for (int64_t j = vptr[u]; j < vptr[u + 1]; ++j) touched[vnets[j]] = 1;
+  for (int32_t e = 0; e < m; ++e) {
+    if (!touched[e]) continue;
+    st->touched_nets += 1;
+    for (int64_t p = eptr[e]; p < eptr[e + 1]; ++p) eligible[pins[p]] = 1;
+  }
+  or_pin_counts(m, eptr, pins, part, k, phi);
+  or_connectivity(m, k, phi, lambda, bits);
+  or_block_weights(n, c, part, k, W);
+  st->km1_after = or_km1(m, w, lambda);
+  st->km1_delta = km1_before - st->km1_after;
+  st->max_block_weight = W[0];
+  for (int32_t i = 1; i < k; ++i) if (W[i] > st->max_block_weight) st->max_block_weight = W[i];
+  free(phi); free(lambda); free(bits); free(W); free(acc); free(gains); free(cand); free(touched);
+  return OR_OK;
+}
+
+/* `rounds` rebalancing rounds (every one recorded; once balanced, or once a */
+/* round moves nothing, the later rounds are empty).  eligible is updated as */
+/* each round says; *km1_out = km1 at the end.                               */
+int or_rebalance(int32_t n, int32_t m, const int64_t* eptr, const int32_t* pins,
+                 const int32_t* c, const int32_t* w, int32_t k, int64_t lmax, int32_t rounds,
+                 int32_t* part, uint8_t* eligible, or_round_stats* stats, int64_t* km1_out) {
+  int64_t* vptr = (int64_t*)malloc(sizeof(int64_t) * ((size_t)n + 1));
+  int32_t* vnets = (int32_t*)malloc(sizeof(int32_t) * (size_t)eptr[m] + 1);
+  uint8_t* moved = (uint8_t*)malloc((size_t)n);
+  int32_t* phi = (int32_t*)malloc(sizeof(int32_t) * (size_t)m * (size_t)k);
+  int32_t* lambda = (int32_t*)malloc(sizeof(int32_t) * (size_t)m);
+  uint32_t* bits = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)m * (size_t)((k + 31) / 32));
+  if (!vptr || !vnets || !moved || !phi || !lambda || !bits) return OR_ERR_INVALID;
+  or_incidence(n, m, eptr, pins, vptr, vnets);
+  int rc = OR_OK;
+  for (int32_t r = 0; r < rounds && rc == OR_OK; ++r)
+    rc = or_rebalance_round(n, m, eptr, pins, vptr, vnets, c, w, k, lmax, part, eligible, moved,
+                            &stats[r]);
+  or_pin_counts(m, eptr, pins, part, k, phi);
+  or_connectivity(m, k, phi, lambda, bits);
+  *km1_out = or_km1(m, w, lambda);
+  free(vptr); free(vnets); free(moved); free(phi); free(lambda); free(bits);
+  return rc;
+}

@@ -76,6 +76,12 @@ def _load():
         _lib.or_lp_round_exact.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, i32, i64, vp, vp,
                                            vp, ctypes.POINTER(RoundStats), ctypes.POINTER(i64)]
         _lib.or_lp_round_exact.restype = ctypes.c_int
+        _lib.or_rebalance_round.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, i32, i64, vp,
+                                            vp, vp, ctypes.POINTER(RoundStats)]
+        _lib.or_rebalance_round.restype = ctypes.c_int
+        _lib.or_rebalance.argtypes = [i32, i32, vp, vp, vp, vp, i32, i64, i32, vp, vp,
+                                      ctypes.POINTER(RoundStats), ctypes.POINTER(i64)]
+        _lib.or_rebalance.restype = ctypes.c_int
         _lib.or_refine_exact.argtypes = [i32, i32, vp, vp, vp, vp, i32, i64, i32, vp,
                                          ctypes.POINTER(RoundStats), ctypes.POINTER(i64)]
         _lib.or_refine_exact.restype = ctypes.c_int
@@ -273,3 +279,33 @@ def refine_exact(h, k, lmax_value, rounds, part):
     if rc != OR_OK:
         raise RuntimeError("oracle refine_exact failed: %d" % rc)
     return part, [stats[r].as_dict() for r in range(rounds)], int(km.value)
+
+
+def rebalance_round(h, k, lmax_value, part, eligible):
+    """One rebalancing round.  Returns (new_part, eligible, moved, stats)."""
+    part = np.array(part, dtype=np.int32, copy=True)
+    elig = np.array(eligible, dtype=np.uint8, copy=True)
+    moved = np.empty(h.n, np.uint8)
+    st = RoundStats()
+    vptr, vnets = h.incidence()
+    rc = _load().or_rebalance_round(h.n, h.m, _p(h.eptr), _p(h.pins), _p(vptr), _p(vnets),
+                                    _p(h.c), _p(h.w), k, int(lmax_value), _p(part), _p(elig),
+                                    _p(moved), ctypes.byref(st))
+    if rc != OR_OK:
+        raise RuntimeError("oracle rebalance_round failed: %d" % rc)
+    return part, elig, moved, st.as_dict()
+
+
+def rebalance(h, k, lmax_value, rounds, part, eligible=None):
+    """`rounds` rebalancing rounds.  Returns (part, eligible, [stats], km1)."""
+    part = np.array(part, dtype=np.int32, copy=True)
+    elig = (np.zeros(h.n, np.uint8) if eligible is None
+            else np.array(eligible, dtype=np.uint8, copy=True))
+    stats = (RoundStats * max(1, rounds))()
+    km = ctypes.c_int64(0)
+    rc = _load().or_rebalance(h.n, h.m, _p(h.eptr), _p(h.pins), _p(h.c), _p(h.w), k,
+                              int(lmax_value), rounds, _p(part), _p(elig), stats,
+                              ctypes.byref(km))
+    if rc != OR_OK:
+        raise RuntimeError("oracle rebalance failed: %d" % rc)
+    return part, elig, [stats[r].as_dict() for r in range(rounds)], int(km.value)

@@ -115,3 +115,65 @@ def lp_round(nets, n, c, w, k, lmax, part, eligible):
     stats["km1_after"] = after
     stats["max_block_weight"] = max(block_weight(new_part, c, i) for i in range(k))
     return new_part, nxt, moved, stats
+
+
+def rebalance_round(nets, n, c, w, k, lmax, part, eligible):
+    """One rebalancing round by brute force: gains as km1 deltas of single
+    moves, every block a possible target.  Same readings as the oracle:
+    vertices of blocks heavier than lmax are considered; target by (gain
+    desc, block weight asc, block id asc) among blocks that stay <= lmax;
+    per source the shortest (gain desc, id asc) prefix reaching the excess is
+    proposed; per target the longest (gain desc, id asc) prefix that fits is
+    applied; pins of nets with a moved vertex become eligible."""
+    part = list(int(x) for x in part)
+    W = [block_weight(part, c, i) for i in range(k)]
+    cw = (lambda v: 1) if c is None else (lambda v: int(c[v]))
+    stats = dict(eligible=0, boundary=0, candidates=0, approved=0, moved_pins=0,
+                 touched_nets=0, active_pins=0)
+    cands = []
+    for u in range(n):
+        a = part[u]
+        if W[a] <= lmax:
+            continue
+        stats["eligible"] += 1
+        stats["active_pins"] += len(incident(nets, u))
+        options = [(-move_gain(nets, w, part, u, i), W[i], i) for i in range(k)
+                   if i != a and W[i] + cw(u) <= lmax]
+        if options:
+            negg, _, t = min(options)
+            cands.append((a, negg, u, t))
+    stats["candidates"] = len(cands)
+    proposed = []
+    taken = [0] * k
+    for a, negg, u, t in sorted(cands):
+        if taken[a] < W[a] - lmax:
+            taken[a] += cw(u)
+            proposed.append((t, negg, u))
+    stats["boundary"] = len(proposed)
+    load = list(W)
+    blocked = set()
+    new_part = list(part)
+    moved = [0] * n
+    for t, negg, u in sorted(proposed):
+        if t in blocked:
+            continue
+        if load[t] + cw(u) > lmax:
+            blocked.add(t)
+            continue
+        load[t] += cw(u)
+        new_part[u] = t
+        moved[u] = 1
+    stats["approved"] = sum(moved)
+    stats["moved_pins"] = sum(len(incident(nets, u)) for u in range(n) if moved[u])
+    touched = [j for j, e in enumerate(nets) if any(moved[v] for v in e)]
+    stats["touched_nets"] = len(touched)
+    nxt = [int(x) for x in eligible]
+    for j in touched:
+        for v in nets[j]:
+            nxt[v] = 1
+    before = km1(nets, w, part)
+    after = km1(nets, w, new_part)
+    stats["km1_delta"] = before - after
+    stats["km1_after"] = after
+    stats["max_block_weight"] = max(block_weight(new_part, c, i) for i in range(k))
+    return new_part, nxt, moved, stats
