@@ -442,6 +442,44 @@ hg_status hg_refine_exact(hg_graph g, int32_t k, double eps, int32_t rounds, int
                           hg_round_stats* stats, int64_t* km1_out, void* workspace,
                           size_t ws_bytes, void* stream);
 
+/* -------------------------------------------------------------- rebalancing
+ * Section "Rebalancing": move vertices out of blocks heavier than L_max,
+ * non-negative gains first, then the smallest losses.  Deterministic
+ * synchronous rounds; each round, from the round-start state:
+ *   1. every vertex u of an overloaded block a (c(V_a) > L_max) picks the
+ *      best block i != a with c(V_i) + c(u) <= L_max -- any block, not only
+ *      neighbouring ones -- by (g_i(u) desc, c(V_i) asc, i asc); gains may
+ *      be negative; no such block: no candidate;
+ *   2. per source block a, the candidates in (gain desc, id asc) order: the
+ *      shortest prefix whose weight reaches the excess c(V_a) - L_max is
+ *      proposed (all of them if their total falls short);
+ *   3. per target block t, the proposals in (gain desc, id asc) order: the
+ *      longest prefix with c(V_t) + prefix weight <= L_max is applied;
+ *   4. pins of nets holding a moved vertex become eligible (others keep
+ *      their flag); moved[u] = 1 for the moved vertices, 0 for the rest.
+ * No block within L_max leaves it and no overloaded block gets heavier; a
+ * balanced partition is left as it is.  The round record (hg_round_stats)
+ * reads: eligible = vertices considered (in overloaded blocks), boundary =
+ * moves proposed, candidates = vertices with a target, approved = moves
+ * applied, active_pins = sum of d(u) over the considered vertices; the other
+ * fields as for a label-propagation round (km1_delta is negative when km1
+ * grows).
+ * ------------------------------------------------------------------------ */
+
+/* Bytes of the rebalancing workspace (device, 256-byte aligned) for n
+ * vertices and k blocks (it holds a gain cache); 0 on bad arguments. */
+size_t hg_rebalance_workspace_size(int32_t n, int32_t k);
+
+/* `rounds` rebalancing rounds on the caller's state (the buffers of
+ * hg_lp_round, describing part: hg_compute_pincounts or earlier rounds
+ * establish that), against L_max = max_block_w; stats gets one record per
+ * round (rounds after balance is restored, or after a round that moved
+ * nothing, are empty).  moved is required. */
+hg_status hg_rebalance(hg_graph g, int32_t k, int64_t max_block_w, int32_t rounds, int32_t* part,
+                       int32_t* phi, uint32_t* netstate, int64_t* block_w, uint8_t* eligible,
+                       uint8_t* moved, int64_t* km1, hg_round_stats* stats, void* workspace,
+                       size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------------------ serving
  * A request server.  Refinement jobs arrive over time.  Each is admitted
  * into a caller-provided device arena once its exact footprint

@@ -142,4 +142,11 @@ __device__ __forceinline__ void wave_expand(long long begin, int len, int* s_exc
   wave_lds_sync();
 }
 
+// A select candidate: gain in the high word, target block in the low word.
+__device__ __forceinline__ long long pack_cand(int gain, int target) {
+  return ((long long)gain << 32) | (unsigned)target;
+}
+__device__ __forceinline__ int cand_target(long long x) { return (int)(x & 0xffffffffLL); }
+__device__ __forceinline__ int cand_gain(long long x) { return (int)(x >> 32); }
+
 }  // namespace hg

@@ -283,6 +283,7 @@ namespace hg {
 // ---- error reporting (hg_last_error) ----
 hg_status fail(hg_status code, const char* fmt, ...);
 size_t moves_workspace_size(long long n, long long m, int k);
+size_t rebalance_workspace_size(long long n, int k);
 hg_status hip_fail(hipError_t e, const char* what);
 hg_status check_k(hg_graph_s* g, int k);
 

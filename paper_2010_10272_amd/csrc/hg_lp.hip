@@ -38,11 +38,6 @@
 
 namespace hg {
 
-__device__ __forceinline__ long long pack_cand(int gain, int target) {
-  return ((long long)gain << 32) | (unsigned)target;
-}
-__device__ __forceinline__ int cand_target(long long x) { return (int)(x & 0xffffffffLL); }
-__device__ __forceinline__ int cand_gain(long long x) { return (int)(x >> 32); }
 
 // XCD-aware strided split of `units` over `grid` workgroups: XCD x owns the
 // contiguous range [x*per_xcd, (x+1)*per_xcd) and its workgroups take

@@ -632,6 +632,240 @@ __global__ void k_copy_best(const long long* best, int* best_len, long long* bes
   }
 }
 
+// ------------------------------------------------------------ rebalancing
+// One synchronous rebalancing round (section "Rebalancing"): vertices of
+// overloaded blocks pick their best feasible target from a gain cache; a
+// stable sort orders the candidates by (gain desc, id asc), a second stable
+// pass groups them by source block, and a segmented scan proposes, per
+// source, the shortest prefix whose weight reaches the block's excess; the
+// proposals, regrouped by target the same way, are approved as the longest
+// prefix per target that fits under L_max, and applied.
+
+struct Rb {
+  const int* cache;            // gain cache of the round-start partition
+  long long* excess;           // [k]: c(V_i) - L_max
+  int* cnt_src;                // [k + 1]: candidates per source (sentinel k last)
+  int* cnt_tgt;                // [k + 1]: proposals per target
+  unsigned char* prop;         // [n]: proposed this round
+  int* mt;                     // [n]: target of sorted item i (own block: rejected)
+  int* gord;                   // [n]: candidates in (gain desc, id asc) order
+  long long* scan;             // [n]: exclusive prefix of item weights
+  long long* csum;             // [chunks]
+  long long* coff;             // [chunks]
+  long long* best;             // [2]: {0, n}, the apply's sequence length
+  unsigned bias;               // max incident weight: key = bias - gain >= 0
+};
+
+__global__ __launch_bounds__(kBlock) void k_rb_begin(InstDesc D, Rb R) {
+  const int k = D.k;
+  for (int i = threadIdx.x; i <= k; i += kBlock) {
+    if (i < k) R.excess[i] = D.block_w[i] - D.lmax;
+    R.cnt_src[i] = 0;
+    R.cnt_tgt[i] = 0;
+  }
+  if (threadIdx.x == 0) {
+    R.best[0] = 0;
+    R.best[1] = D.n;
+  }
+}
+
+// G lanes per vertex read its penalty row in 16-byte quads.  Every vertex
+// gets defaults (not moved, not proposed, no candidate, key 0, value u);
+// those of overloaded blocks look for the best block i != Pi(u) with
+// c(V_i) + c(u) <= L_max by (p_i(u) asc = gain desc, c(V_i) asc, i asc).
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_rb_select(InstDesc D, Rb R, unsigned* key, int* val) {
+  __shared__ long long s_W[HG_MAX_K];
+  __shared__ long long s_tmp[kBlock / kWave];
+  const int k = D.k, n = D.n;
+  const long long lmax = D.lmax;
+  for (int i = threadIdx.x; i < k; i += kBlock) s_W[i] = D.block_w[i];
+  __syncthreads();
+  const int gl = threadIdx.x % G;
+  constexpr int kPer = kBlock / G;
+  const int Q = cache_stride(k) / 4;
+  const int4* __restrict__ rows = (const int4*)(R.cache + cache_pbase(n));
+  long long n_cons = 0, n_pins = 0, n_cand = 0;
+  for (long long base = (long long)blockIdx.x * kPer; base < n; base += (long long)gridDim.x * kPer) {
+    const long long u = base + threadIdx.x / G;
+    if (u >= n) continue;
+    if (gl == 0) {
+      D.moved[u] = 0;
+      R.prop[u] = 0;
+      D.cand[u] = -1;
+      key[u] = 0;
+      val[u] = (int)u;
+    }
+    const int a = D.part[u];
+    if ((unsigned)a >= (unsigned)k) {
+      if (gl == 0) atomicOr(D.err_flags, kErrPart);
+      continue;
+    }
+    if (s_W[a] <= lmax) continue;
+    const long long cu = D.vwgt ? D.vwgt[u] : 1;
+    int bp = 0, bi = -1;
+    long long bw = 0;
+    for (int q = gl; q < Q; q += G) {
+      const int4 p4 = rows[u * Q + q];
+      const int pv[4] = {p4.x, p4.y, p4.z, p4.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int i = q * 4 + j;
+        if (i >= k || i == a) continue;
+        const long long Wi = s_W[i];
+        if (Wi + cu > lmax) continue;
+        if (bi < 0 || pv[j] < bp || (pv[j] == bp && Wi < bw)) {
+          bp = pv[j];
+          bi = i;
+          bw = Wi;
+        }
+      }
+    }
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) {
+      const int op = __shfl_xor(bp, o, G), oi = __shfl_xor(bi, o, G);
+      const long long ow = __shfl_xor(bw, o, G);
+      if (oi >= 0 && (bi < 0 || op < bp || (op == bp && (ow < bw || (ow == bw && oi < bi))))) {
+        bp = op;
+        bi = oi;
+        bw = ow;
+      }
+    }
+    if (gl != 0) continue;
+    n_cons += 1;
+    n_pins += D.vptr[u + 1] - D.vptr[u];
+    if (bi >= 0) {
+      const int g = R.cache[u] - bp;
+      D.cand[u] = pack_cand(g, bi);
+      key[u] = R.bias - (unsigned)g;
+      n_cand += 1;
+    }
+  }
+  n_cons = block_sum64(n_cons, s_tmp);
+  n_pins = block_sum64(n_pins, s_tmp);
+  n_cand = block_sum64(n_cand, s_tmp);
+  if (threadIdx.x == 0) {
+    const int sl = blockIdx.x % kSlots;
+    RoundCounters* ctr = D.ctr;
+    if (n_cons) atomicAdd(&ctr->slot[kCtrEligible][sl], (unsigned long long)n_cons);
+    if (n_pins) atomicAdd(&ctr->slot[kCtrActivePins][sl], (unsigned long long)n_pins);
+    if (n_cand) atomicAdd(&ctr->slot[kCtrCandidates][sl], (unsigned long long)n_cand);
+  }
+}
+
+// Regroup keys: item i of `order` gets key = source block (by_target = 0)
+// or, for proposals, target block (by_target = 1); everything else the
+// sentinel k.  Counts per key go to cnt[0..k].
+__global__ __launch_bounds__(kBlock) void k_rb_keys(InstDesc D, Rb R, const int* order,
+                                                    int by_target, unsigned* key_out,
+                                                    int* val_out, int* cnt) {
+  __shared__ int s_cnt[HG_MAX_K + 1];
+  const int k = D.k;
+  for (int i = threadIdx.x; i <= k; i += kBlock) s_cnt[i] = 0;
+  __syncthreads();
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (i < D.n) {
+    const int u = order[i];
+    const long long c = D.cand[u];
+    int key = k;
+    if (!by_target) {
+      R.gord[i] = u;
+      if (c != -1) key = D.part[u];
+    } else if (R.prop[u]) {
+      key = (int)(c & 0xffffffffLL);
+    }
+    key_out[i] = (unsigned)key;
+    val_out[i] = u;
+    atomicAdd(&s_cnt[key], 1);
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j <= k; j += kBlock)
+    if (s_cnt[j]) atomicAdd(&cnt[j], s_cnt[j]);
+}
+
+// Items in sorted order with their weights: c(u) for items not keyed by
+// the sentinel, else 0.
+struct RbItems {
+  const unsigned* key;
+  const int* val;
+  const int* vwgt;
+  unsigned sentinel;
+  int n;
+};
+
+__device__ __forceinline__ long long rb_weight(const RbItems& I, long long i) {
+  if (i >= I.n || I.key[i] == I.sentinel) return 0;
+  return I.vwgt ? I.vwgt[I.val[i]] : 1;
+}
+
+__global__ __launch_bounds__(kBlock) void k_rb_chunk_sums(RbItems I, long long* csum) {
+  __shared__ long long s_tmp[kBlock / kWave];
+  const long long v = rb_weight(I, (long long)blockIdx.x * kBlock + threadIdx.x);
+  const long long tot = block_sum64(v, s_tmp);
+  if (threadIdx.x == 0) csum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_rb_scan(RbItems I, const long long* coff,
+                                                    long long* scan) {
+  __shared__ long long s_tmp[kBlock / kWave];
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  long long tot;
+  const long long ex = block_excl_scan64(rb_weight(I, i), s_tmp, &tot);
+  if (i < I.n) scan[i] = coff[blockIdx.x] + ex;
+}
+
+// Start of every key's segment: exclusive scan of the counts (k + 1 <= 257
+// entries, one workgroup).
+__device__ void rb_segment_starts(const int* cnt, int k, long long* s_start, long long* s_tmp) {
+  for (int b = 0; b <= k; b += kBlock) {
+    const int i = b + threadIdx.x;
+    long long tot;
+    const long long ex = block_excl_scan64(i <= k ? cnt[i] : 0, s_tmp, &tot);
+    if (i <= k) s_start[i] = ex + (b ? s_start[b - 1] + cnt[b - 1] : 0);
+    __syncthreads();
+  }
+}
+
+// Per source: propose the items whose weight before them (same source) is
+// still below the excess.
+__global__ __launch_bounds__(kBlock) void k_rb_propose(InstDesc D, Rb R, RbItems I) {
+  __shared__ long long s_start[HG_MAX_K + 1];
+  __shared__ long long s_tmp[kBlock / kWave];
+  rb_segment_starts(R.cnt_src, D.k, s_start, s_tmp);
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  long long np = 0;
+  if (i < I.n && I.key[i] != I.sentinel) {
+    const int a = (int)I.key[i];
+    const long long pre = R.scan[i] - R.scan[s_start[a]];
+    if (pre < R.excess[a]) {
+      R.prop[I.val[i]] = 1;
+      np = 1;
+    }
+  }
+  np = block_sum64(np, s_tmp);
+  if (threadIdx.x == 0 && np)
+    atomicAdd(&D.ctr->slot[kCtrBoundary][blockIdx.x % kSlots], (unsigned long long)np);
+}
+
+// Per target: approve the items that still fit; mt[i] = target, or the
+// vertex's own block (a move the apply skips).
+__global__ __launch_bounds__(kBlock) void k_rb_approve(InstDesc D, Rb R, RbItems I) {
+  __shared__ long long s_start[HG_MAX_K + 1];
+  __shared__ long long s_tmp[kBlock / kWave];
+  rb_segment_starts(R.cnt_tgt, D.k, s_start, s_tmp);
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= I.n) return;
+  const int u = I.val[i];
+  int to = D.part[u];
+  if (I.key[i] != I.sentinel) {
+    const int t = (int)I.key[i];
+    const long long cu = I.vwgt ? I.vwgt[u] : 1;
+    const long long pre = R.scan[i] - R.scan[s_start[t]];
+    if (D.block_w[t] + pre + cu <= D.lmax) to = t;
+  }
+  R.mt[i] = to;
+}
+
 }  // namespace
 
 struct MovesLayoutBest {
@@ -777,6 +1011,161 @@ hipError_t launch_round_exact(hg_graph_s* g, InstDesc d, int round, char* ws, hi
   return launch_round_back(plan, round, s, nullptr);
 }
 
+// ------------------------------------------------------------ rebalancing
+
+struct RebalLayout {
+  size_t cache, key[2], val[2], gord, prop, mt, scan, csum, coff, excess, cnt_src, cnt_tgt, best,
+      hist, dtot, total;
+  int sort_tiles, chunks;
+};
+
+static RebalLayout rebal_layout(long long n, int k) {
+  RebalLayout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off = align256(off + bytes);
+    return at;
+  };
+  L.sort_tiles = (int)((n + kSortTile - 1) / kSortTile);
+  L.chunks = (int)((n + kBlock - 1) / kBlock);
+  L.cache = take(4 * (size_t)(cache_pbase(n) + n * (long long)cache_stride(k)));
+  for (int i = 0; i < 2; ++i) {
+    L.key[i] = take(sizeof(unsigned) * (size_t)n);
+    L.val[i] = take(sizeof(int) * (size_t)n);
+  }
+  L.gord = take(sizeof(int) * (size_t)n);
+  L.prop = take((size_t)n);
+  L.mt = take(sizeof(int) * (size_t)n);
+  L.scan = take(sizeof(long long) * (size_t)n);
+  L.csum = take(sizeof(long long) * (size_t)L.chunks);
+  L.coff = take(sizeof(long long) * (size_t)L.chunks);
+  L.excess = take(sizeof(long long) * HG_MAX_K);
+  L.cnt_src = take(sizeof(int) * (HG_MAX_K + 1));
+  L.cnt_tgt = take(sizeof(int) * (HG_MAX_K + 1));
+  L.best = take(sizeof(long long) * 2);
+  L.hist = take(sizeof(unsigned) * (size_t)kDigits * L.sort_tiles);
+  L.dtot = take(sizeof(unsigned) * kDigits);
+  L.total = off;
+  return L;
+}
+
+size_t rebalance_workspace_size(long long n, int k) { return rebal_layout(n, k).total; }
+
+// One rebalancing round of a single instance (see the kernels' comment).
+static hipError_t launch_rebalance_round(hg_graph_s* g, InstDesc d, char* ws, hipStream_t s) {
+  const RebalLayout L = rebal_layout(g->n, d.k);
+  const int n = g->n, k = d.k;
+  Rb R;
+  R.cache = (const int*)(ws + L.cache);
+  R.excess = (long long*)(ws + L.excess);
+  R.cnt_src = (int*)(ws + L.cnt_src);
+  R.cnt_tgt = (int*)(ws + L.cnt_tgt);
+  R.prop = (unsigned char*)(ws + L.prop);
+  R.mt = (int*)(ws + L.mt);
+  R.gord = (int*)(ws + L.gord);
+  R.scan = (long long*)(ws + L.scan);
+  R.csum = (long long*)(ws + L.csum);
+  R.coff = (long long*)(ws + L.coff);
+  R.best = (long long*)(ws + L.best);
+  const long long maxw = g->info.max_incident_weight;   // |gain| <= maxw
+  R.bias = (unsigned)maxw;
+  unsigned* key[2] = {(unsigned*)(ws + L.key[0]), (unsigned*)(ws + L.key[1])};
+  int* val[2] = {(int*)(ws + L.val[0]), (int*)(ws + L.val[1])};
+  hipLaunchKernelGGL(k_rb_begin, dim3(1), dim3(kBlock), 0, s, d, R);
+  hipError_t e = launch_gains(g, d, nullptr, nullptr, s, (int*)(ws + L.cache));
+  if (e != hipSuccess) return e;
+  // candidates: lanes per vertex as the penalty row needs
+  const int q = cache_stride(k) / 4;
+  int G = 1;
+  while (G < q && G < kWave) G <<= 1;
+  typedef void (*SelK)(InstDesc, Rb, unsigned*, int*);
+  SelK sel = G == 1    ? (SelK)k_rb_select<1>
+             : G == 2  ? (SelK)k_rb_select<2>
+             : G == 4  ? (SelK)k_rb_select<4>
+             : G == 8  ? (SelK)k_rb_select<8>
+             : G == 16 ? (SelK)k_rb_select<16>
+             : G == 32 ? (SelK)k_rb_select<32>
+                       : (SelK)k_rb_select<64>;
+  long long sg = ((long long)n + kBlock / G - 1) / (kBlock / G);
+  if (sg > 4096) sg = 4096;
+  hipLaunchKernelGGL(sel, dim3((unsigned)sg), dim3(kBlock), 0, s, d, R, key[0], val[0]);
+  int cur = 0;
+  auto pass = [&](int shift) {
+    SortPass P;
+    P.key_in = key[cur];
+    P.val_in = val[cur];
+    P.key_out = key[cur ^ 1];
+    P.val_out = val[cur ^ 1];
+    P.hist = (unsigned*)(ws + L.hist);
+    P.dtot = (unsigned*)(ws + L.dtot);
+    P.n = n;
+    P.tiles = L.sort_tiles;
+    P.shift = shift;
+    hipLaunchKernelGGL(k_sort_hist, dim3(L.sort_tiles), dim3(kBlock), 0, s, P);
+    hipLaunchKernelGGL(k_sort_scan, dim3(kDigits), dim3(kBlock), 0, s, P);
+    hipLaunchKernelGGL(k_sort_scatter, dim3(L.sort_tiles), dim3(kBlock), 0, s, P);
+    cur ^= 1;
+  };
+  // (gain desc, id asc): keys bias - gain lie in [0, 2 * bias]
+  int bits = 1;
+  while (bits < 32 && (1ull << bits) <= 2ull * (unsigned long long)maxw) ++bits;
+  for (int shift = 0; shift < bits; shift += 8) pass(shift);
+  const int kbits = k < 256 ? 8 : 16;   // block keys 0..k, the sentinel k included
+  const unsigned grid = grid_of(n, kBlock);
+  auto scan = [&](const RbItems& I) {
+    hipLaunchKernelGGL(k_rb_chunk_sums, dim3(L.chunks), dim3(kBlock), 0, s, I, R.csum);
+    hipLaunchKernelGGL(k_prefix_top, dim3(1), dim3(kBlock), 0, s, R.csum, R.coff, L.chunks);
+    hipLaunchKernelGGL(k_rb_scan, dim3(L.chunks), dim3(kBlock), 0, s, I, R.coff, R.scan);
+  };
+  // by source block, proposals per source
+  hipLaunchKernelGGL(k_rb_keys, dim3(grid), dim3(kBlock), 0, s, d, R, val[cur], 0, key[cur ^ 1],
+                     val[cur ^ 1], R.cnt_src);
+  cur ^= 1;
+  for (int shift = 0; shift < kbits; shift += 8) pass(shift);
+  RbItems I;
+  I.vwgt = g->vwgt;
+  I.sentinel = (unsigned)k;
+  I.n = n;
+  I.key = key[cur];
+  I.val = val[cur];
+  scan(I);
+  hipLaunchKernelGGL(k_rb_propose, dim3(grid), dim3(kBlock), 0, s, d, R, I);
+  // proposals by target block, approvals per target
+  hipLaunchKernelGGL(k_rb_keys, dim3(grid), dim3(kBlock), 0, s, d, R, R.gord, 1, key[cur ^ 1],
+                     val[cur ^ 1], R.cnt_tgt);
+  cur ^= 1;
+  for (int shift = 0; shift < kbits; shift += 8) pass(shift);
+  I.key = key[cur];
+  I.val = val[cur];
+  scan(I);
+  hipLaunchKernelGGL(k_rb_approve, dim3(grid), dim3(kBlock), 0, s, d, R, I);
+  // apply the approved moves (the others carry their own block as target)
+  Seq S;
+  memset(&S, 0, sizeof(S));
+  S.mu = val[cur];
+  S.mt = R.mt;
+  S.t = n;
+  S.part = d.part;
+  S.phi = d.phi;
+  S.vptr = g->vptr;
+  S.vnets = g->vnets;
+  S.ewgt = g->ewgt;
+  S.vwgt = g->vwgt;
+  S.n = n;
+  S.k = k;
+  S.err_flags = d.err_flags;
+  hipLaunchKernelGGL(k_apply_prefix, dim3(grid), dim3(kBlock), 0, s, S, (const long long*)R.best,
+                     d);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  RoundPlan plan;
+  single_round_plan(d, plan);
+  e = launch_round_finalize(plan, s, nullptr);
+  if (e != hipSuccess) return e;
+  return launch_round_stats(plan, 0, s, nullptr);
+}
+
 }  // namespace hg
 
 using hg::check_k;
@@ -876,6 +1265,39 @@ hg_status hg_refine_exact(hg_graph g, int32_t k, double eps, int32_t rounds, int
   for (int r = 0; r < rounds; ++r) {
     d.stats = stats + r;
     HG_TRY(hg::launch_round_exact(g, d, 0, (char*)workspace, s), "monotone round");
+  }
+  return HG_OK;
+}
+
+
+size_t hg_rebalance_workspace_size(int32_t n, int32_t k) {
+  if (n < 1 || k < 2 || k > HG_MAX_K) return 0;
+  return hg::rebalance_workspace_size(n, k);
+}
+
+hg_status hg_rebalance(hg_graph g, int32_t k, int64_t max_block_w, int32_t rounds, int32_t* part,
+                       int32_t* phi, uint32_t* netstate, int64_t* block_w, uint8_t* eligible,
+                       uint8_t* moved, int64_t* km1, hg_round_stats* stats, void* workspace,
+                       size_t ws_bytes, void* stream) {
+  hg_status st = check_k(g, k);
+  if (st != HG_OK) return st;
+  if (rounds < 0) return fail(HG_ERR_INVALID, "rounds must be >= 0");
+  if (max_block_w < 0) return fail(HG_ERR_INVALID, "max_block_w must be >= 0");
+  if (!part || !phi || !netstate || !block_w || !eligible || !moved || !km1 ||
+      (rounds > 0 && !stats))
+    return fail(HG_ERR_INVALID, "part, phi, netstate, block_w, eligible, moved, km1 and stats "
+                                "must be non-NULL");
+  const size_t need = hg::rebalance_workspace_size(g->n, k);
+  if (!workspace || ws_bytes < need)
+    return fail(HG_ERR_WORKSPACE, "rebalance workspace needs %zu bytes (got %zu)", need, ws_bytes);
+  if (((uintptr_t)workspace & 255) != 0)
+    return fail(HG_ERR_INVALID, "the rebalance workspace must be 256-byte aligned");
+  hg::InstDesc d = hg::make_desc(g, k, max_block_w, part, phi, netstate, (long long*)block_w,
+                                 eligible, moved, (long long*)km1, stats);
+  for (int r = 0; r < rounds; ++r) {
+    d.stats = stats + r;
+    HG_TRY(hg::launch_rebalance_round(g, d, (char*)workspace, (hipStream_t)stream),
+           "rebalance round");
   }
   return HG_OK;
 }

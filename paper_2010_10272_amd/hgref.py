@@ -174,6 +174,10 @@ def _load():
     lib.hg_lp_round_cached.restype = i32
     lib.hg_refine_cached.argtypes = [vp, i32, dbl, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.hg_refine_cached.restype = i32
+    lib.hg_rebalance_workspace_size.argtypes = [i32, i32]
+    lib.hg_rebalance_workspace_size.restype = sz
+    lib.hg_rebalance.argtypes = [vp, i32, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.hg_rebalance.restype = i32
     lib.hg_last_error.argtypes = []
     lib.hg_last_error.restype = ctypes.c_char_p
     return lib
@@ -763,3 +767,21 @@ def hg_refine_cached(g, st, eps, rounds, stats, cache, stream=None):
                                  _ptr(st.phi), _ptr(st.netstate), _ptr(st.block_w),
                                  _ptr(st.eligible), _ptr(st.moved), _ptr(stats), _ptr(st.km1),
                                  _ptr(cache), _stream(stream)))
+
+
+# ---------------------------------------------------------------- rebalancing
+
+def rebalance_workspace(g, k):
+    nbytes = int(_lib.hg_rebalance_workspace_size(g.n, int(k)))
+    if nbytes == 0:
+        raise ValueError("bad n or k for a rebalance workspace")
+    return torch.empty(nbytes, dtype=torch.uint8, device=g.device)
+
+
+def hg_rebalance(g, st, max_block_w, rounds, stats, ws, stream=None):
+    """`rounds` rebalancing rounds on State st (its pin counts must describe
+    st.part); stats: int64 device tensor of rounds * STATS_WORDS entries."""
+    _check(_lib.hg_rebalance(g.handle, st.k, int(max_block_w), int(rounds), _ptr(st.part),
+                             _ptr(st.phi), _ptr(st.netstate), _ptr(st.block_w),
+                             _ptr(st.eligible), _ptr(st.moved), _ptr(st.km1), _ptr(stats),
+                             _ptr(ws), ws.numel(), _stream(stream)))
