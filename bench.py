@@ -523,6 +523,55 @@ def cached_leg(args, H, dev):
     return out
 
 
+def rebalance_leg(args, H, dev):
+    """Rebalancing rounds on the sparse-matrix workload at k = 8 and 64 from
+    an overloaded start: a seeded 10% of the vertices piled into block 0 (and
+    block 1 at k = 64) on top of the strip partition; 4 rounds."""
+    import numpy as np
+    import torch
+    import synth
+    inst = sparse_instance()
+    out = {}
+    RB_ROUNDS = 4
+    for k in KS:
+        ik = synth.with_k(inst, k)
+        rng = np.random.default_rng(11)
+        part0 = ik.part.copy()
+        pick = rng.random(inst.n) < 0.1
+        part0[pick] = rng.choice(np.array([0] if k == 8 else [0, 1], np.int32), int(pick.sum()))
+        g = H.hg_load_csr(inst.n, inst.eptr, inst.pins, inst.c, inst.w, k_max=k, device=dev)
+        L = H.hg_max_block_weight(g, k, inst.eps)
+        st = H.State(g, k, part0)
+        ws = H.rebalance_workspace(g, k)
+        stats = torch.zeros(RB_ROUNDS * H.STATS_WORDS, dtype=torch.int64, device=dev)
+        p0 = st.part.clone()
+        xs = []
+        for rep in range(args.mono_reps + 1):
+            st.part.copy_(p0)
+            st.eligible.zero_()
+            H.hg_compute_pincounts(g, st)
+            km0 = int(st.km1.item())
+            w0 = int(st.block_w.max().item())
+            a, b = _events(torch)
+            a.record()
+            H.hg_rebalance(g, st, L, RB_ROUNDS, stats, ws)
+            b.record()
+            b.synchronize()
+            if rep:
+                xs.append(a.elapsed_time(b))
+        recs = H.stats_to_dicts(stats)
+        ms = percentile(xs, 50)
+        out["k%d" % k] = {
+            "rounds": RB_ROUNDS, "ms": ms, "round_ms": ms / RB_ROUNDS,
+            "l_max": L, "max_block_weight_before": w0,
+            "max_block_weight_after": [r["max_block_weight"] for r in recs],
+            "moves": [r["approved"] for r in recs], "considered": recs[0]["eligible"],
+            "km1_before": km0, "km1_after": recs[-1]["km1_after"],
+            "pins_per_s": inst.P * RB_ROUNDS / (ms / 1e3)}
+        g.free()
+    return out
+
+
 def plain_leg(args, H, dev):
     """The plain workload (module docstring): returns the JSON record."""
     import torch
@@ -694,8 +743,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-rounds", type=int, default=4)
     ap.add_argument("--latency-reps", type=int, default=5)
-    ap.add_argument("--legs", default="plain,batched,served,monotone,cached",
-                    help="comma list of plain, batched, served, monotone, cached")
+    ap.add_argument("--legs", default="plain,batched,served,monotone,cached,rebalance",
+                    help="comma list of plain, batched, served, monotone, cached, rebalance")
     ap.add_argument("--mono-reps", type=int, default=3)
     ap.add_argument("--served-seconds", type=float, default=10.0,
                     help="length of the open-loop request trace")
@@ -734,6 +783,10 @@ def main():
         torch.cuda.empty_cache()
         print("gain-cache rounds ...", file=sys.stderr, flush=True)
         out["cached"] = cached_leg(args, H, dev)
+    if "rebalance" in legs:
+        torch.cuda.empty_cache()
+        print("rebalancing rounds ...", file=sys.stderr, flush=True)
+        out["rebalance"] = rebalance_leg(args, H, dev)
     print(json.dumps(out), flush=True)
 
 
