@@ -813,3 +813,110 @@ int or_rebalance(int32_t n, int32_t m, const int64_t* eptr, const int32_t* pins,
   free(vptr); free(vnets); free(moved); free(phi); free(lambda); free(bits);
   return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Contraction (section "Coarsening", subsection "Contraction") of a vertex  */
+/* clustering cluster[v] in [0, n):                                          */
+/*  1. cluster ids are renumbered to 0..n'-1 in increasing id order (the    */
+/*     rank of the id among the used ones): map[v];                          */
+/*  2. c'(x) = sum of c(v) over map[v] = x;                                  */
+/*  3. every net's pins are mapped and duplicates removed; the pins of a     */
+/*     coarse net are listed in increasing order;                            */
+/*  4. nets left with a single pin are dropped;                              */
+/*  5. nets with the same pin set are one net whose weight is the sum; it    */
+/*     keeps the place of the lowest original net id among them;            */
+/*  6. coarse nets are numbered in increasing order of those ids.            */
+/* Written from the definition: identical nets are found by sorting the     */
+/* nets by (size, pins) and comparing neighbours; no fingerprints.           */
+/* Outputs (capacity n, n, m+1, P, m): map, cvwgt, ceptr, cpins, cewgt;      */
+/* sizes[0..2] = n', m', P'.  Returns OR_ERR_INVALID for a cluster id        */
+/* outside [0, n) and OR_ERR_UNSUPPORTED when a cluster weighs >= 2^31.      */
+/* ------------------------------------------------------------------------ */
+
+typedef struct { const int32_t* pins; int64_t size; int32_t id; } or_net_ref;
+
+static int cmp_net_ref(const void* x, const void* y) {
+  const or_net_ref* a = (const or_net_ref*)x;
+  const or_net_ref* b = (const or_net_ref*)y;
+  if (a->size != b->size) return a->size < b->size ? -1 : 1;
+  for (int64_t i = 0; i < a->size; ++i)
+    if (a->pins[i] != b->pins[i]) return a->pins[i] < b->pins[i] ? -1 : 1;
+  return (a->id > b->id) - (a->id < b->id);
+}
+
+int or_contract(int32_t n, int32_t m, const int64_t* eptr, const int32_t* pins,
+                const int32_t* c, const int32_t* w, const int32_t* cluster, int32_t* map,
+                int32_t* cvwgt, int64_t* ceptr, int32_t* cpins, int32_t* cewgt,
+                int64_t* sizes) {
+  if (n < 1 || m < 0) return OR_ERR_INVALID;
+  const size_t nn = (size_t)(uint32_t)n;
+  for (int32_t v = 0; v < n; ++v)
+    if (cluster[v] < 0 || cluster[v] >= n) return OR_ERR_INVALID;
+  /* 1. renumbering */
+  int32_t* rank = (int32_t*)calloc(nn, sizeof(int32_t));
+  uint8_t* used = (uint8_t*)calloc(nn, 1);
+  for (int32_t v = 0; v < n; ++v) used[cluster[v]] = 1;
+  int32_t nc = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    rank[i] = nc;
+    nc += used[i];
+  }
+  for (int32_t v = 0; v < n; ++v) map[v] = rank[cluster[v]];
+  /* 2. weights */
+  int64_t* cw64 = (int64_t*)calloc(nn, sizeof(int64_t));
+  for (int32_t v = 0; v < n; ++v) cw64[map[v]] += cw(c, v);
+  int rc = OR_OK;
+  for (int32_t x = 0; x < nc; ++x) {
+    if (cw64[x] > 0x7fffffffLL) rc = OR_ERR_UNSUPPORTED;
+    cvwgt[x] = (int32_t)cw64[x];
+  }
+  /* 3-4. mapped, sorted, deduplicated pins; single-pin nets dropped */
+  const int64_t P = eptr[m];
+  int32_t* tmp = (int32_t*)malloc(sizeof(int32_t) * (size_t)(P + 1));
+  int64_t* tsize = (int64_t*)calloc((size_t)m + 1, sizeof(int64_t));
+  for (int32_t e = 0; e < m; ++e) {
+    int32_t* t = tmp + eptr[e];
+    const int64_t s = eptr[e + 1] - eptr[e];
+    for (int64_t i = 0; i < s; ++i) t[i] = map[pins[eptr[e] + i]];
+    qsort(t, (size_t)s, sizeof(int32_t), cmp_i32);
+    int64_t d = 0;
+    for (int64_t i = 0; i < s; ++i)
+      if (i == 0 || t[i] != t[i - 1]) t[d++] = t[i];
+    tsize[e] = d;
+  }
+  /* 5. identical nets: sort by (size, pins, id), equal neighbours merge */
+  or_net_ref* ref = (or_net_ref*)malloc(sizeof(or_net_ref) * ((size_t)m + 1));
+  int32_t* rep = (int32_t*)malloc(sizeof(int32_t) * ((size_t)m + 1));
+  int64_t* wsum = (int64_t*)calloc((size_t)m + 1, sizeof(int64_t));
+  int32_t nr = 0;
+  for (int32_t e = 0; e < m; ++e) {
+    rep[e] = -1;
+    if (tsize[e] < 2) continue;
+    ref[nr].pins = tmp + eptr[e];
+    ref[nr].size = tsize[e];
+    ref[nr].id = e;
+    ++nr;
+  }
+  qsort(ref, (size_t)nr, sizeof(or_net_ref), cmp_net_ref);
+  for (int32_t j = 0; j < nr; ++j) {
+    const int same = j > 0 && ref[j].size == ref[j - 1].size &&
+                     memcmp(ref[j].pins, ref[j - 1].pins, sizeof(int32_t) * (size_t)ref[j].size) == 0;
+    rep[ref[j].id] = same ? rep[ref[j - 1].id] : ref[j].id;   /* lowest id comes first */
+    wsum[rep[ref[j].id]] += ww(w, ref[j].id);
+  }
+  /* 6. output in increasing representative id */
+  int32_t mc = 0;
+  int64_t pc = 0;
+  ceptr[0] = 0;
+  for (int32_t e = 0; e < m; ++e) {
+    if (rep[e] != e) continue;
+    for (int64_t i = 0; i < tsize[e]; ++i) cpins[pc++] = tmp[eptr[e] + i];
+    cewgt[mc] = (int32_t)wsum[e];
+    ceptr[++mc] = pc;
+  }
+  sizes[0] = nc;
+  sizes[1] = mc;
+  sizes[2] = pc;
+  free(rank); free(used); free(cw64); free(tmp); free(tsize); free(ref); free(rep); free(wsum);
+  return rc;
+}

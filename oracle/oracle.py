@@ -82,6 +82,8 @@ def _load():
         _lib.or_rebalance.argtypes = [i32, i32, vp, vp, vp, vp, i32, i64, i32, vp, vp,
                                       ctypes.POINTER(RoundStats), ctypes.POINTER(i64)]
         _lib.or_rebalance.restype = ctypes.c_int
+        _lib.or_contract.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        _lib.or_contract.restype = ctypes.c_int
         _lib.or_refine_exact.argtypes = [i32, i32, vp, vp, vp, vp, i32, i64, i32, vp,
                                          ctypes.POINTER(RoundStats), ctypes.POINTER(i64)]
         _lib.or_refine_exact.restype = ctypes.c_int
@@ -309,3 +311,25 @@ def rebalance(h, k, lmax_value, rounds, part, eligible=None):
     if rc != OR_OK:
         raise RuntimeError("oracle rebalance failed: %d" % rc)
     return part, elig, [stats[r].as_dict() for r in range(rounds)], int(km.value)
+
+
+def contract(h, cluster):
+    """Contract the clustering.  Returns (map, coarse Hypergraph); the coarse
+    hypergraph has explicit weights and may have m' = 0."""
+    cl = _c(cluster, np.int32)
+    n, m, P = h.n, h.m, h.P
+    mp = np.empty(max(n, 1), np.int32)
+    cv = np.empty(max(n, 1), np.int32)
+    ce = np.empty(m + 1, np.int64)
+    cpn = np.empty(max(P, 1), np.int32)
+    cw = np.empty(max(m, 1), np.int32)
+    sizes = np.zeros(3, np.int64)
+    rc = _load().or_contract(n, m, _p(h.eptr), _p(h.pins), _p(h.c), _p(h.w), _p(cl), _p(mp),
+                             _p(cv), _p(ce), _p(cpn), _p(cw), _p(sizes))
+    if rc == OR_ERR_INVALID:
+        raise ValueError("cluster id outside [0, n)")
+    if rc != OR_OK:
+        raise OverflowError("a cluster weighs 2^31 or more")
+    nc, mc, pc = (int(x) for x in sizes)
+    coarse = Hypergraph(nc, ce[:mc + 1].copy(), cpn[:pc].copy(), cv[:nc].copy(), cw[:mc].copy())
+    return mp[:n].copy(), coarse
