@@ -480,6 +480,38 @@ hg_status hg_rebalance(hg_graph g, int32_t k, int64_t max_block_w, int32_t round
                        uint8_t* moved, int64_t* km1, hg_round_stats* stats, void* workspace,
                        size_t ws_bytes, void* stream);
 
+/* -------------------------------------------------------------- contraction
+ * Section "Coarsening", subsection "Contraction": contract a clustering of
+ * the vertices of a loaded hypergraph into a coarse hypergraph.
+ *   cluster  int32[n]   cluster id of every vertex, in [0, n) (ids need not
+ *                       be consecutive; an id out of range raises the error
+ *                       flag that hg_sync_status reports)
+ * Outputs (device, caller-owned, capacities from the fine sizes):
+ *   map      int32[n]     coarse vertex of every vertex: the rank of its
+ *                         cluster id among the used ids (increasing order)
+ *   cvwgt    int32[n]     c'(x) = sum of c(v) over map[v] = x (first n'
+ *                         entries; a sum >= 2^31 raises the error flag)
+ *   ceptr    int64[m+1]   coarse net CSR offsets (first m' + 1 entries)
+ *   cpins    int32[P]     coarse pins, increasing within each net (first P')
+ *   cewgt    int32[m]     coarse net weights (first m')
+ *   sizes    int64[3]     n', m', P'
+ * A coarse net is a fine net with its pins mapped and duplicates removed;
+ * nets left with one pin are dropped; nets with the same pin set become one
+ * net whose weight is the sum, placed at the lowest fine net id among them;
+ * coarse nets are numbered in increasing order of that id.  m' may be 0.
+ * Identical nets are found with the paper's fingerprints (sum of v^2, with
+ * the size) and pin-by-pin comparison.  km1 of any partition of the coarse
+ * hypergraph equals km1 of its projection through map.  hg_load_csr on the
+ * outputs (when m' >= 1) gives the coarse graph handle (incidence arrays).
+ * Requires P < 2^31.  The workspace (device, 256-byte aligned) is
+ * hg_contract_workspace_size(n, m, P) bytes.
+ * ------------------------------------------------------------------------ */
+size_t hg_contract_workspace_size(int32_t n, int32_t m, int64_t P);
+
+hg_status hg_contract(hg_graph g, const int32_t* cluster, int32_t* map, int32_t* cvwgt,
+                      int64_t* ceptr, int32_t* cpins, int32_t* cewgt, int64_t* sizes,
+                      void* workspace, size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------------------ serving
  * A request server.  Refinement jobs arrive over time.  Each is admitted
  * into a caller-provided device arena once its exact footprint

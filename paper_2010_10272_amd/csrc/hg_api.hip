@@ -61,6 +61,8 @@ const char* describe_err(int err) {
   if (err & hg::kErrWeight) return "vertex and net weights must be positive";
   if (err & hg::kErrDuplicate) return "a vertex appears twice in one net (nets are sets)";
   if (err & hg::kErrPart) return "a partition id lies outside [0, k)";
+  if (err & hg::kErrCluster) return "a cluster id lies outside [0, n)";
+  if (err & hg::kErrClusterWeight) return "a cluster weighs 2^31 or more";
   if (err & hg::kErrMoves)
     return "a move sequence moves a vertex twice, to a block outside [0, k) or to its own block";
   return "invalid input";

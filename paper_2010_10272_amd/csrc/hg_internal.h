@@ -38,6 +38,8 @@ enum : int {
   kErrPart = 16,       // partition id outside [0,k)
   kErrNetWeight = 32,  // total net weight >= 2^31
   kErrMoves = 64,      // a move sequence names a vertex twice, a bad target or its own block
+  kErrCluster = 128,   // cluster id outside [0,n)
+  kErrClusterWeight = 256,  // a cluster weighs 2^31 or more
 };
 
 // Same-address global atomics serialize (tens of ns each), so every
@@ -284,6 +286,7 @@ namespace hg {
 hg_status fail(hg_status code, const char* fmt, ...);
 size_t moves_workspace_size(long long n, long long m, int k);
 size_t rebalance_workspace_size(long long n, int k);
+size_t contract_workspace_size(long long n, long long m, long long P);
 hg_status hip_fail(hipError_t e, const char* what);
 hg_status check_k(hg_graph_s* g, int k);
 

@@ -178,6 +178,10 @@ def _load():
     lib.hg_rebalance_workspace_size.restype = sz
     lib.hg_rebalance.argtypes = [vp, i32, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.hg_rebalance.restype = i32
+    lib.hg_contract_workspace_size.argtypes = [i32, i32, i64]
+    lib.hg_contract_workspace_size.restype = sz
+    lib.hg_contract.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.hg_contract.restype = i32
     lib.hg_last_error.argtypes = []
     lib.hg_last_error.restype = ctypes.c_char_p
     return lib
@@ -785,3 +789,43 @@ def hg_rebalance(g, st, max_block_w, rounds, stats, ws, stream=None):
                              _ptr(st.phi), _ptr(st.netstate), _ptr(st.block_w),
                              _ptr(st.eligible), _ptr(st.moved), _ptr(st.km1), _ptr(stats),
                              _ptr(ws), ws.numel(), _stream(stream)))
+
+
+# ---------------------------------------------------------------- contraction
+
+class Coarse:
+    """Outputs of hg_contract (device tensors at their capacities) and the
+    coarse sizes n', m', P' (read back, which synchronizes)."""
+
+    def __init__(self, g):
+        dev = g.device
+        self.map = torch.empty(g.n, dtype=torch.int32, device=dev)
+        self.cvwgt = torch.empty(g.n, dtype=torch.int32, device=dev)
+        self.ceptr = torch.empty(g.m + 1, dtype=torch.int64, device=dev)
+        self.cpins = torch.empty(g.P, dtype=torch.int32, device=dev)
+        self.cewgt = torch.empty(g.m, dtype=torch.int32, device=dev)
+        self.sizes = torch.zeros(3, dtype=torch.int64, device=dev)
+
+    def read_sizes(self):
+        return tuple(int(x) for x in self.sizes.cpu().tolist())
+
+    def views(self):
+        """(map, cvwgt, ceptr, cpins, cewgt) cut to the coarse sizes."""
+        nc, mc, pc = self.read_sizes()
+        return (self.map, self.cvwgt[:nc], self.ceptr[:mc + 1], self.cpins[:pc],
+                self.cewgt[:mc])
+
+
+def contract_workspace(g):
+    nbytes = int(_lib.hg_contract_workspace_size(g.n, g.m, g.P))
+    if nbytes == 0:
+        raise ValueError("bad sizes for a contraction workspace")
+    return torch.empty(nbytes, dtype=torch.uint8, device=g.device)
+
+
+def hg_contract(g, cluster, out, ws, stream=None):
+    cluster = _dev(cluster, torch.int32, g.device)
+    _check(_lib.hg_contract(g.handle, _ptr(cluster), _ptr(out.map), _ptr(out.cvwgt),
+                            _ptr(out.ceptr), _ptr(out.cpins), _ptr(out.cewgt), _ptr(out.sizes),
+                            _ptr(ws), ws.numel(), _stream(stream)))
+    return out

@@ -3,5 +3,5 @@
 Input generation only: nothing here computes pin counts, gains or moves.
 """
 from .hypergraphs import (Instance, Request, batch_instances, describe,  # noqa: F401
-                          random_power_law, served_pool, served_trace, sparse_matrix,
+                          neighbour_clusters, random_power_law, served_pool, served_trace, sparse_matrix,
                           tiny_plain, vlsi_grid, with_k)

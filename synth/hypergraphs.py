@@ -339,6 +339,34 @@ def _big_netlist(seed):
     return vlsi_grid(seed=seed, side=2000, height=1000, m=2_100_000, k=16, rounds=10)
 
 
+def neighbour_clusters(inst, seed=6, join=0.5):
+    """A seeded clustering of the shape one coarsening pass produces: a
+    random `join` share of the vertices names a neighbour (another pin of one
+    of its nets, drawn at random) as its cluster id; the others keep their
+    own id.  Ids are vertex ids, so most of [0, n) is unused."""
+    rng = np.random.default_rng(seed)
+    n, eptr, pins = inst.n, inst.eptr, inst.pins
+    sizes = np.diff(eptr)
+    net_of = np.repeat(np.arange(inst.m), sizes)
+    # every vertex picks the incident net of its highest-priority pin slot
+    prio = rng.random(pins.shape[0])
+    order = np.argsort(pins + prio)          # by vertex, then by priority
+    last = np.ones(pins.shape[0], bool)
+    last[:-1] = pins[order][1:] != pins[order][:-1]
+    pick = np.full(n, -1, np.int64)
+    pick[pins[order][last]] = net_of[order][last]
+    cluster = np.arange(n, dtype=np.int32)
+    has = pick >= 0
+    e = pick[has]
+    first = pins[eptr[e]]
+    second = pins[np.minimum(eptr[e] + 1, eptr[e + 1] - 1)]
+    verts = np.nonzero(has)[0]
+    partner = np.where(first != verts, first, second)
+    joins = rng.random(verts.shape[0]) < join
+    cluster[verts[joins]] = partner[joins]
+    return cluster
+
+
 def describe(inst):
     sizes = np.diff(inst.eptr)
     deg = np.bincount(inst.pins, minlength=inst.n)
