@@ -572,6 +572,45 @@ def rebalance_leg(args, H, dev):
     return out
 
 
+def contract_leg(args, H, dev):
+    """Contraction of the sparse-matrix hypergraph under a seeded clustering
+    of the shape one coarsening pass makes (synth.neighbour_clusters: half of
+    the vertices join a neighbour): pins/s, the coarse sizes, and the time of
+    the oracle's contraction of the same input on the host."""
+    import torch
+    import synth
+    inst = sparse_instance()
+    cl = synth.neighbour_clusters(inst)
+    g = H.hg_load_csr(inst.n, inst.eptr, inst.pins, inst.c, inst.w, k_max=2, device=dev)
+    out = H.Coarse(g)
+    ws = H.contract_workspace(g)
+    cl_d = torch.as_tensor(cl).to(dev)
+    xs = []
+    for rep in range(args.mono_reps + 2):
+        a, b = _events(torch)
+        a.record()
+        H.hg_contract(g, cl_d, out, ws)
+        b.record()
+        b.synchronize()
+        if rep:
+            xs.append(a.elapsed_time(b))
+    H.hg_sync_status(g)
+    nc, mc, pc = out.read_sizes()
+    ms = percentile(xs, 50)
+    res = {"ms": ms, "pins_per_s": inst.P / (ms / 1e3), "n": inst.n, "m": inst.m, "P": inst.P,
+           "coarse": {"n": nc, "m": mc, "P": pc}, "workspace_bytes": ws.numel()}
+    if not args.no_cpu:
+        from oracle import oracle as O
+        h = O.Hypergraph(inst.n, inst.eptr, inst.pins, inst.c, inst.w)
+        t0 = time.perf_counter()
+        O.contract(h, cl)
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": inst.P / dt, "unit": "pins/s", "cores": 1,
+                               "kind": "oracle", "sample": "the whole contraction, once"}
+    g.free()
+    return res
+
+
 def plain_leg(args, H, dev):
     """The plain workload (module docstring): returns the JSON record."""
     import torch
@@ -743,8 +782,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-rounds", type=int, default=4)
     ap.add_argument("--latency-reps", type=int, default=5)
-    ap.add_argument("--legs", default="plain,batched,served,monotone,cached,rebalance",
-                    help="comma list of plain, batched, served, monotone, cached, rebalance")
+    ap.add_argument("--legs", default="plain,batched,served,monotone,cached,rebalance,contract",
+                    help="comma list of plain, batched, served, monotone, cached, rebalance, "
+                         "contract")
     ap.add_argument("--mono-reps", type=int, default=3)
     ap.add_argument("--served-seconds", type=float, default=10.0,
                     help="length of the open-loop request trace")
@@ -787,6 +827,10 @@ def main():
         torch.cuda.empty_cache()
         print("rebalancing rounds ...", file=sys.stderr, flush=True)
         out["rebalance"] = rebalance_leg(args, H, dev)
+    if "contract" in legs:
+        torch.cuda.empty_cache()
+        print("contraction ...", file=sys.stderr, flush=True)
+        out["contract"] = contract_leg(args, H, dev)
     print(json.dumps(out), flush=True)
 
 
