@@ -5,11 +5,13 @@
 //   1. used cluster ids are flagged and renumbered by a prefix sum (the
 //      rank of the id among the used ones): map[v];
 //   2. coarse vertex weights by integer atomics;
-//   3. every pin is mapped; a stable radix sort by the mapped pin and then
-//      by the net id sorts the pins inside every net while keeping the nets
-//      where they were (net e still owns positions eptr[e] .. eptr[e+1]);
-//      the first occurrence of each pin survives (a prefix sum compacts
-//      them);
+//   3. every net's pins are mapped, sorted and deduplicated in the net's own
+//      slots of a scratch copy (tmp[eptr[e] ..]): nets of up to kSmallNet
+//      pins a tile of consecutive nets per workgroup in LDS (stable rank
+//      inside the net, first occurrences numbered by a block scan), longer
+//      nets one workgroup each (bitonic sort in LDS, or in place beyond the
+//      LDS capacity, then a compaction by block scans); the same pass gives
+//      the surviving size and the fingerprint;
 //   4. nets left with fewer than two pins are dropped;
 //   5. identical nets (parallel INRSRT): the fingerprint sum of v^2 and the
 //      size of every net are hashed to a 32-bit key; a stable sort by key
@@ -53,10 +55,10 @@ struct Ct {
   unsigned char* used;   // [n]
   long long* rank;       // [n]
   unsigned long long* cw;// [n]
-  unsigned* pkey[2];     // [P]
-  int* pval[2];          // [P]
-  long long* dpos;       // [P]: compacted position of a surviving pin
-  int* dp;               // [P]: surviving pins, net by net
+  int* tmp;              // [P]: net e's sorted distinct coarse pins at eptr[e] ..
+  int* big;              // [m]: nets longer than kSmallNet
+  int* big_count;        // [1]
+  int* tile_first;       // [tiles + 1]: first net starting in each small-net tile
   int* nsize;            // [m]: pins after deduplication
   unsigned long long* fp;// [m]
   unsigned* nkey[2];     // [m]
@@ -104,35 +106,6 @@ __global__ __launch_bounds__(kBlock) void k_ct_vweights(Ct C) {
   C.cvwgt[x] = (int)w;
 }
 
-// Sort input: key = mapped pin, value = its net (binary search in eptr).
-__global__ __launch_bounds__(kBlock) void k_ct_pin_keys(Ct C) {
-  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= C.P) return;
-  int lo = 0, hi = C.m - 1;     // net: last e with eptr[e] <= i
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (C.eptr[mid] <= i) lo = mid; else hi = mid - 1;
-  }
-  const int v = C.pins[i];
-  C.pkey[0][i] = (unsigned)((unsigned)v < (unsigned)C.n ? C.map[v] : 0);
-  C.pval[0][i] = lo;
-}
-
-// After both sorts: pins (sorted in their net) in `pin`, nets in `net`.
-struct FirstF {
-  const int* pin;
-  const unsigned* net;
-  __device__ long long operator()(long long i) const {
-    return i == 0 || net[i] != net[i - 1] || pin[i] != pin[i - 1];
-  }
-};
-
-__global__ __launch_bounds__(kBlock) void k_ct_compact(Ct C, const int* pin, const unsigned* net) {
-  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= C.P) return;
-  if (i == 0 || net[i] != net[i - 1] || pin[i] != pin[i - 1]) C.dp[C.dpos[i]] = pin[i];
-}
-
 __device__ __forceinline__ unsigned ct_hash(unsigned long long fp, int size) {
   unsigned long long h = fp * 0x9E3779B97F4A7C15ULL + (unsigned long long)size * 0xC2B2AE3D27D4EB4FULL;
   h ^= h >> 29;
@@ -141,31 +114,213 @@ __device__ __forceinline__ unsigned ct_hash(unsigned long long fp, int size) {
   return (unsigned)h;
 }
 
-// Per net: identity order for the net sort, no representative yet.
-__global__ __launch_bounds__(kBlock) void k_ct_nets(Ct C) {
-  const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (e >= C.m) return;
+constexpr int kSmallNet = 128;      // nets up to this many pins go through the tiles
+constexpr int kNetLdsCap = 8192;    // longer nets sort in LDS up to this many pins
+
+__device__ __forceinline__ void ct_net_done(const Ct& C, long long e, int size,
+                                            unsigned long long fp) {
+  C.nsize[e] = size;
+  C.fp[e] = fp;
+  C.nkey[0][e] = size >= 2 ? ct_hash(fp, size) : 0xffffffffu;
   C.nval[0][e] = (int)e;
   C.rep[e] = -1;
   C.wsum[e] = 0;
 }
 
-// Per net: surviving size, fingerprint, sort key (dropped nets: all ones).
-// The last net ends at the total of the first-occurrence scan.
-__global__ __launch_bounds__(kBlock) void k_ct_fingerprints(Ct C, const long long* dtotal) {
+constexpr int kNetTile = 1024;      // pins per small-net tile (by net start)
+
+// tile_first[t] = the first net whose first pin is at or after kNetTile * t
+// (m when there is none); every net writes the entries of the tiles between
+// its predecessor's start and its own.
+__global__ __launch_bounds__(kBlock) void k_ct_tiles(Ct C, long long tiles) {
   const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (e >= C.m) return;
-  const long long b = C.dpos[C.eptr[e]];
-  const long long t = e + 1 < C.m ? C.dpos[C.eptr[e + 1]] : *dtotal;
-  const int size = (int)(t - b);
-  unsigned long long fp = 0;
-  for (long long j = b; j < t; ++j) {
-    const unsigned long long v = (unsigned)C.dp[j];
-    fp += v * v;
+  if (e > C.m) return;
+  const long long from = e == 0 ? 0 : (C.eptr[e - 1] / kNetTile) + 1;
+  const long long to = e == C.m ? tiles : C.eptr[e] / kNetTile;
+  for (long long t = from; t <= to; ++t) C.tile_first[t] = (int)e;
+}
+
+// Small nets, a tile at a time: the nets whose first pin lies in pins
+// [kNetTile * t, kNetTile * (t + 1)) -- at most kNetTile + kSmallNet - 1 pins
+// when every one of them is small, because a long net ends the tile.  Their
+// mapped pins go to LDS; every pin learns whether it is the first of its
+// value in its net and, if so, how many distinct values of the net are
+// smaller (its place in the sorted distinct list); sizes and fingerprints
+// are LDS sums per net.  Long nets are listed for k_ct_big_nets.
+__global__ __launch_bounds__(kBlock) void k_ct_small_nets(Ct C) {
+  constexpr int kCap = kNetTile + kSmallNet;
+  __shared__ int s_val[kCap];
+  __shared__ short s_net[kCap];
+  __shared__ int s_sorted[kCap];
+  __shared__ int s_rank[kCap + 1];
+  __shared__ int s_start[kNetTile + 1];
+  __shared__ unsigned long long s_fp[kNetTile];
+  __shared__ long long s_tmp[kBlock / kWave];
+  __shared__ int s_e0, s_e1;
+  __shared__ unsigned s_big, s_big_base;
+  __shared__ int s_bigv[kNetTile / (kSmallNet + 1) + 2];   // long nets starting in a tile
+  const long long tiles = (C.P + kNetTile - 1) / kNetTile;
+  for (long long t = blockIdx.x; t < tiles; t += gridDim.x) {
+    if (threadIdx.x < 2) {
+      const int f = C.tile_first[t + threadIdx.x];
+      if (threadIdx.x == 0) s_e0 = f; else s_e1 = f;
+    }
+    if (threadIdx.x == 0) s_big = 0;
+    __syncthreads();
+    const int e0 = s_e0, nets = s_e1 - s_e0;
+    // local offsets of the small nets (long nets take no room)
+    long long carry = 0;
+    for (int j0 = 0; j0 < nets; j0 += kBlock) {
+      const int j = j0 + threadIdx.x;
+      int size = 0;
+      if (j < nets) {
+        const long long e = e0 + j;
+        size = (int)(C.eptr[e + 1] - C.eptr[e]);
+        if (size > kSmallNet) {
+          s_bigv[atomicAdd(&s_big, 1u)] = (int)e;
+          size = 0;
+        }
+      }
+      long long tot;
+      const long long ex = block_excl_scan64(size, s_tmp, &tot);
+      if (j < nets) {
+        s_start[j] = (int)(carry + ex);
+        s_fp[j] = 0;
+      }
+      carry += tot;
+    }
+    const int total = (int)carry;
+    if (threadIdx.x == 0) s_start[nets] = total;
+    __syncthreads();
+    // mapped pins into LDS: every thread's positions first, then all their
+    // pin loads, then all their map loads (independent loads in flight)
+    constexpr int kPer = (kCap + kBlock - 1) / kBlock;
+    long long src[kPer];
+    int pin[kPer];
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+      const int q = threadIdx.x + r * kBlock;
+      src[r] = -1;
+      if (q < total) {
+        int lo = 0, hi = nets - 1;     // net: the last j with s_start[j] <= q
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_start[mid] <= q) lo = mid; else hi = mid - 1;
+        }
+        src[r] = C.eptr[e0 + lo] + (q - s_start[lo]);
+        s_net[q] = (short)lo;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) pin[r] = src[r] >= 0 ? C.pins[src[r]] : 0;
+#pragma unroll
+    for (int r = 0; r < kPer; ++r)
+      if (src[r] >= 0) s_val[threadIdx.x + r * kBlock] = C.map[pin[r]];
+    __syncthreads();
+    // stable rank inside the net -> sorted copy (a permutation of the net)
+    for (int q = threadIdx.x; q < total; q += kBlock) {
+      const int j = s_net[q], x = s_val[q];
+      const int b = s_start[j], t2 = s_start[j + 1];
+      int rank = 0;
+#pragma unroll 4
+      for (int r = b; r < t2; ++r) {
+        const int v = s_val[r];
+        rank += v < x || (v == x && r < q);
+      }
+      s_sorted[b + rank] = x;
+    }
+    __syncthreads();
+    // first occurrences in sorted order, numbered by a scan over the tile
+    long long run = 0;
+    int firsts[kPer];
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+      const int q = threadIdx.x + r * kBlock;
+      int f = 0;
+      if (q < total) {
+        const int j = s_net[q];
+        f = q == s_start[j] || s_sorted[q - 1] != s_sorted[q];
+      }
+      firsts[r] = f;
+      long long tot;
+      const long long ex = block_excl_scan64(f, s_tmp, &tot);
+      if (q < total) s_rank[q] = (int)(run + ex);
+      run += tot;
+    }
+    if (threadIdx.x == 0) s_rank[total] = (int)run;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+      const int q = threadIdx.x + r * kBlock;
+      if (q >= total || !firsts[r]) continue;
+      const int j = s_net[q], x = s_sorted[q];
+      C.tmp[C.eptr[e0 + j] + (s_rank[q] - s_rank[s_start[j]])] = x;
+      atomicAdd(&s_fp[j], (unsigned long long)(unsigned)x * (unsigned)x);
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < nets; j += kBlock)
+      if (s_start[j + 1] > s_start[j])
+        ct_net_done(C, e0 + j, s_rank[s_start[j + 1]] - s_rank[s_start[j]], s_fp[j]);
+    if (threadIdx.x == 0 && s_big) s_big_base = atomicAdd((unsigned*)C.big_count, s_big);
+    __syncthreads();
+    for (int j = threadIdx.x; j < (int)s_big; j += kBlock) C.big[s_big_base + j] = s_bigv[j];
+    __syncthreads();
   }
-  C.nsize[e] = size;
-  C.fp[e] = fp;
-  C.nkey[0][e] = size >= 2 ? ct_hash(fp, size) : 0xffffffffu;
+}
+
+// One workgroup per listed net (workgroups stride over the list): map,
+// bitonic sort (LDS when it fits), then keep first occurrences in order by
+// block scans over chunks of the sorted row.
+__global__ __launch_bounds__(kBlock) void k_ct_big_nets(Ct C) {
+  __shared__ int s_row[kNetLdsCap];
+  __shared__ long long s_tmp[kBlock / kWave];
+  __shared__ int s_prev;
+  const int count = *C.big_count;
+  for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
+    const int e = C.big[idx];
+    const long long b = C.eptr[e];
+    const int len = (int)(C.eptr[e + 1] - b);
+    int pow2 = 1;
+    while (pow2 < len) pow2 <<= 1;
+    int* row = C.tmp + b;
+    if (pow2 <= kNetLdsCap) {
+      for (int i = threadIdx.x; i < len; i += kBlock) s_row[i] = C.map[C.pins[b + i]];
+      __syncthreads();
+      bitonic_sort_block(len, pow2, [&](int i) { return s_row[i]; },
+                         [&](int i, int x) { s_row[i] = x; });
+      for (int i = threadIdx.x; i < len; i += kBlock) row[i] = s_row[i];
+    } else {
+      for (int i = threadIdx.x; i < len; i += kBlock) row[i] = C.map[C.pins[b + i]];
+      __syncthreads();
+      bitonic_sort_block(len, pow2, [&](int i) { return row[i]; },
+                         [&](int i, int x) { row[i] = x; });
+    }
+    __syncthreads();
+    // compaction in place: writes never pass the chunk being read
+    long long kept = 0;
+    unsigned long long fp = 0;
+    if (threadIdx.x == 0) s_prev = -1;
+    __syncthreads();
+    for (int c0 = 0; c0 < len; c0 += kBlock) {
+      const int i = c0 + threadIdx.x;
+      const int x = i < len ? row[i] : 0;
+      const int before = i == 0 ? -1 : (threadIdx.x == 0 ? s_prev : row[i - 1]);
+      const bool first = i < len && (i == 0 || x != before);
+      long long tot;
+      const long long at = kept + block_excl_scan64(first ? 1 : 0, s_tmp, &tot);
+      if (threadIdx.x == kBlock - 1 || i == len - 1) s_prev = x;
+      __syncthreads();
+      if (first) {
+        row[at] = x;
+        fp += (unsigned long long)(unsigned)x * (unsigned)x;
+      }
+      kept += tot;
+      __syncthreads();
+    }
+    const unsigned long long f = (unsigned long long)block_sum64((long long)fp, s_tmp);
+    if (threadIdx.x == 0) ct_net_done(C, e, (int)kept, f);
+    __syncthreads();
+  }
 }
 
 struct HeadF {
@@ -181,7 +336,7 @@ __global__ __launch_bounds__(kBlock) void k_ct_heads(Ct C, const unsigned* key) 
 
 __device__ bool ct_same(const Ct& C, long long be, long long bf, int size) {
   for (int x = 0; x < size; ++x)
-    if (C.dp[be + x] != C.dp[bf + x]) return false;
+    if (C.tmp[be + x] != C.tmp[bf + x]) return false;
   return true;
 }
 
@@ -196,12 +351,12 @@ __global__ __launch_bounds__(kBlock) void k_ct_reps(Ct C, const unsigned* key, c
   const bool head = j == 0 || key[j] != key[j - 1];
   const long long h = C.heads[C.hscan[j] + (head ? 1 : 0) - 1];
   const unsigned long long fe = C.fp[e];
-  const long long be = C.dpos[C.eptr[e]];
+  const long long be = C.eptr[e];
   int r = e;
   for (long long i = h; i < j; ++i) {
     const int f = val[i];
     if (C.nsize[f] != size || C.fp[f] != fe) continue;
-    if (ct_same(C, be, C.dpos[C.eptr[f]], size)) {
+    if (ct_same(C, be, C.eptr[f], size)) {
       r = f;
       break;
     }
@@ -221,15 +376,21 @@ struct KeptSizeF {
   __device__ long long operator()(long long e) const { return rep[e] == e ? nsize[e] : 0; }
 };
 
+// kEmitLanes lanes per net copy a kept net's pins side by side.
+constexpr int kEmitLanes = 8;
+
 __global__ __launch_bounds__(kBlock) void k_ct_emit(Ct C) {
-  const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const long long e = ((long long)blockIdx.x * kBlock + threadIdx.x) / kEmitLanes;
+  const int gl = threadIdx.x % kEmitLanes;
   if (e >= C.m || C.rep[e] != e) return;
   const long long id = C.nid[e], pos = C.npos[e];
-  const long long b = C.dpos[C.eptr[e]];
+  const long long b = C.eptr[e];
   const int size = C.nsize[e];
-  C.ceptr[id] = pos;
-  C.cewgt[id] = (int)C.wsum[e];
-  for (int x = 0; x < size; ++x) C.cpins[pos + x] = C.dp[b + x];
+  if (gl == 0) {
+    C.ceptr[id] = pos;
+    C.cewgt[id] = (int)C.wsum[e];
+  }
+  for (int x = gl; x < size; x += kEmitLanes) C.cpins[pos + x] = C.tmp[b + x];
 }
 
 __global__ void k_ct_close(Ct C) {
@@ -239,8 +400,8 @@ __global__ void k_ct_close(Ct C) {
 }  // namespace
 
 struct ContractLayout {
-  size_t used, rank, cw, pkey[2], pval[2], dpos, dp, nsize, fp, nkey[2], nval[2], hscan, heads,
-      rep, wsum, nid, npos, csum, coff, phist, pdtot, nhist, ndtot, dtotal, total;
+  size_t used, rank, cw, tmp, big, big_count, tile_first, nsize, fp, nkey[2], nval[2], hscan, heads, rep, wsum,
+      nid, npos, csum, coff, nhist, ndtot, total;
 };
 
 static ContractLayout contract_layout(long long n, long long m, long long P) {
@@ -254,14 +415,14 @@ static ContractLayout contract_layout(long long n, long long m, long long P) {
   L.used = take((size_t)n);
   L.rank = take(8 * (size_t)n);
   L.cw = take(8 * (size_t)n);
+  L.tmp = take(4 * (size_t)P);
+  L.big = take(4 * (size_t)m);
+  L.big_count = take(4);
+  L.tile_first = take(4 * (size_t)((P + kNetTile - 1) / kNetTile + 1));
   for (int i = 0; i < 2; ++i) {
-    L.pkey[i] = take(4 * (size_t)P);
-    L.pval[i] = take(4 * (size_t)P);
     L.nkey[i] = take(4 * (size_t)m);
     L.nval[i] = take(4 * (size_t)m);
   }
-  L.dpos = take(8 * (size_t)P);
-  L.dp = take(4 * (size_t)P);
   L.nsize = take(4 * (size_t)m);
   L.fp = take(8 * (size_t)m);
   L.hscan = take(8 * (size_t)m);
@@ -270,15 +431,11 @@ static ContractLayout contract_layout(long long n, long long m, long long P) {
   L.wsum = take(4 * (size_t)m);
   L.nid = take(8 * (size_t)m);
   L.npos = take(8 * (size_t)m);
-  long long most = n > m ? n : m;
-  if (P > most) most = P;
+  const long long most = n > m ? n : m;
   L.csum = take(8 * (size_t)scan_chunks(most));
   L.coff = take(8 * (size_t)scan_chunks(most));
-  L.phist = take(4 * (size_t)kDigits * sort_tiles(P));
-  L.pdtot = take(4 * (size_t)kDigits);
   L.nhist = take(4 * (size_t)kDigits * sort_tiles(m));
   L.ndtot = take(4 * (size_t)kDigits);
-  L.dtotal = take(8);
   L.total = off;
   return L;
 }
@@ -290,12 +447,6 @@ size_t contract_workspace_size(long long n, long long m, long long P) {
 static unsigned blocks_of(long long items) {
   long long b = (items + kBlock - 1) / kBlock;
   return (unsigned)(b < 1 ? 1 : b);
-}
-
-static int bits_for(long long max_value) {
-  int b = 1;
-  while (b < 32 && (1ll << b) <= max_value) ++b;
-  return b;
 }
 
 static hipError_t launch_contract(hg_graph_s* g, const int* cluster, int* map, int* cvwgt,
@@ -322,13 +473,13 @@ static hipError_t launch_contract(hg_graph_s* g, const int* cluster, int* map, i
   C.rank = (long long*)(ws + L.rank);
   C.cw = (unsigned long long*)(ws + L.cw);
   for (int i = 0; i < 2; ++i) {
-    C.pkey[i] = (unsigned*)(ws + L.pkey[i]);
-    C.pval[i] = (int*)(ws + L.pval[i]);
     C.nkey[i] = (unsigned*)(ws + L.nkey[i]);
     C.nval[i] = (int*)(ws + L.nval[i]);
   }
-  C.dpos = (long long*)(ws + L.dpos);
-  C.dp = (int*)(ws + L.dp);
+  C.tmp = (int*)(ws + L.tmp);
+  C.big = (int*)(ws + L.big);
+  C.big_count = (int*)(ws + L.big_count);
+  C.tile_first = (int*)(ws + L.tile_first);
   C.nsize = (int*)(ws + L.nsize);
   C.fp = (unsigned long long*)(ws + L.fp);
   C.hscan = (long long*)(ws + L.hscan);
@@ -341,8 +492,7 @@ static hipError_t launch_contract(hg_graph_s* g, const int* cluster, int* map, i
   ScanBufs B;
   B.csum = (long long*)(ws + L.csum);
   B.coff = (long long*)(ws + L.coff);
-  long long* dtotal = (long long*)(ws + L.dtotal);
-  const long long n = g->n, m = g->m, P = g->P;
+  const long long n = g->n, m = g->m;
 
   // 1-2. renumbering, map, coarse weights
   hipError_t e = fill_u8(C.used, 0, n, s);
@@ -353,43 +503,16 @@ static hipError_t launch_contract(hg_graph_s* g, const int* cluster, int* map, i
   hipLaunchKernelGGL(k_ct_map, dim3(blocks_of(n)), dim3(kBlock), 0, s, C);
   hipLaunchKernelGGL(k_ct_vweights, dim3(blocks_of(n)), dim3(kBlock), 0, s, C);
 
-  // 3. mapped pins sorted inside their nets: by pin, then (stably) by net
-  hipLaunchKernelGGL(k_ct_pin_keys, dim3(blocks_of(P)), dim3(kBlock), 0, s, C);
-  int cur = 0;
-  SortPass SP;
-  SP.hist = (unsigned*)(ws + L.phist);
-  SP.dtot = (unsigned*)(ws + L.pdtot);
-  SP.n = (int)P;
-  SP.tiles = sort_tiles(P);
-  const int pin_bits = bits_for(n - 1), net_bits = bits_for(m - 1);
-  for (int shift = 0; shift < pin_bits; shift += 8) {
-    SP.key_in = C.pkey[cur];
-    SP.val_in = C.pval[cur];
-    SP.key_out = C.pkey[cur ^ 1];
-    SP.val_out = C.pval[cur ^ 1];
-    SP.shift = shift;
-    sort_pass(SP, s);
-    cur ^= 1;
-  }
-  // the same buffers with the roles swapped: key = net, value = pin
-  for (int shift = 0; shift < net_bits; shift += 8) {
-    SP.key_in = (const unsigned*)C.pval[cur];
-    SP.val_in = (const int*)C.pkey[cur];
-    SP.key_out = (unsigned*)C.pval[cur ^ 1];
-    SP.val_out = (int*)C.pkey[cur ^ 1];
-    SP.shift = shift;
-    sort_pass(SP, s);
-    cur ^= 1;
-  }
-  const unsigned* pnet = (const unsigned*)C.pval[cur];
-  const int* ppin = (const int*)C.pkey[cur];
-  exclusive_scan(FirstF{ppin, pnet}, P, C.dpos, dtotal, B, s);
-  hipLaunchKernelGGL(k_ct_compact, dim3(blocks_of(P)), dim3(kBlock), 0, s, C, ppin, pnet);
+  // 3-4. per net: mapped, sorted, deduplicated pins, size, fingerprint
+  e = fill_i32(C.big_count, 0, 1, s);
+  if (e != hipSuccess) return e;
+  const long long tiles = (g->P + kNetTile - 1) / kNetTile;
+  hipLaunchKernelGGL(k_ct_tiles, dim3(blocks_of(m + 1)), dim3(kBlock), 0, s, C, tiles);
+  long long sg = tiles < 8192 ? tiles : 8192;
+  hipLaunchKernelGGL(k_ct_small_nets, dim3((unsigned)sg), dim3(kBlock), 0, s, C);
+  hipLaunchKernelGGL(k_ct_big_nets, dim3(1024), dim3(kBlock), 0, s, C);
 
-  // 4-5. sizes, fingerprints, identical nets
-  hipLaunchKernelGGL(k_ct_nets, dim3(blocks_of(m)), dim3(kBlock), 0, s, C);
-  hipLaunchKernelGGL(k_ct_fingerprints, dim3(blocks_of(m)), dim3(kBlock), 0, s, C,
-                     (const long long*)dtotal);
+  // 5. identical nets
   int ncur = 0;
   SortPass SN;
   SN.hist = (unsigned*)(ws + L.nhist);
@@ -413,7 +536,7 @@ static hipError_t launch_contract(hg_graph_s* g, const int* cluster, int* map, i
   // 6. coarse net CSR in representative order
   exclusive_scan(KeptF{C.rep}, m, C.nid, &sizes[1], B, s);
   exclusive_scan(KeptSizeF{C.rep, C.nsize}, m, C.npos, &sizes[2], B, s);
-  hipLaunchKernelGGL(k_ct_emit, dim3(blocks_of(m)), dim3(kBlock), 0, s, C);
+  hipLaunchKernelGGL(k_ct_emit, dim3(blocks_of(m * kEmitLanes)), dim3(kBlock), 0, s, C);
   hipLaunchKernelGGL(k_ct_close, dim3(1), dim3(kWave), 0, s, C);
   return hipGetLastError();
 }

@@ -9,6 +9,7 @@
 // order in which the scatter's atomics happened.
 #include "hg_device.h"
 #include "hg_internal.h"
+#include "hg_sort.h"
 
 namespace hg {
 
@@ -308,33 +309,6 @@ __global__ __launch_bounds__(kBlock) void k_sort_small_rows(int n, const long lo
 // (indices past the row end act as +infinity and never move), in LDS when the
 // padded row fits, else in place in global memory.
 constexpr int kLdsSortCap = 8192;
-
-template <typename Get, typename Put>
-__device__ void bitonic_sort_block(int len, int pow2, Get get, Put put) {
-  for (int size = 2; size <= pow2; size <<= 1) {
-    // first step of each merge: compare i with its mirror in the size-block
-    for (int i = threadIdx.x; i < pow2 / 2; i += blockDim.x) {
-      int blk = i / (size / 2), off = i % (size / 2);
-      int a = blk * size + off, b = blk * size + size - 1 - off;
-      if (b < len) {
-        int x = get(a), y = get(b);
-        if (x > y) { put(a, y); put(b, x); }
-      }
-    }
-    __syncthreads();
-    for (int stride = size / 4; stride > 0; stride >>= 1) {
-      for (int i = threadIdx.x; i < pow2 / 2; i += blockDim.x) {
-        int blk = i / stride, off = i % stride;
-        int a = blk * 2 * stride + off, b = a + stride;
-        if (b < len) {
-          int x = get(a), y = get(b);
-          if (x > y) { put(a, y); put(b, x); }
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
 
 __global__ void k_sort_big_rows(const long long* vptr, int* vnets, const int* ewgt,
                                 const int* big_list, int* heavy_list, LoadInfo* info) {

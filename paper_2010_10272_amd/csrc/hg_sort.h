@@ -119,5 +119,35 @@ inline void sort_pass(const SortPass& P, hipStream_t s) {
 
 inline int sort_tiles(long long n) { return (int)((n + kSortTile - 1) / kSortTile); }
 
+// Ascending bitonic sort of len int32 items by one workgroup (indices past
+// the end act as +infinity and never move); get/put address LDS or global
+// memory.  Every comparator stage ends with a barrier.
+template <typename Get, typename Put>
+__device__ void bitonic_sort_block(int len, int pow2, Get get, Put put) {
+  for (int size = 2; size <= pow2; size <<= 1) {
+    // first step of each merge: compare i with its mirror in the size-block
+    for (int i = threadIdx.x; i < pow2 / 2; i += blockDim.x) {
+      int blk = i / (size / 2), off = i % (size / 2);
+      int a = blk * size + off, b = blk * size + size - 1 - off;
+      if (b < len) {
+        int x = get(a), y = get(b);
+        if (x > y) { put(a, y); put(b, x); }
+      }
+    }
+    __syncthreads();
+    for (int stride = size / 4; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < pow2 / 2; i += blockDim.x) {
+        int blk = i / stride, off = i % stride;
+        int a = blk * 2 * stride + off, b = a + stride;
+        if (b < len) {
+          int x = get(a), y = get(b);
+          if (x > y) { put(a, y); put(b, x); }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 }  // namespace
 }  // namespace hg

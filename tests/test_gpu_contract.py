@@ -40,6 +40,22 @@ def _with_duplicates(inst, seed):
                           inst.c, w, inst.part, inst.k, inst.eps, inst.rounds)
 
 
+def _with_huge_nets(seed):
+    """A power-law hypergraph plus nets of 100, 5,000, 9,000 and 20,000 pins
+    (longer than one thread's sort, and than the LDS sort), one of them twice."""
+    rng = np.random.default_rng(seed)
+    base = synth.random_power_law(seed, 30000, 20000, 4, hi=32, unit=False)
+    nets = [base.pins[base.eptr[e]:base.eptr[e + 1]] for e in range(base.m)]
+    for size in (100, 5000, 9000, 20000, 9000):
+        nets.append(np.sort(rng.choice(base.n, size=size, replace=False)).astype(np.int32))
+    nets.append(nets[-2].copy())
+    w = np.concatenate([base.w, rng.integers(1, 50, 6)]).astype(np.int32)
+    eptr = np.zeros(len(nets) + 1, np.int64)
+    eptr[1:] = np.cumsum([len(x) for x in nets])
+    return synth.Instance("huge", base.n, eptr, np.concatenate(nets).astype(np.int32), base.c, w,
+                          base.part, 4, 0.03, 3)
+
+
 def _clusterings(inst):
     rng = np.random.default_rng(5)
     n = inst.n
@@ -57,6 +73,7 @@ def _instances():
         synth.random_power_law(502, 7000, 6600, 7, hi=16, unit=False), 1)
     yield "band", lambda: synth.sparse_matrix(16, seed=503, rows=30000, cols=30000, band=1000)
     yield "hub-w", lambda: _hub_instance(8, 6000, 5000, 16, 400, True)
+    yield "huge-nets", lambda: _with_huge_nets(506)
 
 
 INSTANCES = list(_instances())
