@@ -18,11 +18,13 @@ namespace hg {
 // Row u of `gains` (k int64) and benefit[u] are written.
 // With `cache` set, the sweeps fill a gain cache instead (subsection "Gain
 // Caching"): b(u), w(I(u)) and the row p_i(u) = w(I(u)) - conn_i (0 for the
-// own block), laid out as cache_pbase / cache_stride say.
+// own block), laid out as cache_pbase / cache_stride say.  With only_over
+// set, only vertices of blocks heavier than L_max are filled (the rows the
+// rebalancer reads).
 template <int WK, int VIEW>
 __global__ __launch_bounds__(kBlock) void k_gains_light(Launch L, long long* __restrict__ gains,
                                                         long long* __restrict__ benefit,
-                                                        int* __restrict__ cache) {
+                                                        int* __restrict__ cache, int only_over) {
   WorkItem fb;
   fb.inst = 0;
   fb.first = (int)xcd_remap(blockIdx.x, gridDim.x);
@@ -42,6 +44,7 @@ __global__ __launch_bounds__(kBlock) void k_gains_light(Launch L, long long* __r
     if (benefit) benefit[u] = 0;
     return;
   }
+  if (only_over && D.block_w[a] <= D.lmax) return;
   const long long b0 = D.vptr[u], b1 = D.vptr[u + 1];
   if (b1 - b0 > kLightLimit) return;                 // heavy: other kernel
   BitCounters<WK> C;
@@ -116,7 +119,7 @@ __global__ __launch_bounds__(kBlock) void k_gains_light(Launch L, long long* __r
 // Unit: 4 consecutive heavy-list entries (one per wavefront).
 __global__ __launch_bounds__(kBlock) void k_gains_heavy(Launch L, long long* __restrict__ gains,
                                                         long long* __restrict__ benefit,
-                                                        int* __restrict__ cache) {
+                                                        int* __restrict__ cache, int only_over) {
   __shared__ int s_conn[kBlock / kWave][HG_MAX_K];
   WorkItem fb;
   fb.inst = 0;
@@ -132,6 +135,7 @@ __global__ __launch_bounds__(kBlock) void k_gains_heavy(Launch L, long long* __r
   const int u = D.heavy_list[idx];
   const int a = D.part[u];
   if ((unsigned)a >= (unsigned)k) return;           // flagged and zeroed by the light kernel
+  if (only_over && D.block_w[a] <= D.lmax) return;
   int* conn = s_conn[wv];
   for (int i = lane; i < k; i += kWave) conn[i] = 0;
   wave_lds_sync();
@@ -172,7 +176,7 @@ __global__ __launch_bounds__(kBlock) void k_gains_heavy(Launch L, long long* __r
 }
 
 GainsKernel gains_kernel(int k, int view) {
-  typedef void (*K)(Launch, long long*, long long*, int*);
+  typedef void (*K)(Launch, long long*, long long*, int*, int);
   K kern;
   switch (view) {
     case kView16: kern = k_gains_light<1, kView16>; break;
@@ -190,15 +194,16 @@ GainsKernel gains_kernel(int k, int view) {
 }
 
 hipError_t launch_gains(hg_graph_s* g, const InstDesc& d, long long* gains, long long* benefit,
-                        hipStream_t s, int* cache) {
-  typedef void (*K)(Launch, long long*, long long*, int*);
+                        hipStream_t s, int* cache, int only_over) {
+  typedef void (*K)(Launch, long long*, long long*, int*, int);
   const Launch L = single_launch(d);
   unsigned grid = (unsigned)(((long long)d.n + kBlock - 1) / kBlock);
   hipLaunchKernelGGL((K)(void*)gains_kernel(d.k, d.view), dim3(grid), dim3(kBlock), 0, s, L,
-                     gains, benefit, cache);
+                     gains, benefit, cache, only_over);
   if (d.heavy_count > 0) {
     unsigned hg = (unsigned)((d.heavy_count + (kBlock / kWave) - 1) / (kBlock / kWave));
-    hipLaunchKernelGGL(k_gains_heavy, dim3(hg), dim3(kBlock), 0, s, L, gains, benefit, cache);
+    hipLaunchKernelGGL(k_gains_heavy, dim3(hg), dim3(kBlock), 0, s, L, gains, benefit, cache,
+                       only_over);
   }
   (void)g;
   return hipGetLastError();

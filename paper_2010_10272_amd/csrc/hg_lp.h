@@ -70,9 +70,10 @@ hipError_t launch_cached_round(const RoundPlan& plan, int round, hipStream_t s,
 hipError_t launch_counts(const CountPlan& plan, bool want_km1, bool mark_eligible, hipStream_t s);
 void single_count_plan(const InstDesc& d, CountPlan& plan);
 
-// All gains (or, with `cache`, a gain cache: b, w(I), p rows; see hgref.h).
+// All gains (or, with `cache`, a gain cache: b, w(I), p rows; see hgref.h;
+// with only_over, only the rows of vertices in blocks heavier than d.lmax).
 hipError_t launch_gains(hg_graph_s* g, const InstDesc& d, long long* gains, long long* benefit,
-                        hipStream_t s, int* cache = nullptr);
+                        hipStream_t s, int* cache = nullptr, int only_over = 0);
 hipError_t launch_km1(hg_graph_s* g, int k, const unsigned* netstate, long long* km1,
                       hipStream_t s);
 

@@ -973,7 +973,7 @@ static hipError_t launch_rebalance_round(hg_graph_s* g, InstDesc d, char* ws, hi
   unsigned* key[2] = {(unsigned*)(ws + L.key[0]), (unsigned*)(ws + L.key[1])};
   int* val[2] = {(int*)(ws + L.val[0]), (int*)(ws + L.val[1])};
   hipLaunchKernelGGL(k_rb_begin, dim3(1), dim3(kBlock), 0, s, d, R);
-  hipError_t e = launch_gains(g, d, nullptr, nullptr, s, (int*)(ws + L.cache));
+  hipError_t e = launch_gains(g, d, nullptr, nullptr, s, (int*)(ws + L.cache), 1);
   if (e != hipSuccess) return e;
   // candidates: lanes per vertex as the penalty row needs
   const int q = cache_stride(k) / 4;
