@@ -48,6 +48,20 @@ def select_bytes(st, n, k):
             16.0 * st["candidates"])
 
 
+def roofline_of(name, alg_bytes, ms):
+    """A roofline record: algorithmic bytes of one call over its time."""
+    achieved = alg_bytes / (ms / 1e3) / 1e9
+    return {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "alg_bytes": alg_bytes, "ms": ms}
+
+
+def timed_oracle(fn):
+    """Seconds one oracle call takes on this host (one thread)."""
+    t0 = time.perf_counter()
+    out = fn()
+    return time.perf_counter() - t0, out
+
+
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "plain_sparse_matrix_traffic.md")
 
 
@@ -463,8 +477,25 @@ def monotone_leg(args, H, dev):
             if rep:
                 xs.append(a.elapsed_time(b))
         deg = (g.vptr[1:] - g.vptr[:-1])[mu.long()].sum().item()
-        res["move_gains"] = {"moves": t, "incidences": int(deg), "ms": percentile(xs, 50),
-                             "incidences_per_s": deg / (percentile(xs, 50) / 1e3)}
+        mg_ms = percentile(xs, 50)
+        res["move_gains"] = {"moves": t, "incidences": int(deg), "ms": mg_ms,
+                             "incidences_per_s": deg / (mg_ms / 1e3),
+                             # per incidence: net id read by the three passes (12 B),
+                             # the (e, a) and (e, b) cells cleared (24 B) and updated
+                             # (24 B), then Phi and the cells read (36 B) plus w(e) (4 B);
+                             # per move: the move (8 B), offsets (16 B), part (4 B), gain
+                             "roofline": roofline_of("k_seq_init + k_seq_collect + k_seq_gains",
+                                                     100.0 * deg + 36.0 * t, mg_ms)}
+        if not args.no_cpu:
+            from oracle import oracle as O
+            h = O.Hypergraph(inst.n, inst.eptr, inst.pins, inst.c, inst.w)
+            h.incidence()
+            dt, want = timed_oracle(lambda: O.move_gains(h, k, ik.part, mu.cpu().numpy(),
+                                                         mt.cpu().numpy()))
+            assert np.array_equal(want, gains.cpu().numpy()), "move gains differ from the oracle"
+            res["move_gains"]["cpu_baseline"] = {
+                "value": deg / dt, "unit": "incidences/s", "cores": 1, "kind": "oracle",
+                "sample": "the same %d-move sequence, once" % t}
         out["k%d" % k] = res
         g.free()
     return out
@@ -518,6 +549,23 @@ def cached_leg(args, H, dev):
         assert torch.equal(finals["plain"][0], finals["cached"][0]), "cached rounds differ"
         assert torch.equal(finals["plain"][1], finals["cached"][1]), "cached records differ"
         res["cache_bytes"] = cache.numel() * 4
+        # the cached select per launch: eligible and moved flags (2n), candidate
+        # words (8n), and per eligible vertex part, b, w(I) and its padded row
+        recs = H.stats_to_dicts(finals["cached"][1])
+        ks = (k + 3) // 4 * 4
+        sel_bytes = sum(10.0 * inst.n + r["eligible"] * (12.0 + 4.0 * ks) + 16.0 * r["candidates"]
+                        for r in recs) / len(recs)
+        res["roofline"] = roofline_of("k_select_cached", sel_bytes,
+                                      res["cached"]["phase_ms_per_round"]["select"])
+        if not args.no_cpu:
+            from oracle import oracle as O
+            h = O.Hypergraph(inst.n, inst.eptr, inst.pins, inst.c, inst.w)
+            L = H.hg_max_block_weight(g, k, inst.eps)
+            dt, (p1, _, _) = timed_oracle(lambda: O.refine(h, k, L, 1, ik.part))
+            res["cpu_baseline"] = {"value": inst.P / dt, "unit": "pins/s", "cores": 1,
+                                   "kind": "oracle",
+                                   "sample": "one label-propagation round (the cached round's "
+                                             "result), k = %d" % k}
         out["k%d" % k] = res
         g.free()
     return out
@@ -561,7 +609,31 @@ def rebalance_leg(args, H, dev):
                 xs.append(a.elapsed_time(b))
         recs = H.stats_to_dicts(stats)
         ms = percentile(xs, 50)
-        out["k%d" % k] = {
+        # per round, the terms every rebalancing round must move: the cache
+        # rows of the considered vertices (filled from their incidences, then
+        # read: (12 + w_Lambda) B per incidence, 2 x (8 + 4 ks) B per vertex),
+        # flags / keys / candidate words of all vertices (2n + 8n + 8n), the
+        # applied moves (16 B each, 20 B per incidence) and the finalize of the
+        # touched nets (8 B each; their pins are left out, the records do not
+        # count them, so this is a lower bound)
+        w_l = 4 * ((k + 31) // 32)
+        ks = (k + 3) // 4 * 4
+        rb_bytes = sum((12.0 + w_l) * r["active_pins"] + 2 * (8.0 + 4 * ks) * r["eligible"] +
+                       18.0 * inst.n + 16.0 * r["approved"] + 20.0 * r["moved_pins"] +
+                       8.0 * r["touched_nets"] for r in recs)
+        base = None
+        if not args.no_cpu:
+            from oracle import oracle as O
+            h = O.Hypergraph(inst.n, inst.eptr, inst.pins, inst.c, inst.w)
+            h.incidence()
+            dt, (p1, _, _, s1) = timed_oracle(lambda: O.rebalance_round(
+                h, k, L, part0, np.zeros(inst.n, np.uint8)))
+            assert s1["approved"] == recs[0]["approved"], "rebalancing differs from the oracle"
+            base = {"value": inst.P / dt, "unit": "pins/s", "cores": 1, "kind": "oracle",
+                    "sample": "the first rebalancing round, k = %d" % k}
+        out["k%d" % k] = {"roofline": roofline_of("rebalancing round (all kernels)", rb_bytes,
+                                                  ms),
+                          "cpu_baseline": base,
             "rounds": RB_ROUNDS, "ms": ms, "round_ms": ms / RB_ROUNDS,
             "l_max": L, "max_block_weight_before": w0,
             "max_block_weight_after": [r["max_block_weight"] for r in recs],
@@ -597,8 +669,13 @@ def contract_leg(args, H, dev):
     H.hg_sync_status(g)
     nc, mc, pc = out.read_sizes()
     ms = percentile(xs, 50)
+    # what any contraction moves: cluster ids and map (4n + 4n), net offsets
+    # (8m), pins read and mapped (4P + 4P), the coarse weights, offsets, pins
+    # and net weights written (4n' + 8m' + 4P' + 4m')
+    alg = 8.0 * inst.n + 8.0 * inst.m + 8.0 * inst.P + 4.0 * nc + 12.0 * mc + 4.0 * pc
     res = {"ms": ms, "pins_per_s": inst.P / (ms / 1e3), "n": inst.n, "m": inst.m, "P": inst.P,
-           "coarse": {"n": nc, "m": mc, "P": pc}, "workspace_bytes": ws.numel()}
+           "coarse": {"n": nc, "m": mc, "P": pc}, "workspace_bytes": ws.numel(),
+           "roofline": roofline_of("contraction (all kernels)", alg, ms)}
     if not args.no_cpu:
         from oracle import oracle as O
         h = O.Hypergraph(inst.n, inst.eptr, inst.pins, inst.c, inst.w)

@@ -399,8 +399,9 @@ hg_status hg_batch_get_schedule(hg_batch b, hg_schedule* sched);
  * at most once in a sequence (as in one FM round). */
 
 /* Bytes of the workspace of the calls below for a graph with n vertices and
- * m nets at k blocks: three int32 per (net, block) cell, sort and scan
- * buffers.  0 for unsupported arguments.  Any contents are fine on entry. */
+ * m nets at k blocks: 16 bytes per (net, block) cell (three int32 and a
+ * pad), sort and scan buffers.  0 for unsupported arguments.  Any contents
+ * are fine on entry. */
 size_t hg_moves_workspace_size(int32_t n, int32_t m, int32_t k);
 
 /* gains[j] (int64, device) = km1 before move j minus km1 after it, when the

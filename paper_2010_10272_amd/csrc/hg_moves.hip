@@ -9,7 +9,8 @@
 //   out_max(e, i)  the largest J moving a pin of e out of i   (0 if none)
 //   in_min(e, i)   the smallest J moving a pin of e into i     (INT_MAX if none)
 //   out_cnt(e, i)  how many moves take a pin of e out of i
-// with integer atomics (max, min, add: order-independent), and then, per move
+// with integer atomics (max, min, add: order-independent) on one 16-byte cell
+// per (net, block), so a move touches one cache line per cell, and then, per move
 // and incident net e, Psi(e, i) = Phi(e, i) - out_cnt(e, i) and the Lemma:
 //   Phi(e, a) = 1 just before move J  iff  Psi(e,a) = 0, out_max(e,a) = J,
 //                                          in_min(e,a) > J
@@ -43,7 +44,7 @@ constexpr int kPrefixChunk = kTile;         // moves per prefix-scan workgroup
 
 // Layout of the caller's move-sequence workspace.
 struct MovesLayout {
-  size_t out_max, in_min, out_cnt, seen, appr, key[2], val[2], hist, dtot, gains, csum, coff,
+  size_t cell, seen, appr, key[2], val[2], hist, dtot, gains, csum, coff,
       cbest_v, cbest_i, best, tdev, total;
   int sort_tiles, chunks;
 };
@@ -61,9 +62,7 @@ MovesLayout moves_layout(long long n, long long m, int k) {
   const size_t cells = (size_t)m * (size_t)k;
   L.sort_tiles = (int)((n + kSortTile - 1) / kSortTile);
   L.chunks = (int)((n + kPrefixChunk - 1) / kPrefixChunk);
-  L.out_max = take(sizeof(int) * cells);
-  L.in_min = take(sizeof(int) * cells);
-  L.out_cnt = take(sizeof(int) * cells);
+  L.cell = take(sizeof(int4) * cells);
   L.seen = take(sizeof(int) * (size_t)n);
   L.appr = take((size_t)n);
   for (int i = 0; i < 2; ++i) {
@@ -100,9 +99,7 @@ struct Seq {
   const int* ewgt;
   const int* vwgt;
   int n, k;
-  int* out_max;
-  int* in_min;
-  int* out_cnt;
+  int4* cell;                    // per (net, block): out_max, in_min, out_cnt, unused
   int* seen;
   int* err_flags;
 };
@@ -190,12 +187,8 @@ __global__ __launch_bounds__(kBlock) void k_seq_init(Seq S) {
   if ((int)(blockIdx.x * kBlock) >= t) return;
   for_incidences(S, t, [&](int, int, int a, int b, int e) {
     const size_t ca = (size_t)e * S.k + a, cb = (size_t)e * S.k + b;
-    S.out_max[ca] = 0;
-    S.in_min[ca] = INT_MAX;
-    S.out_cnt[ca] = 0;
-    S.out_max[cb] = 0;
-    S.in_min[cb] = INT_MAX;
-    S.out_cnt[cb] = 0;
+    S.cell[ca] = make_int4(0, INT_MAX, 0, 0);
+    S.cell[cb] = make_int4(0, INT_MAX, 0, 0);
   });
 }
 
@@ -204,9 +197,9 @@ __global__ __launch_bounds__(kBlock) void k_seq_collect(Seq S) {
   if ((int)(blockIdx.x * kBlock) >= t) return;
   for_incidences(S, t, [&](int j, int, int a, int b, int e) {
     const size_t ca = (size_t)e * S.k + a, cb = (size_t)e * S.k + b;
-    atomicMax(&S.out_max[ca], j + 1);
-    atomicAdd(&S.out_cnt[ca], 1);
-    atomicMin(&S.in_min[cb], j + 1);
+    atomicMax(&S.cell[ca].x, j + 1);
+    atomicAdd(&S.cell[ca].z, 1);
+    atomicMin(&S.cell[cb].y, j + 1);
   });
 }
 
@@ -220,10 +213,9 @@ __global__ __launch_bounds__(kBlock) void k_seq_gains(Seq S, long long* gains) {
   for_incidences(S, t, [&](int j, int, int a, int b, int e) {
     const int J = j + 1;
     const size_t ca = (size_t)e * S.k + a, cb = (size_t)e * S.k + b;
-    const bool last_out = S.phi[ca] - S.out_cnt[ca] == 0 && S.out_max[ca] == J &&
-                          S.in_min[ca] > J;
-    const bool first_in = S.phi[cb] - S.out_cnt[cb] == 0 && S.in_min[cb] == J &&
-                          S.out_max[cb] < J;
+    const int4 A = S.cell[ca], B = S.cell[cb];
+    const bool last_out = S.phi[ca] - A.z == 0 && A.x == J && A.y > J;
+    const bool first_in = S.phi[cb] - B.z == 0 && B.y == J && B.x < J;
     if (last_out != first_in) {
       const long long w = S.ewgt ? S.ewgt[e] : 1;
       atomicAdd((unsigned long long*)&s_gain[j - blockIdx.x * kBlock],
@@ -797,9 +789,7 @@ static Seq make_seq(hg_graph_s* g, int k, char* ws, const MovesLayout& L, const 
   S.vwgt = g->vwgt;
   S.n = g->n;
   S.k = k;
-  S.out_max = (int*)(ws + L.out_max);
-  S.in_min = (int*)(ws + L.in_min);
-  S.out_cnt = (int*)(ws + L.out_cnt);
+  S.cell = (int4*)(ws + L.cell);
   S.seen = (int*)(ws + L.seen);
   S.err_flags = (int*)(g->ws + g->lay.flags);
   return S;
@@ -834,7 +824,8 @@ hipError_t launch_best_prefix(hg_graph_s* g, int k, long long lmax, const int* p
   MovesLayout L;
   memset(&L, 0, sizeof(L));
   Seq S = make_seq(g, k, nullptr, L, part, nullptr, mu, mt, t);
-  S.out_max = S.in_min = S.out_cnt = S.seen = nullptr;
+  S.cell = nullptr;
+  S.seen = nullptr;
   hipLaunchKernelGGL(k_best_prefix_balanced, dim3(1), dim3(kBlock), 0, s, S, lmax, block_w, gains,
                      out2);
   hipLaunchKernelGGL(k_copy_best, dim3(1), dim3(kWave), 0, s, out2, best_len, best_gain);
