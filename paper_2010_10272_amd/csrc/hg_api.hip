@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "hg_internal.h"
+#include "hg_sort.h"
 #include "hg_lp.h"
 
 namespace hg {
@@ -120,7 +121,6 @@ hg_status timing_marks(hg_graph_s* g, hipStream_t s, hipEvent_t** marks) {
 namespace hg {
 
 WsLayout ws_layout(int n, int m, long long P, int k_max) {
-  (void)P;
   WsLayout L;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -144,6 +144,11 @@ WsLayout ws_layout(int n, int m, long long P, int k_max) {
   L.flags = take(256);
   L.red = take(sizeof(unsigned long long) * kSlots);
   L.bw_slots = take(sizeof(long long) * kSlots * (size_t)k_max);
+  L.lkey[0] = take(sizeof(unsigned) * (size_t)P);
+  L.lkey[1] = take(sizeof(unsigned) * (size_t)P);
+  L.lval = take(sizeof(int) * (size_t)P);
+  L.lhist = take(sizeof(unsigned) * (size_t)kDigits * (size_t)sort_tiles(P));
+  L.ldtot = take(sizeof(unsigned) * kDigits);
   L.total = off;
   return L;
 }

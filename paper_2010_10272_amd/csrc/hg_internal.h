@@ -200,6 +200,7 @@ struct WsLayout {
   size_t cand, touched, heavy, big, hist, overflow, thr, tilesum, ctr, info, scan, flags;
   size_t red;   // kSlots partial sums for whole-array reductions (km1)
   size_t bw_slots;   // kSlots x k_max block-weight deltas (apply), folded in by the round record
+  size_t lkey[2], lval, lhist, ldtot;   // load only: radix-sort buffers of the transpose
   size_t total;
   int num_tiles;
   int scan_blocks;

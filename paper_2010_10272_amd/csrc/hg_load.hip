@@ -3,10 +3,9 @@
 //
 // The paper stores a hypergraph as two adjacency arrays, the pins of each net
 // and the incident nets of each vertex (section "Coarsening", subsection
-// "Contraction").  Here the second array is built on the device: degree count
-// (integer atomics), exclusive scan, scatter, then every row is sorted so that
-// I(v) lists nets in increasing id and the result does not depend on the
-// order in which the scatter's atomics happened.
+// "Contraction").  Here the second array is built on the device by a stable
+// radix sort of the (pin, net) pairs by pin, so that I(v) lists nets in
+// increasing id.
 #include "hg_device.h"
 #include "hg_internal.h"
 #include "hg_sort.h"
@@ -154,98 +153,52 @@ hipError_t load_check(hg_graph_s* g, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ transpose
-// Degree count: one integer atomic per pin (order-independent result).
-__global__ void k_count_degrees(long long P, const int* pins, int* deg) {
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  long long stride = (long long)gridDim.x * blockDim.x;
-  for (; i < P; i += stride) atomicAdd(&deg[pins[i]], 1);
-}
+// (pin, net) pairs in net order, stably radix-sorted by pin: the values are
+// then the incidence rows, each listing its nets in increasing id, with no
+// atomics anywhere (so nothing depends on timing).  Row starts come from
+// where the sorted keys change.
 
-// Exclusive scan of deg[0..n) into vptr[0..n], three passes.
-constexpr int kScanPerBlock = kBlock * 8;
-
-__global__ void k_scan_partials(int n, const int* deg, long long* partial) {
-  __shared__ long long s_tmp[kBlock / kWave];
-  long long base = (long long)blockIdx.x * kScanPerBlock;
-  long long sum = 0;
-  for (int j = 0; j < 8; ++j) {
-    long long i = base + (long long)j * kBlock + threadIdx.x;
-    if (i < n) sum += deg[i];
-  }
-  long long tot = block_sum64(sum, s_tmp);
-  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
-}
-
-// One workgroup scans the per-block partial sums in place (exclusive).
-__global__ void k_scan_top(int nblocks, long long* partial) {
-  __shared__ long long s_tmp[kBlock / kWave];
-  long long carry = 0;
-  for (int base = 0; base < nblocks; base += kBlock) {
-    int i = base + threadIdx.x;
-    long long v = i < nblocks ? partial[i] : 0;
-    long long tot;
-    long long ex = block_excl_scan64(v, s_tmp, &tot);
-    if (i < nblocks) partial[i] = carry + ex;
-    carry += tot;
-    __syncthreads();
-  }
-}
-
-__global__ void k_scan_final(int n, const int* deg, const long long* partial, long long* vptr,
-                             long long P) {
-  __shared__ long long s_tmp[kBlock / kWave];
-  long long base = (long long)blockIdx.x * kScanPerBlock;
-  // each thread owns 8 consecutive entries
-  long long first = base + (long long)threadIdx.x * 8;
-  int d[8];
-  long long local = 0;
-  for (int j = 0; j < 8; ++j) {
-    long long i = first + j;
-    d[j] = i < n ? deg[i] : 0;
-    local += d[j];
-  }
-  long long tot;
-  long long ex = block_excl_scan64(local, s_tmp, &tot);
-  long long run = partial[blockIdx.x] + ex;
-  for (int j = 0; j < 8; ++j) {
-    long long i = first + j;
-    if (i < n) vptr[i] = run;
-    run += d[j];
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) vptr[n] = P;
-}
-
-// Scatter: each wave walks the pins of 64 consecutive nets, load-balanced.
-__global__ void k_scatter(int m, const long long* eptr, const int* pins, const long long* vptr,
-                          int* cursor, int* vnets) {
+// Each wave expands the pins of 64 consecutive nets, load-balanced.
+__global__ void k_pin_pairs(int m, const long long* eptr, const int* pins, unsigned* key,
+                            int* val) {
   __shared__ int s_excl[kBlock / kWave][kWave];
   __shared__ long long s_begin[kBlock / kWave][kWave];
-  int w = threadIdx.x / kWave, lane = lane_id();
-  long long wave_global = (long long)blockIdx.x * (kBlock / kWave) + w;
-  long long e = wave_global * kWave + lane;
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  const long long wave_global = (long long)blockIdx.x * (kBlock / kWave) + w;
+  const long long e = wave_global * kWave + lane;
   long long b = 0;
   int len = 0;
   if (e < m) {
     b = eptr[e];
     len = (int)(eptr[e + 1] - b);
   }
-  int first_net = (int)(wave_global * kWave);
+  const int first_net = (int)(wave_global * kWave);
   wave_expand(b, len, s_excl[w], s_begin[w], [&](bool act, int owner, long long p) {
     if (act) {
-      int v = pins[p];
-      int pos = atomicAdd(&cursor[v], 1);
-      vnets[vptr[v] + pos] = first_net + owner;
+      key[p] = (unsigned)pins[p];
+      val[p] = first_net + owner;
     }
   });
 }
 
-// Sort incidence rows of length <= kSmallRow in place (one thread per
-// vertex, insertion sort), then gather per-vertex facts.  Longer rows are
-// listed for k_sort_big_rows.
-__global__ __launch_bounds__(kBlock) void k_sort_small_rows(int n, const long long* vptr,
-                                                            int* vnets, const int* ewgt,
-                                                            int* big_list, int* heavy_list,
-                                                            LoadInfo* info) {
+// vptr[v] = the first sorted position with key >= v; vptr[n] = P.
+__global__ void k_row_starts(long long P, int n, const unsigned* key, long long* vptr) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P) return;
+  const long long cur = key[i];
+  const long long prev = i == 0 ? -1 : (long long)key[i - 1];
+  for (long long v = prev + 1; v <= cur; ++v) vptr[v] = i;
+  if (i == P - 1)
+    for (long long v = cur + 1; v <= n; ++v) vptr[v] = P;
+}
+
+// Per-vertex facts of the sorted rows (one thread per row up to kSmallRow
+// incidences; longer rows are listed for k_big_row_facts): repeated nets
+// (a vertex twice in a net), degree, w(I(v)), the heavy list.
+__global__ __launch_bounds__(kBlock) void k_row_facts(int n, const long long* vptr,
+                                                      const int* vnets, const int* ewgt,
+                                                      int* big_list, int* heavy_list,
+                                                      LoadInfo* info) {
   __shared__ int s_imax[kBlock / kWave];
   __shared__ unsigned s_big, s_heavy, s_big_base, s_heavy_base;
   __shared__ int s_bigv[kBlock], s_heavyv[kBlock];
@@ -264,20 +217,14 @@ __global__ __launch_bounds__(kBlock) void k_sort_small_rows(int n, const long lo
       if (deg > kSmallRow) {
         big = true;
       } else {
-        int* row = vnets + b;
-        for (int i = 1; i < deg; ++i) {
-          const int x = row[i];
-          int j = i - 1;
-          while (j >= 0 && row[j] > x) {
-            row[j + 1] = row[j];
-            --j;
-          }
-          row[j + 1] = x;
-        }
+        const int* row = vnets + b;
         long long tot = 0;
+        int prev = -1;
         for (int i = 0; i < deg; ++i) {
-          if (i > 0 && row[i] == row[i - 1]) err = kErrDuplicate;
-          tot += ewgt ? ewgt[row[i]] : 1;
+          const int x = row[i];
+          if (x == prev) err = kErrDuplicate;
+          prev = x;
+          tot += ewgt ? ewgt[x] : 1;
         }
         const int incw = tot > 0x7fffffffLL ? 0x7fffffff : (int)tot;
         maxincw = incw > maxincw ? incw : maxincw;
@@ -305,35 +252,18 @@ __global__ __launch_bounds__(kBlock) void k_sort_small_rows(int n, const long lo
   }
 }
 
-// One workgroup per long row: bitonic sort with all comparators ascending
-// (indices past the row end act as +infinity and never move), in LDS when the
-// padded row fits, else in place in global memory.
-constexpr int kLdsSortCap = 8192;
-
-__global__ void k_sort_big_rows(const long long* vptr, int* vnets, const int* ewgt,
+// One workgroup per long row: the same facts with the row's entries spread
+// over the workgroup.
+__global__ void k_big_row_facts(const long long* vptr, const int* vnets, const int* ewgt,
                                 const int* big_list, int* heavy_list, LoadInfo* info) {
-  __shared__ int s_row[kLdsSortCap];
   __shared__ long long s_tmp[kBlock / kWave];
   __shared__ int s_err;
-  int v = big_list[blockIdx.x];
-  long long b = vptr[v];
-  int len = (int)(vptr[v + 1] - b);
-  int pow2 = 1;
-  while (pow2 < len) pow2 <<= 1;
-  int* row = vnets + b;
+  const int v = big_list[blockIdx.x];
+  const long long b = vptr[v];
+  const int len = (int)(vptr[v + 1] - b);
+  const int* row = vnets + b;
   if (threadIdx.x == 0) s_err = 0;
-  if (pow2 <= kLdsSortCap) {
-    for (int i = threadIdx.x; i < len; i += blockDim.x) s_row[i] = row[i];
-    __syncthreads();
-    bitonic_sort_block(len, pow2, [&](int i) { return s_row[i]; },
-                       [&](int i, int x) { s_row[i] = x; });
-    for (int i = threadIdx.x; i < len; i += blockDim.x) row[i] = s_row[i];
-    __syncthreads();
-  } else {
-    __syncthreads();
-    bitonic_sort_block(len, pow2, [&](int i) { return row[i]; },
-                       [&](int i, int x) { row[i] = x; });
-  }
+  __syncthreads();
   long long tot = 0;
   int err = 0;
   for (int i = threadIdx.x; i < len; i += blockDim.x) {
@@ -344,41 +274,53 @@ __global__ void k_sort_big_rows(const long long* vptr, int* vnets, const int* ew
   tot = block_sum64(tot, s_tmp);
   if (threadIdx.x == 0) {
     if (s_err) atomicOr(&info->err, s_err);
-    int incw = tot > 0x7fffffffLL ? 0x7fffffff : (int)tot;
+    const int incw = tot > 0x7fffffffLL ? 0x7fffffff : (int)tot;
     atomicMax(&info->max_degree, len);
     atomicMax(&info->max_incident_weight, incw);
     if (tot > kLightLimit) {
-      int hi = atomicAdd(&info->heavy_count, 1);
+      const int hi = atomicAdd(&info->heavy_count, 1);
       heavy_list[hi] = v;
     }
   }
 }
 
-// Builds vptr/vnets.  Needs LoadInfo.big_rows from a synchronized read to
-// launch the long-row pass, so it is split: this part runs the small-row pass
-// and leaves big_rows for load_sort_big.
+// Builds vptr/vnets and the short rows' facts.  The long-row pass needs
+// LoadInfo.big_rows from a synchronized read, so it is load_sort_big.
 hipError_t load_build(hg_graph_s* g, hipStream_t s) {
   LoadInfo* info = (LoadInfo*)(g->ws + g->lay.info);
-  int* deg = (int*)(g->ws + g->lay.cand);     // the candidate array is free at load time
-  int* cursor = deg + g->n;
-  long long* partial = (long long*)(g->ws + g->lay.scan);
   int* big = (int*)(g->ws + g->lay.big);
   int* heavy = (int*)(g->ws + g->lay.heavy);
-  hipError_t e = fill_i32(deg, 0, 2LL * g->n, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_count_degrees, dim3(grid_for(g->P, 4)), dim3(kBlock), 0, s, g->P,
-                     g->pins, deg);
-  int nb = g->lay.scan_blocks;
-  hipLaunchKernelGGL(k_scan_partials, dim3(nb), dim3(kBlock), 0, s, g->n, deg, partial);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, nb, partial);
-  hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(kBlock), 0, s, g->n, deg, partial, g->vptr,
-                     g->P);
-  long long waves = ((long long)g->m + kWave - 1) / kWave;
-  unsigned blocks = (unsigned)((waves + kBlock / kWave - 1) / (kBlock / kWave));
-  hipLaunchKernelGGL(k_scatter, dim3(blocks), dim3(kBlock), 0, s, g->m, g->eptr, g->pins,
-                     g->vptr, cursor, g->vnets);
-  hipLaunchKernelGGL(k_sort_small_rows, dim3(grid_cap_load(g->n)), dim3(kBlock), 0, s, g->n,
-                     g->vptr, g->vnets, g->ewgt, big, heavy, info);
+  const long long P = g->P;
+  int passes = 0;
+  for (int bits = 0; bits < 32 && (1ll << bits) < (long long)g->n; bits += 8) ++passes;
+  if (passes == 0) passes = 1;
+  // the last pass must leave its values in vnets
+  unsigned* key[2] = {(unsigned*)(g->ws + g->lay.lkey[0]), (unsigned*)(g->ws + g->lay.lkey[1])};
+  int* scratch = (int*)(g->ws + g->lay.lval);
+  int* val[2];
+  val[passes & 1] = g->vnets;
+  val[(passes & 1) ^ 1] = scratch;
+  const long long waves = ((long long)g->m + kWave - 1) / kWave;
+  const unsigned blocks = (unsigned)((waves + kBlock / kWave - 1) / (kBlock / kWave));
+  hipLaunchKernelGGL(k_pin_pairs, dim3(blocks), dim3(kBlock), 0, s, g->m, g->eptr, g->pins,
+                     key[0], val[0]);
+  SortPass SP;
+  SP.hist = (unsigned*)(g->ws + g->lay.lhist);
+  SP.dtot = (unsigned*)(g->ws + g->lay.ldtot);
+  SP.n = (int)P;
+  SP.tiles = sort_tiles(P);
+  for (int q = 0; q < passes; ++q) {
+    SP.key_in = key[q & 1];
+    SP.val_in = val[q & 1];
+    SP.key_out = key[(q & 1) ^ 1];
+    SP.val_out = val[(q & 1) ^ 1];
+    SP.shift = 8 * q;
+    sort_pass(SP, s);
+  }
+  hipLaunchKernelGGL(k_row_starts, dim3((unsigned)((P + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                     s, P, g->n, (const unsigned*)key[passes & 1], g->vptr);
+  hipLaunchKernelGGL(k_row_facts, dim3(grid_cap_load(g->n)), dim3(kBlock), 0, s, g->n, g->vptr,
+                     g->vnets, g->ewgt, big, heavy, info);
   return hipGetLastError();
 }
 
@@ -387,7 +329,7 @@ hipError_t load_sort_big(hg_graph_s* g, int big_rows, hipStream_t s) {
   LoadInfo* info = (LoadInfo*)(g->ws + g->lay.info);
   int* big = (int*)(g->ws + g->lay.big);
   int* heavy = (int*)(g->ws + g->lay.heavy);
-  hipLaunchKernelGGL(k_sort_big_rows, dim3(big_rows), dim3(kBlock), 0, s, g->vptr, g->vnets,
+  hipLaunchKernelGGL(k_big_row_facts, dim3(big_rows), dim3(kBlock), 0, s, g->vptr, g->vnets,
                      g->ewgt, big, heavy, info);
   return hipGetLastError();
 }
