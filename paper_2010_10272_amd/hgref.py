@@ -825,6 +825,7 @@ def contract_workspace(g):
 
 def hg_contract(g, cluster, out, ws, stream=None):
     cluster = _dev(cluster, torch.int32, g.device)
+    out.cluster = cluster          # alive while the call may still be running
     _check(_lib.hg_contract(g.handle, _ptr(cluster), _ptr(out.map), _ptr(out.cvwgt),
                             _ptr(out.ceptr), _ptr(out.cpins), _ptr(out.cewgt), _ptr(out.sizes),
                             _ptr(ws), ws.numel(), _stream(stream)))
