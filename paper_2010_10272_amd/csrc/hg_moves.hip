@@ -538,6 +538,7 @@ struct Rb {
   long long* excess;           // [k]: c(V_i) - L_max
   int* cnt_src;                // [k + 1]: candidates per source (sentinel k last)
   int* cnt_tgt;                // [k + 1]: proposals per target
+  int* cnt_slots;              // [kSlots][k + 1]: per-workgroup-slot counts, summed into cnt
   unsigned char* prop;         // [n]: proposed this round
   int* mt;                     // [n]: target of sorted item i (own block: rejected)
   int* gord;                   // [n]: candidates in (gain desc, id asc) order
@@ -555,6 +556,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_begin(InstDesc D, Rb R) {
     R.cnt_src[i] = 0;
     R.cnt_tgt[i] = 0;
   }
+  for (int i = threadIdx.x; i < kSlots * (k + 1); i += kBlock) R.cnt_slots[i] = 0;
   if (threadIdx.x == 0) {
     R.best[0] = 0;
     R.best[1] = D.n;
@@ -647,19 +649,20 @@ __global__ __launch_bounds__(kBlock) void k_rb_select(InstDesc D, Rb R, unsigned
 
 // Regroup keys: item i of `order` gets key = source block (by_target = 0)
 // or, for proposals, target block (by_target = 1); everything else the
-// sentinel k.  Counts per key go to cnt[0..k].
+// sentinel k.  Counts per key go to the count slots (k_rb_sum_counts).
 __global__ __launch_bounds__(kBlock) void k_rb_keys(InstDesc D, Rb R, const int* order,
                                                     int by_target, unsigned* key_out,
-                                                    int* val_out, int* cnt) {
+                                                    int* val_out) {
   __shared__ int s_cnt[HG_MAX_K + 1];
   const int k = D.k;
   for (int i = threadIdx.x; i <= k; i += kBlock) s_cnt[i] = 0;
   __syncthreads();
   const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (i < D.n) {
+  const bool live = i < D.n;
+  int key = k;
+  if (live) {
     const int u = order[i];
     const long long c = D.cand[u];
-    int key = k;
     if (!by_target) {
       R.gord[i] = u;
       if (c != -1) key = D.part[u];
@@ -668,11 +671,37 @@ __global__ __launch_bounds__(kBlock) void k_rb_keys(InstDesc D, Rb R, const int*
     }
     key_out[i] = (unsigned)key;
     val_out[i] = u;
-    atomicAdd(&s_cnt[key], 1);
+  }
+  // most lanes share a key (the sentinel above all): one LDS add per
+  // distinct key and wavefront
+  unsigned long long left = __ballot(live);
+  while (left) {
+    const int leader = __ffsll((long long)left) - 1;
+    const int lk = __shfl(key, leader);
+    const unsigned long long same = __ballot(live && key == lk);
+    if (lane_id() == leader) atomicAdd(&s_cnt[lk], (int)__popcll(same));
+    left &= ~same;
   }
   __syncthreads();
+  // one of kSlots partial counts per workgroup (a single shared counter
+  // would take every workgroup's atomic in turn)
+  int* slot = R.cnt_slots + (blockIdx.x % kSlots) * (k + 1);
   for (int j = threadIdx.x; j <= k; j += kBlock)
-    if (s_cnt[j]) atomicAdd(&cnt[j], s_cnt[j]);
+    if (s_cnt[j]) atomicAdd(&slot[j], s_cnt[j]);
+}
+
+// cnt[j] = the sum of the slots' counts of key j; the slots are cleared for
+// the next regrouping.
+__global__ __launch_bounds__(kBlock) void k_rb_sum_counts(InstDesc D, Rb R, int* cnt) {
+  const int k = D.k;
+  for (int j = threadIdx.x; j <= k; j += kBlock) {
+    int sum = 0;
+    for (int q = 0; q < kSlots; ++q) {
+      sum += R.cnt_slots[q * (k + 1) + j];
+      R.cnt_slots[q * (k + 1) + j] = 0;
+    }
+    cnt[j] = sum;
+  }
 }
 
 // Items in sorted order with their weights: c(u) for items not keyed by
@@ -905,7 +934,8 @@ hipError_t launch_round_exact(hg_graph_s* g, InstDesc d, int round, char* ws, hi
 // ------------------------------------------------------------ rebalancing
 
 struct RebalLayout {
-  size_t cache, key[2], val[2], gord, prop, mt, scan, csum, coff, excess, cnt_src, cnt_tgt, best,
+  size_t cache, key[2], val[2], gord, prop, mt, scan, csum, coff, excess, cnt_src, cnt_tgt,
+      cnt_slots, best,
       hist, dtot, total;
   int sort_tiles, chunks;
 };
@@ -934,6 +964,7 @@ static RebalLayout rebal_layout(long long n, int k) {
   L.excess = take(sizeof(long long) * HG_MAX_K);
   L.cnt_src = take(sizeof(int) * (HG_MAX_K + 1));
   L.cnt_tgt = take(sizeof(int) * (HG_MAX_K + 1));
+  L.cnt_slots = take(sizeof(int) * kSlots * (HG_MAX_K + 1));
   L.best = take(sizeof(long long) * 2);
   L.hist = take(sizeof(unsigned) * (size_t)kDigits * L.sort_tiles);
   L.dtot = take(sizeof(unsigned) * kDigits);
@@ -952,6 +983,7 @@ static hipError_t launch_rebalance_round(hg_graph_s* g, InstDesc d, char* ws, hi
   R.excess = (long long*)(ws + L.excess);
   R.cnt_src = (int*)(ws + L.cnt_src);
   R.cnt_tgt = (int*)(ws + L.cnt_tgt);
+  R.cnt_slots = (int*)(ws + L.cnt_slots);
   R.prop = (unsigned char*)(ws + L.prop);
   R.mt = (int*)(ws + L.mt);
   R.gord = (int*)(ws + L.gord);
@@ -1011,7 +1043,8 @@ static hipError_t launch_rebalance_round(hg_graph_s* g, InstDesc d, char* ws, hi
   };
   // by source block, proposals per source
   hipLaunchKernelGGL(k_rb_keys, dim3(grid), dim3(kBlock), 0, s, d, R, val[cur], 0, key[cur ^ 1],
-                     val[cur ^ 1], R.cnt_src);
+                     val[cur ^ 1]);
+  hipLaunchKernelGGL(k_rb_sum_counts, dim3(1), dim3(kBlock), 0, s, d, R, R.cnt_src);
   cur ^= 1;
   for (int shift = 0; shift < kbits; shift += 8) pass(shift);
   RbItems I;
@@ -1024,7 +1057,8 @@ static hipError_t launch_rebalance_round(hg_graph_s* g, InstDesc d, char* ws, hi
   hipLaunchKernelGGL(k_rb_propose, dim3(grid), dim3(kBlock), 0, s, d, R, I);
   // proposals by target block, approvals per target
   hipLaunchKernelGGL(k_rb_keys, dim3(grid), dim3(kBlock), 0, s, d, R, R.gord, 1, key[cur ^ 1],
-                     val[cur ^ 1], R.cnt_tgt);
+                     val[cur ^ 1]);
+  hipLaunchKernelGGL(k_rb_sum_counts, dim3(1), dim3(kBlock), 0, s, d, R, R.cnt_tgt);
   cur ^= 1;
   for (int shift = 0; shift < kbits; shift += 8) pass(shift);
   I.key = key[cur];
