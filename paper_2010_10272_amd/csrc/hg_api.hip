@@ -149,6 +149,7 @@ WsLayout ws_layout(int n, int m, long long P, int k_max) {
   L.lval = take(sizeof(int) * (size_t)P);
   L.lhist = take(sizeof(unsigned) * (size_t)kDigits * (size_t)sort_tiles(P));
   L.ldtot = take(sizeof(unsigned) * kDigits);
+  L.lpart = take(sizeof(LoadPart) * kLoadGrid);
   L.total = off;
   return L;
 }

@@ -92,6 +92,15 @@ struct LoadInfo {
   int pad[5];
 };
 
+// One load workgroup's share of the LoadInfo maxima and sums; the load folds
+// them into LoadInfo with one small kernel instead of one atomic per
+// workgroup on the same words.
+constexpr int kLoadGrid = 1024;   // workgroups of the load's sweeps
+struct LoadPart {
+  unsigned long long total_net_weight, total_vertex_weight;
+  int max_net_size, max_vertex_weight, max_degree, max_incident_weight;
+};
+
 // Everything a kernel needs about one instance: a loaded hypergraph, its
 // workspace, and one k-way partition state.  Single-instance entry points pass
 // one by value inside the kernel arguments; batched launches pass a device
@@ -201,6 +210,7 @@ struct WsLayout {
   size_t red;   // kSlots partial sums for whole-array reductions (km1)
   size_t bw_slots;   // kSlots x k_max block-weight deltas (apply), folded in by the round record
   size_t lkey[2], lval, lhist, ldtot;   // load only: radix-sort buffers of the transpose
+  size_t lpart;      // load only: per-workgroup partial facts (LoadPart[kLoadGrid])
   size_t total;
   int num_tiles;
   int scan_blocks;

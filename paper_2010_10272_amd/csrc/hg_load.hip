@@ -53,9 +53,8 @@ hipError_t fill_u8(unsigned char* p, unsigned char v, long long count, hipStream
 }
 
 // ------------------------------------------------------------------ checks
-// Load-time checks run on a capped grid and reduce per workgroup, so that
-// each shared LoadInfo field takes at most one atomic per workgroup.
-constexpr int kLoadGrid = 1024;
+// Load-time checks run on a capped grid (kLoadGrid) and reduce per
+// workgroup into that workgroup's LoadPart; k_fold_load folds the parts.
 
 __device__ __forceinline__ int block_max_int(int v, int* s_tmp) {
   v = wave_max(v);
@@ -70,7 +69,7 @@ __device__ __forceinline__ int block_max_int(int v, int* s_tmp) {
 // Nets: increasing offsets with fixed ends (no empty net), positive weights.
 __global__ __launch_bounds__(kBlock) void k_check_nets(int m, long long P,
                                                        const long long* eptr, const int* ewgt,
-                                                       LoadInfo* info) {
+                                                       LoadInfo* info, LoadPart* part) {
   __shared__ long long s_tmp[kBlock / kWave];
   __shared__ int s_imax[kBlock / kWave];
   int err = 0, size = 0;
@@ -90,8 +89,8 @@ __global__ __launch_bounds__(kBlock) void k_check_nets(int m, long long P,
   const int mx = block_max_int(size, s_imax);
   const long long ws = block_sum64(wsum, s_tmp);
   if (threadIdx.x == 0) {
-    atomicMax(&info->max_net_size, mx);
-    atomicAdd(&info->total_net_weight, (unsigned long long)ws);
+    part[blockIdx.x].max_net_size = mx;
+    part[blockIdx.x].total_net_weight = (unsigned long long)ws;
   }
 }
 
@@ -108,7 +107,7 @@ __global__ __launch_bounds__(kBlock) void k_check_pins(int n, long long P, const
 }
 
 __global__ __launch_bounds__(kBlock) void k_check_vertices(int n, const int* vwgt,
-                                                           LoadInfo* info) {
+                                                           LoadInfo* info, LoadPart* part) {
   __shared__ long long s_tmp[kBlock / kWave];
   __shared__ int s_imax[kBlock / kWave];
   int err = 0, cmax = 0;
@@ -127,8 +126,39 @@ __global__ __launch_bounds__(kBlock) void k_check_vertices(int n, const int* vwg
   const int mx = block_max_int(cmax, s_imax);
   const long long cs = block_sum64(csum, s_tmp);
   if (threadIdx.x == 0) {
-    atomicAdd(&info->total_vertex_weight, (unsigned long long)cs);
-    atomicMax(&info->max_vertex_weight, mx);
+    part[blockIdx.x].total_vertex_weight = (unsigned long long)cs;
+    part[blockIdx.x].max_vertex_weight = mx;
+  }
+}
+
+// LoadInfo's maxima and sums from the workgroups' parts (one workgroup).
+__global__ __launch_bounds__(kBlock) void k_fold_load(const LoadPart* part, LoadInfo* info) {
+  __shared__ long long s_tmp[kBlock / kWave];
+  __shared__ int s_imax[kBlock / kWave];
+  unsigned long long tnw = 0, tvw = 0;
+  int mns = 0, mvw = 0, md = 0, miw = 0;
+  for (int b = threadIdx.x; b < kLoadGrid; b += kBlock) {
+    const LoadPart p = part[b];
+    tnw += p.total_net_weight;
+    tvw += p.total_vertex_weight;
+    mns = p.max_net_size > mns ? p.max_net_size : mns;
+    mvw = p.max_vertex_weight > mvw ? p.max_vertex_weight : mvw;
+    md = p.max_degree > md ? p.max_degree : md;
+    miw = p.max_incident_weight > miw ? p.max_incident_weight : miw;
+  }
+  tnw = (unsigned long long)block_sum64((long long)tnw, s_tmp);
+  tvw = (unsigned long long)block_sum64((long long)tvw, s_tmp);
+  mns = block_max_int(mns, s_imax);
+  mvw = block_max_int(mvw, s_imax);
+  md = block_max_int(md, s_imax);
+  miw = block_max_int(miw, s_imax);
+  if (threadIdx.x == 0) {
+    info->total_net_weight = tnw;
+    info->total_vertex_weight = tvw;
+    info->max_net_size = mns;
+    info->max_vertex_weight = mvw;
+    info->max_degree = md;
+    info->max_incident_weight = miw;
   }
 }
 
@@ -143,12 +173,16 @@ hipError_t load_check(hg_graph_s* g, hipStream_t s) {
   LoadInfo* info = (LoadInfo*)(g->ws + g->lay.info);
   hipError_t e = fill_i32((int*)info, 0, sizeof(LoadInfo) / sizeof(int), s);
   if (e != hipSuccess) return e;
+  LoadPart* part = (LoadPart*)(g->ws + g->lay.lpart);
+  e = fill_i32((int*)part, 0, (long long)(sizeof(LoadPart) / sizeof(int)) * kLoadGrid, s);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_check_nets, dim3(grid_cap_load(g->m)), dim3(kBlock), 0, s, g->m, g->P,
-                     g->eptr, g->ewgt, info);
+                     g->eptr, g->ewgt, info, part);
   hipLaunchKernelGGL(k_check_pins, dim3(grid_for(g->P, 4)), dim3(kBlock), 0, s, g->n, g->P,
                      g->pins, info);
   hipLaunchKernelGGL(k_check_vertices, dim3(grid_cap_load(g->n)), dim3(kBlock), 0, s, g->n,
-                     g->vwgt, info);
+                     g->vwgt, info, part);
+  hipLaunchKernelGGL(k_fold_load, dim3(1), dim3(kBlock), 0, s, (const LoadPart*)part, info);
   return hipGetLastError();
 }
 
@@ -198,7 +232,7 @@ __global__ void k_row_starts(long long P, int n, const unsigned* key, long long*
 __global__ __launch_bounds__(kBlock) void k_row_facts(int n, const long long* vptr,
                                                       const int* vnets, const int* ewgt,
                                                       int* big_list, int* heavy_list,
-                                                      LoadInfo* info) {
+                                                      LoadInfo* info, LoadPart* part) {
   __shared__ int s_imax[kBlock / kWave];
   __shared__ unsigned s_big, s_heavy, s_big_base, s_heavy_base;
   __shared__ int s_bigv[kBlock], s_heavyv[kBlock];
@@ -247,8 +281,8 @@ __global__ __launch_bounds__(kBlock) void k_row_facts(int n, const long long* vp
   const int md = block_max_int(maxdeg, s_imax);
   const int mi = block_max_int(maxincw, s_imax);
   if (threadIdx.x == 0) {
-    atomicMax(&info->max_degree, md);
-    atomicMax(&info->max_incident_weight, mi);
+    part[blockIdx.x].max_degree = md;
+    part[blockIdx.x].max_incident_weight = mi;
   }
 }
 
@@ -319,8 +353,10 @@ hipError_t load_build(hg_graph_s* g, hipStream_t s) {
   }
   hipLaunchKernelGGL(k_row_starts, dim3((unsigned)((P + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                      s, P, g->n, (const unsigned*)key[passes & 1], g->vptr);
+  LoadPart* part = (LoadPart*)(g->ws + g->lay.lpart);
   hipLaunchKernelGGL(k_row_facts, dim3(grid_cap_load(g->n)), dim3(kBlock), 0, s, g->n, g->vptr,
-                     g->vnets, g->ewgt, big, heavy, info);
+                     g->vnets, g->ewgt, big, heavy, info, part);
+  hipLaunchKernelGGL(k_fold_load, dim3(1), dim3(kBlock), 0, s, (const LoadPart*)part, info);
   return hipGetLastError();
 }
 
