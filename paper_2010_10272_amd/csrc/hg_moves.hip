@@ -125,17 +125,21 @@ __device__ __forceinline__ bool seq_move(const Seq& S, int j, int& u, int& a, in
 
 // Every incidence (move j, net e) of the workgroup's kBlock moves, spread
 // over all threads (prefix sum of the movers' degrees, owner by binary
-// search in LDS).  f(j, u, a, b, e) is called once per incidence.
+// search in LDS).  f(j, u, a, b, e) is called once per incidence.  A
+// workgroup owns kSeqTile moves, so a short sequence still spreads over
+// many workgroups.
+constexpr int kSeqTile = 64;
+
 template <typename F>
 __device__ void for_incidences(const Seq& S, int t, F f) {
   __shared__ long long s_beg[kBlock];
   __shared__ int s_off[kBlock + 1];
   __shared__ int s_u[kBlock], s_a[kBlock], s_b[kBlock];
   __shared__ long long s_tmp[kBlock / kWave];
-  const int j = blockIdx.x * kBlock + threadIdx.x;
+  const int j = blockIdx.x * kSeqTile + threadIdx.x;
   int u = -1, a = 0, b = 0;
   long long len = 0, beg = 0;
-  if (j < t && seq_move(S, j, u, a, b)) {
+  if (threadIdx.x < kSeqTile && j < t && seq_move(S, j, u, a, b)) {
     beg = S.vptr[u];
     len = S.vptr[u + 1] - beg;
   } else {
@@ -150,14 +154,14 @@ __device__ void for_incidences(const Seq& S, int t, F f) {
   s_b[threadIdx.x] = b;
   __syncthreads();
   for (long long x = threadIdx.x; x < total; x += kBlock) {
-    int lo = 0, hi = kBlock - 1;   // owner: last slot with s_off <= x
+    int lo = 0, hi = kSeqTile - 1;   // owner: last slot with s_off <= x
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (s_off[mid] <= x) lo = mid; else hi = mid - 1;
     }
     // slots without a move have length 0, so the owner always holds one
     const int e = S.vnets[s_beg[lo] + (x - s_off[lo])];
-    f(blockIdx.x * kBlock + lo, s_u[lo], s_a[lo], s_b[lo], e);
+    f(blockIdx.x * kSeqTile + lo, s_u[lo], s_a[lo], s_b[lo], e);
   }
 }
 
@@ -184,7 +188,7 @@ __global__ __launch_bounds__(kBlock) void k_seq_clear(Seq S) {
 // Cells (e, a) and (e, b) of every incidence start empty.
 __global__ __launch_bounds__(kBlock) void k_seq_init(Seq S) {
   const int t = seq_len(S);
-  if ((int)(blockIdx.x * kBlock) >= t) return;
+  if ((int)(blockIdx.x * kSeqTile) >= t) return;
   for_incidences(S, t, [&](int, int, int a, int b, int e) {
     const size_t ca = (size_t)e * S.k + a, cb = (size_t)e * S.k + b;
     S.cell[ca] = make_int4(0, INT_MAX, 0, 0);
@@ -194,7 +198,7 @@ __global__ __launch_bounds__(kBlock) void k_seq_init(Seq S) {
 
 __global__ __launch_bounds__(kBlock) void k_seq_collect(Seq S) {
   const int t = seq_len(S);
-  if ((int)(blockIdx.x * kBlock) >= t) return;
+  if ((int)(blockIdx.x * kSeqTile) >= t) return;
   for_incidences(S, t, [&](int j, int, int a, int b, int e) {
     const size_t ca = (size_t)e * S.k + a, cb = (size_t)e * S.k + b;
     atomicMax(&S.cell[ca].x, j + 1);
@@ -205,10 +209,10 @@ __global__ __launch_bounds__(kBlock) void k_seq_collect(Seq S) {
 
 // gains[j] = exact gain of move j (the Lemma).
 __global__ __launch_bounds__(kBlock) void k_seq_gains(Seq S, long long* gains) {
-  __shared__ long long s_gain[kBlock];
+  __shared__ long long s_gain[kSeqTile];
   const int t = seq_len(S);
-  if ((int)(blockIdx.x * kBlock) >= t) return;
-  s_gain[threadIdx.x] = 0;
+  if ((int)(blockIdx.x * kSeqTile) >= t) return;
+  if (threadIdx.x < kSeqTile) s_gain[threadIdx.x] = 0;
   __syncthreads();
   for_incidences(S, t, [&](int j, int, int a, int b, int e) {
     const int J = j + 1;
@@ -218,13 +222,13 @@ __global__ __launch_bounds__(kBlock) void k_seq_gains(Seq S, long long* gains) {
     const bool first_in = S.phi[cb] - B.z == 0 && B.y == J && B.x < J;
     if (last_out != first_in) {
       const long long w = S.ewgt ? S.ewgt[e] : 1;
-      atomicAdd((unsigned long long*)&s_gain[j - blockIdx.x * kBlock],
+      atomicAdd((unsigned long long*)&s_gain[j - blockIdx.x * kSeqTile],
                 (unsigned long long)(last_out ? w : -w));
     }
   });
   __syncthreads();
-  const int j = blockIdx.x * kBlock + threadIdx.x;
-  if (j < t) gains[j] = s_gain[threadIdx.x];
+  const int j = blockIdx.x * kSeqTile + threadIdx.x;
+  if (threadIdx.x < kSeqTile && j < t) gains[j] = s_gain[threadIdx.x];
 }
 
 // Pass input of a monotone round: key = top - gain for marked vertices (so
@@ -381,15 +385,15 @@ __global__ __launch_bounds__(kBlock) void k_apply_prefix(Seq S, const long long*
   __shared__ unsigned long long s_dW[HG_MAX_K];
   __shared__ long long s_tmp2[kBlock / kWave];
   const int p = (int)best[1];
-  if ((int)(blockIdx.x * kBlock) >= p) return;
+  if ((int)(blockIdx.x * kSeqTile) >= p) return;
   const int k = D.k;
   for (int i = threadIdx.x; i < k; i += kBlock) s_dW[i] = 0;
   __syncthreads();
   long long delta = 0, moved_pins = 0, approved = 0;
   {
-    const int j = blockIdx.x * kBlock + threadIdx.x;
+    const int j = blockIdx.x * kSeqTile + threadIdx.x;
     int u, a, b;
-    if (j < p && seq_move(S, j, u, a, b)) {
+    if (threadIdx.x < kSeqTile && j < p && seq_move(S, j, u, a, b)) {
       const long long cu = D.vwgt ? D.vwgt[u] : 1;
       atomicAdd(&s_dW[b], (unsigned long long)cu);
       atomicAdd(&s_dW[a], (unsigned long long)(-cu));
@@ -411,9 +415,9 @@ __global__ __launch_bounds__(kBlock) void k_apply_prefix(Seq S, const long long*
   });
   __syncthreads();
   {
-    const int j = blockIdx.x * kBlock + threadIdx.x;
+    const int j = blockIdx.x * kSeqTile + threadIdx.x;
     int u, a, b;
-    if (j < p && seq_move(S, j, u, a, b)) D.part[u] = b;
+    if (threadIdx.x < kSeqTile && j < p && seq_move(S, j, u, a, b)) D.part[u] = b;
   }
   long long* my_dw = D.bw_slots + (size_t)(blockIdx.x % kSlots) * k;
   for (int i = threadIdx.x; i < k; i += kBlock)
@@ -545,7 +549,7 @@ struct Rb {
   long long* scan;             // [n]: exclusive prefix of item weights
   long long* csum;             // [chunks]
   long long* coff;             // [chunks]
-  long long* best;             // [2]: {0, n}, the apply's sequence length
+  long long* best;             // [2]: {0, number of proposals}, the apply's sequence length
   unsigned bias;               // max incident weight: key = bias - gain >= 0
 };
 
@@ -691,9 +695,14 @@ __global__ __launch_bounds__(kBlock) void k_rb_keys(InstDesc D, Rb R, const int*
 }
 
 // cnt[j] = the sum of the slots' counts of key j; the slots are cleared for
-// the next regrouping.
-__global__ __launch_bounds__(kBlock) void k_rb_sum_counts(InstDesc D, Rb R, int* cnt) {
+// the next regrouping.  For the regrouping by target (set_len), the number
+// of proposals (keys below the sentinel, sorted first) becomes the length of
+// the sequence the apply walks.
+__global__ __launch_bounds__(kBlock) void k_rb_sum_counts(InstDesc D, Rb R, int* cnt,
+                                                          int set_len) {
+  __shared__ long long s_tmp[kBlock / kWave];
   const int k = D.k;
+  long long below = 0;
   for (int j = threadIdx.x; j <= k; j += kBlock) {
     int sum = 0;
     for (int q = 0; q < kSlots; ++q) {
@@ -701,7 +710,10 @@ __global__ __launch_bounds__(kBlock) void k_rb_sum_counts(InstDesc D, Rb R, int*
       R.cnt_slots[q * (k + 1) + j] = 0;
     }
     cnt[j] = sum;
+    if (j < k) below += sum;
   }
+  below = block_sum64(below, s_tmp);
+  if (set_len && threadIdx.x == 0) R.best[1] = below;
 }
 
 // Items in sorted order with their weights: c(u) for items not keyed by
@@ -839,9 +851,10 @@ hipError_t launch_move_gains(hg_graph_s* g, int k, const int* part, const int* p
   // anything), then the checks claim each vertex once
   hipLaunchKernelGGL(k_seq_clear, dim3(grid), dim3(kBlock), 0, s, S);
   hipLaunchKernelGGL(k_seq_check, dim3(grid), dim3(kBlock), 0, s, S);
-  hipLaunchKernelGGL(k_seq_init, dim3(grid), dim3(kBlock), 0, s, S);
-  hipLaunchKernelGGL(k_seq_collect, dim3(grid), dim3(kBlock), 0, s, S);
-  hipLaunchKernelGGL(k_seq_gains, dim3(grid), dim3(kBlock), 0, s, S, gains);
+  const unsigned tiles = grid_of(t, kSeqTile);
+  hipLaunchKernelGGL(k_seq_init, dim3(tiles), dim3(kBlock), 0, s, S);
+  hipLaunchKernelGGL(k_seq_collect, dim3(tiles), dim3(kBlock), 0, s, S);
+  hipLaunchKernelGGL(k_seq_gains, dim3(tiles), dim3(kBlock), 0, s, S, gains);
   hipLaunchKernelGGL(k_seq_clear, dim3(grid), dim3(kBlock), 0, s, S);
   return hipGetLastError();
 }
@@ -912,10 +925,10 @@ hipError_t launch_round_exact(hg_graph_s* g, InstDesc d, int round, char* ws, hi
   S.t_dev = tdev;
   hipLaunchKernelGGL(k_count_marked, dim3(1), dim3(kWave), 0, s, d.ctr->slot[kCtrMarked], tdev);
   long long* gains = (long long*)(ws + L.gains);
-  const unsigned grid = grid_of(n, kBlock);
-  hipLaunchKernelGGL(k_seq_init, dim3(grid), dim3(kBlock), 0, s, S);
-  hipLaunchKernelGGL(k_seq_collect, dim3(grid), dim3(kBlock), 0, s, S);
-  hipLaunchKernelGGL(k_seq_gains, dim3(grid), dim3(kBlock), 0, s, S, gains);
+  const unsigned tiles = grid_of(n, kSeqTile);
+  hipLaunchKernelGGL(k_seq_init, dim3(tiles), dim3(kBlock), 0, s, S);
+  hipLaunchKernelGGL(k_seq_collect, dim3(tiles), dim3(kBlock), 0, s, S);
+  hipLaunchKernelGGL(k_seq_gains, dim3(tiles), dim3(kBlock), 0, s, S, gains);
   long long* csum = (long long*)(ws + L.csum);
   long long* coff = (long long*)(ws + L.coff);
   long long* cbv = (long long*)(ws + L.cbest_v);
@@ -925,7 +938,7 @@ hipError_t launch_round_exact(hg_graph_s* g, InstDesc d, int round, char* ws, hi
   hipLaunchKernelGGL(k_prefix_top, dim3(1), dim3(kBlock), 0, s, csum, coff, L.chunks);
   hipLaunchKernelGGL(k_prefix_best, dim3(L.chunks), dim3(kBlock), 0, s, S, gains, coff, cbv, cbi);
   hipLaunchKernelGGL(k_prefix_final, dim3(1), dim3(kBlock), 0, s, cbv, cbi, L.chunks, best);
-  hipLaunchKernelGGL(k_apply_prefix, dim3(grid), dim3(kBlock), 0, s, S, best, d);
+  hipLaunchKernelGGL(k_apply_prefix, dim3(tiles), dim3(kBlock), 0, s, S, best, d);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_round_back(plan, round, s, nullptr);
@@ -1044,7 +1057,7 @@ static hipError_t launch_rebalance_round(hg_graph_s* g, InstDesc d, char* ws, hi
   // by source block, proposals per source
   hipLaunchKernelGGL(k_rb_keys, dim3(grid), dim3(kBlock), 0, s, d, R, val[cur], 0, key[cur ^ 1],
                      val[cur ^ 1]);
-  hipLaunchKernelGGL(k_rb_sum_counts, dim3(1), dim3(kBlock), 0, s, d, R, R.cnt_src);
+  hipLaunchKernelGGL(k_rb_sum_counts, dim3(1), dim3(kBlock), 0, s, d, R, R.cnt_src, 0);
   cur ^= 1;
   for (int shift = 0; shift < kbits; shift += 8) pass(shift);
   RbItems I;
@@ -1058,7 +1071,7 @@ static hipError_t launch_rebalance_round(hg_graph_s* g, InstDesc d, char* ws, hi
   // proposals by target block, approvals per target
   hipLaunchKernelGGL(k_rb_keys, dim3(grid), dim3(kBlock), 0, s, d, R, R.gord, 1, key[cur ^ 1],
                      val[cur ^ 1]);
-  hipLaunchKernelGGL(k_rb_sum_counts, dim3(1), dim3(kBlock), 0, s, d, R, R.cnt_tgt);
+  hipLaunchKernelGGL(k_rb_sum_counts, dim3(1), dim3(kBlock), 0, s, d, R, R.cnt_tgt, 1);
   cur ^= 1;
   for (int shift = 0; shift < kbits; shift += 8) pass(shift);
   I.key = key[cur];
@@ -1080,8 +1093,8 @@ static hipError_t launch_rebalance_round(hg_graph_s* g, InstDesc d, char* ws, hi
   S.n = n;
   S.k = k;
   S.err_flags = d.err_flags;
-  hipLaunchKernelGGL(k_apply_prefix, dim3(grid), dim3(kBlock), 0, s, S, (const long long*)R.best,
-                     d);
+  hipLaunchKernelGGL(k_apply_prefix, dim3(grid_of(n, kSeqTile)), dim3(kBlock), 0, s, S,
+                     (const long long*)R.best, d);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   RoundPlan plan;

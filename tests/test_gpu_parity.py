@@ -125,6 +125,12 @@ def test_load_pincounts_km1_gains(H, name, make):
     assert info["total_net_weight"] == int(inst.w.astype(np.int64).sum())
     deg = np.diff(vptr_o)
     assert info["max_degree"] == int(deg.max())
+    sizes = np.diff(inst.eptr)
+    assert info["max_net_size"] == int(sizes.max())
+    w = np.ones(inst.m, np.int64) if inst.w is None else inst.w.astype(np.int64)
+    inc_w = np.array([w[vnets_o[vptr_o[v]:vptr_o[v + 1]]].sum() for v in range(inst.n)])
+    assert info["max_incident_weight"] == int(inc_w.max())
+    assert info["heavy_vertices"] == int((inc_w > 255).sum())
     st = H.State(g, k, inst.part)
     H.hg_compute_pincounts(g, st)
     torch.cuda.synchronize()
