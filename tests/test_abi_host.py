@@ -88,3 +88,42 @@ def test_calls_on_null_handle_fail_cleanly(lib):
     assert lib.hg_max_block_weight(None, 2, 0.03) == -1
     lib.hg_free.argtypes = [vp]
     lib.hg_free(None)
+
+
+def test_next_row_sizes_and_null_handles(lib):
+    vp = ctypes.c_void_p
+    i32, i64, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    lib.hg_gain_cache_bytes.argtypes = [i32, i32]
+    lib.hg_gain_cache_bytes.restype = i64
+    # b and w(I) (2n int32, rounded up to whole quads) plus rows of k rounded up to 4
+    assert lib.hg_gain_cache_bytes(10, 8) == 4 * (20 + 10 * 8)
+    assert lib.hg_gain_cache_bytes(11, 7) == 4 * (24 + 11 * 8)
+    assert lib.hg_gain_cache_bytes(0, 8) == -1 and lib.hg_gain_cache_bytes(10, 1) == -1
+    lib.hg_moves_workspace_size.argtypes = [i32, i32, i32]
+    lib.hg_moves_workspace_size.restype = sz
+    assert lib.hg_moves_workspace_size(100, 100, 8) >= 16 * 100 * 8
+    assert lib.hg_moves_workspace_size(100, 100, 1) == 0
+    lib.hg_rebalance_workspace_size.argtypes = [i32, i32]
+    lib.hg_rebalance_workspace_size.restype = sz
+    assert lib.hg_rebalance_workspace_size(100, 8) >= lib.hg_gain_cache_bytes(100, 8)
+    assert lib.hg_rebalance_workspace_size(0, 8) == 0
+    assert lib.hg_rebalance_workspace_size(100, 300) == 0
+    lib.hg_contract_workspace_size.argtypes = [i32, i32, i64]
+    lib.hg_contract_workspace_size.restype = sz
+    assert lib.hg_contract_workspace_size(100, 50, 400) >= 4 * 400
+    assert lib.hg_contract_workspace_size(100, 50, 1 << 31) == 0
+    assert lib.hg_contract_workspace_size(0, 50, 400) == 0
+    # calls on a null graph handle fail before touching the device
+    lib.hg_gain_cache_init.argtypes = [vp] * 6
+    lib.hg_gain_cache_init.argtypes[1] = i32
+    lib.hg_gain_cache_init.restype = i32
+    assert lib.hg_gain_cache_init(None, 8, None, None, None, None) == -1
+    lib.hg_rebalance.argtypes = [vp, i32, i64, i32] + [vp] * 9 + [sz, vp]
+    lib.hg_rebalance.restype = i32
+    assert lib.hg_rebalance(None, 8, 10, 1, *([None] * 9), 0, None) == -1
+    lib.hg_contract.argtypes = [vp] * 9 + [sz, vp]
+    lib.hg_contract.restype = i32
+    assert lib.hg_contract(*([None] * 9), 0, None) == -1
+    lib.hg_move_gains.argtypes = [vp, i32, vp, vp, i32, vp, vp, vp, vp, sz, vp]
+    lib.hg_move_gains.restype = i32
+    assert lib.hg_move_gains(None, 8, None, None, 1, None, None, None, None, 0, None) == -1
