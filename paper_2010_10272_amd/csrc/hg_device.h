@@ -149,4 +149,18 @@ __device__ __forceinline__ long long pack_cand(int gain, int target) {
 __device__ __forceinline__ int cand_target(long long x) { return (int)(x & 0xffffffffLL); }
 __device__ __forceinline__ int cand_gain(long long x) { return (int)(x >> 32); }
 
+// The same pointer in the global address space.  Pointers that reach a
+// kernel inside a descriptor (rather than as a plain kernel argument) are
+// generic to the compiler, which then issues flat loads; global loads are the
+// plain vector-memory path.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* global_ptr(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+
+// Plain vector types for 8- and 16-byte global loads (the HIP vector structs
+// cannot be copied out of another address space).
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
 }  // namespace hg

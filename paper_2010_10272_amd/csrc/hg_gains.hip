@@ -57,12 +57,13 @@ __global__ __launch_bounds__(kBlock) void k_gains_light(Launch L, long long* __r
     bool cut[kUnroll];
     int e[kUnroll];
 #pragma unroll
-    for (int q = 0; q < kUnroll; ++q) e[q] = j + q < b1 ? D.vnets[j + q] : -1;
+    for (int q = 0; q < kUnroll; ++q) e[q] = global_ptr(D.vnets)[j + q < b1 ? j + q : j];
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q)
+      read_net<WK, VIEW>(D.netstate, D.rw, D.view_ptr, e[q], aw, w[q], cut[q], Lb[q], S[q]);
 #pragma unroll
     for (int q = 0; q < kUnroll; ++q) {
-      if (e[q] >= 0) {
-        read_net<WK, VIEW>(D.netstate, D.rw, D.view_ptr, e[q], aw, w[q], cut[q], Lb[q], S[q]);
-      } else {
+      if (j + q >= b1) {             // past the row end: a repeated slot, masked
         w[q] = 0;
         S[q] = 0;
 #pragma unroll

@@ -150,18 +150,21 @@ __global__ __launch_bounds__(kBlock) void k_select_light(Launch L) {
     const int aw = a >> 5;
     const unsigned abit = 1u << (a & 31);
     // Software-pipelined sweep: issue kUnroll independent record gathers
-    // before consuming any of them.
+    // before consuming any of them.  Slots past the row end load the row's
+    // first entry again (always valid) and are masked afterwards, so no load
+    // sits in a branch of its own.
     for (long long j = b0; j < b1 && !heavy; j += kUnroll) {
       unsigned w[kUnroll], S[kUnroll], Lb[kUnroll][WK];
       bool cut[kUnroll];
       int e[kUnroll];
 #pragma unroll
-      for (int q = 0; q < kUnroll; ++q) e[q] = j + q < b1 ? vnets[j + q] : -1;
+      for (int q = 0; q < kUnroll; ++q) e[q] = global_ptr(vnets)[j + q < b1 ? j + q : j];
+#pragma unroll
+      for (int q = 0; q < kUnroll; ++q)
+        read_net<WK, VIEW>(netstate, rw, view, e[q], aw, w[q], cut[q], Lb[q], S[q]);
 #pragma unroll
       for (int q = 0; q < kUnroll; ++q) {
-        if (e[q] >= 0) {
-          read_net<WK, VIEW>(netstate, rw, view, e[q], aw, w[q], cut[q], Lb[q], S[q]);
-        } else {
+        if (j + q >= b1) {
           w[q] = 0;
           cut[q] = false;
           S[q] = 0;

@@ -2,6 +2,7 @@
 // net, from either the full net record or the compact Lambda/S view.
 #pragma once
 
+#include "hg_device.h"
 #include "hg_internal.h"
 
 namespace hg {
@@ -16,27 +17,27 @@ __device__ __forceinline__ void read_net(const unsigned* __restrict__ netstate, 
                                          const unsigned* __restrict__ view, int e, int aw,
                                          unsigned& w, bool& cut, unsigned (&L)[WK], unsigned& S) {
   if constexpr (VIEW == kView16) {
-    const unsigned x = view[e];
+    const unsigned x = global_ptr(view)[e];
     L[0] = x & 0xffffu;
     S = x >> 16;
     w = 1;
     cut = __popc(L[0]) > 1;
   } else if constexpr (VIEW == kView32) {
-    const uint2 x = reinterpret_cast<const uint2*>(view)[e];
+    const u32x2 x = global_ptr(reinterpret_cast<const u32x2*>(view))[e];
     L[0] = x.x;
     S = x.y;
     w = 1;
     cut = __popc(L[0]) > 1;
   } else if constexpr (VIEW == kView64) {
-    const uint4 x = reinterpret_cast<const uint4*>(view)[e];
+    const u32x4 x = global_ptr(reinterpret_cast<const u32x4*>(view))[e];
     L[0] = x.x;
     L[1] = x.y;
     S = aw ? x.w : x.z;
     w = 1;
     cut = __popc(x.x) + __popc(x.y) > 1;
   } else {
-    const unsigned* r = netstate + (long long)e * rw;
-    const uint4 q = *reinterpret_cast<const uint4*>(r);
+    const auto r = global_ptr(netstate + (long long)e * rw);
+    const u32x4 q = *global_ptr(reinterpret_cast<const u32x4*>(netstate + (long long)e * rw));
     w = q.x;
     cut = q.y > 1u;
     L[0] = q.z;
