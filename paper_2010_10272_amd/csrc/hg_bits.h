@@ -46,6 +46,21 @@ struct BitCounters {
     }
   }
 
+  // counter_i += 1 for every i in mask: one ripple-carry pass, no weight
+  // bits to test (unit net weights).
+  __device__ __forceinline__ void add_one(const unsigned (&mask)[WK]) {
+#pragma unroll
+    for (int w = 0; w < WK; ++w) {
+      unsigned carry = mask[w];
+#pragma unroll
+      for (int p = 0; p < kPlanes; ++p) {
+        const unsigned t = c[p][w] & carry;
+        c[p][w] ^= carry;
+        carry = t;
+      }
+    }
+  }
+
   // Blocks with a non-zero counter.
   __device__ __forceinline__ void nonzero(unsigned (&out)[WK]) const {
 #pragma unroll

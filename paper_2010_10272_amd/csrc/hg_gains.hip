@@ -77,8 +77,13 @@ __global__ __launch_bounds__(kBlock) void k_gains_light(Launch L, long long* __r
     }
     if (tot > kLightLimit) return;                  // heavy: other kernel
 #pragma unroll
-    for (int q = 0; q < kUnroll; ++q)
-      if (w[q]) C.add(Lb[q], w[q]);
+    for (int q = 0; q < kUnroll; ++q) {
+      if constexpr (VIEW != kViewFull) {
+        C.add_one(Lb[q]);                 // unit nets (masked slots add nothing)
+      } else if (w[q]) {
+        C.add(Lb[q], w[q]);
+      }
+    }
   }
   if (cache) {
     const long long n = D.n;

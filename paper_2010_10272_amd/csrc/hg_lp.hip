@@ -183,8 +183,13 @@ __global__ __launch_bounds__(kBlock) void k_select_light(Launch L) {
         break;
       }
 #pragma unroll
-      for (int q = 0; q < kUnroll; ++q)
-        if (w[q]) C.add(Lb[q], w[q]);
+      for (int q = 0; q < kUnroll; ++q) {
+        if constexpr (VIEW != kViewFull) {
+          C.add_one(Lb[q]);               // unit nets (masked slots add nothing)
+        } else if (w[q]) {
+          C.add(Lb[q], w[q]);
+        }
+      }
     }
     if (heavy) continue;
     D.eligible[u] = 0;
