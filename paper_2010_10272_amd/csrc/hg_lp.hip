@@ -152,19 +152,23 @@ __global__ __launch_bounds__(kBlock) void k_select_light(Launch L) {
     // Software-pipelined sweep: issue kUnroll independent record gathers
     // before consuming any of them.  Slots past the row end load the row's
     // first entry again (always valid) and are masked afterwards, so no load
-    // sits in a branch of its own.
-    for (long long j = b0; j < b1 && !heavy; j += kUnroll) {
+    // sits in a branch of its own.  With unit nets w(I(u)) is the degree,
+    // which the row length already bounds, so only weighted nets are
+    // watched for the heavy limit.
+    const int deg = (int)(b1 - b0);
+    const auto row = global_ptr(vnets + b0);
+    for (int jj = 0; jj < deg; jj += kUnroll) {
       unsigned w[kUnroll], S[kUnroll], Lb[kUnroll][WK];
       bool cut[kUnroll];
       int e[kUnroll];
 #pragma unroll
-      for (int q = 0; q < kUnroll; ++q) e[q] = global_ptr(vnets)[j + q < b1 ? j + q : j];
+      for (int q = 0; q < kUnroll; ++q) e[q] = row[jj + q < deg ? jj + q : jj];
 #pragma unroll
       for (int q = 0; q < kUnroll; ++q)
         read_net<WK, VIEW>(netstate, rw, view, e[q], aw, w[q], cut[q], Lb[q], S[q]);
 #pragma unroll
       for (int q = 0; q < kUnroll; ++q) {
-        if (j + q >= b1) {
+        if (jj + q >= deg) {
           w[q] = 0;
           cut[q] = false;
           S[q] = 0;
@@ -174,13 +178,16 @@ __global__ __launch_bounds__(kBlock) void k_select_light(Launch L) {
       }
 #pragma unroll
       for (int q = 0; q < kUnroll; ++q) {
-        tot += (int)w[q];
         bnd |= cut[q];
         if (S[q] & abit) ben += (int)w[q];
       }
-      if (tot > kLightLimit) {
-        heavy = true;
-        break;
+      if constexpr (VIEW == kViewFull) {
+#pragma unroll
+        for (int q = 0; q < kUnroll; ++q) tot += (int)w[q];
+        if (tot > kLightLimit) {
+          heavy = true;
+          break;
+        }
       }
 #pragma unroll
       for (int q = 0; q < kUnroll; ++q) {
@@ -191,6 +198,7 @@ __global__ __launch_bounds__(kBlock) void k_select_light(Launch L) {
         }
       }
     }
+    if constexpr (VIEW != kViewFull) tot = deg;
     if (heavy) continue;
     D.eligible[u] = 0;
     n_elig += 1;
