@@ -1037,7 +1037,18 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Launch L) {
       if (D.cache) {
         cache_net_delta<G>(D, e, wk, gl, old_word, nb.word, b, t);
       } else {
-        for (long long p = b + gl; p < t; p += G) D.eligible[D.pins[p]] = 1;
+        // every pin eligible; four pin loads in flight before the stores
+        for (long long p0 = b + gl; p0 < t; p0 += 4 * G) {
+          int v[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const long long p = p0 + r * G;
+            v[r] = D.pins[p < t ? p : p0];
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (p0 + r * G < t) D.eligible[v[r]] = 1;
+        }
       }
     }
     __syncthreads();

@@ -32,9 +32,11 @@ __device__ __forceinline__ NetBits net_bits(int k, int gl, Get get, Put put) {
 #pragma unroll
   for (int c = 0; c < kMaxChunks; ++c) {
     const int i = c * G + gl;
-    cvs[c] = 0;
-    if (c < nchunks && i < k) cvs[c] = get(i);
+    cvs[c] = get(i < k ? i : k - 1);   // unconditional, so the loads overlap
   }
+#pragma unroll
+  for (int c = 0; c < kMaxChunks; ++c)
+    if (!(c < nchunks && c * G + gl < k)) cvs[c] = 0;
   for (int c = 0; c < nchunks; ++c) {
     int i = c * G + gl;
     int cv = 0;
