@@ -217,9 +217,11 @@ __global__ __launch_bounds__(kBlock) void k_seq_gains(Seq S, long long* gains) {
   for_incidences(S, t, [&](int j, int, int a, int b, int e) {
     const int J = j + 1;
     const size_t ca = (size_t)e * S.k + a, cb = (size_t)e * S.k + b;
+    // all four reads first (no short-circuit: loads in branches would not overlap)
     const int4 A = S.cell[ca], B = S.cell[cb];
-    const bool last_out = S.phi[ca] - A.z == 0 && A.x == J && A.y > J;
-    const bool first_in = S.phi[cb] - B.z == 0 && B.y == J && B.x < J;
+    const int pa = S.phi[ca], pb = S.phi[cb];
+    const bool last_out = (pa - A.z == 0) & (A.x == J) & (A.y > J);
+    const bool first_in = (pb - B.z == 0) & (B.y == J) & (B.x < J);
     if (last_out != first_in) {
       const long long w = S.ewgt ? S.ewgt[e] : 1;
       atomicAdd((unsigned long long*)&s_gain[j - blockIdx.x * kSeqTile],
