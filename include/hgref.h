@@ -183,9 +183,12 @@ hg_status hg_km1(hg_graph g, int32_t k, const uint32_t* netstate, int64_t* km1_o
  *   b(u)   = w({e in I(u) : Phi(e, Pi(u)) = 1})
  *   p_i(u) = w({e in I(u) : Phi(e, i) = 0})
  *   gains[u*k + i] = b(u) - p_i(u) for i != Pi(u), and 0 for i = Pi(u)
+ *   gains is int64[n*k], row-major (vertex-major), 16-byte aligned
+ *   (HG_ERR_INVALID otherwise)
  *   benefit[u] = b(u) (int64[n], may be NULL)
  * part and netstate must describe the same partition (hg_compute_pincounts
- * or a sequence of hg_lp_round calls establishes that). */
+ * or a sequence of hg_lp_round calls establishes that).  Rows are written
+ * with streaming (nontemporal) stores. */
 hg_status hg_gains(hg_graph g, int32_t k, const int32_t* part, const uint32_t* netstate,
                    int64_t* gains, int64_t* benefit, void* stream);
 

@@ -360,6 +360,7 @@ hg_status hg_gains(hg_graph g, int32_t k, const int32_t* part, const uint32_t* n
   if (st != HG_OK) return st;
   if (!part || !netstate || !gains)
     return fail(HG_ERR_INVALID, "part, netstate and gains must be non-NULL");
+  if (((uintptr_t)gains & 15) != 0) return fail(HG_ERR_INVALID, "gains must be 16-byte aligned");
   hg::InstDesc d = hg::make_desc(g, k, 0, (int*)part, nullptr, (unsigned*)netstate, nullptr,
                                  nullptr, nullptr, nullptr, nullptr);
   HG_TRY(hg::launch_gains(g, d, (long long*)gains, (long long*)benefit, (hipStream_t)stream),

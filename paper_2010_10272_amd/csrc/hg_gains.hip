@@ -21,10 +21,53 @@ namespace hg {
 // own block), laid out as cache_pbase / cache_stride say.  With only_over
 // set, only vertices of blocks heavier than L_max are filled (the rows the
 // rebalancer reads).
+// Staged output of a wavefront's gain rows (k a multiple of S): the lanes
+// put S gains of their own rows into LDS, then write them out as 64 rows of
+// S * 8 contiguous bytes, S / 2 lanes per row, so that every store covers
+// whole cache lines (S = 16: one line) instead of touching 64 rows at once.
+// The stores are nontemporal: the rows are not read again by this pass.
+constexpr int kStageMax = 16;
+typedef long long i64x2 __attribute__((ext_vector_type(2)));
+
+template <int S, int WK>
+__device__ __forceinline__ void write_rows_staged(long long (*stage)[kStageMax + 1],
+                                                  long long* __restrict__ gains, int k,
+                                                  long long row0, unsigned long long mine,
+                                                  bool have, int a, long long base,
+                                                  const BitCounters<WK>& C) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int w = 0; w < WK; ++w) {
+#pragma unroll
+    for (int h = 0; h < 32; h += S) {
+      const int c0 = w * 32 + h;
+      if (c0 >= k) break;                              // k is a multiple of S
+      if (have) {
+#pragma unroll
+        for (int x = 0; x < S; ++x) stage[lane][x] = c0 + x == a ? 0 : base + C.value(w, h + x);
+      }
+      wave_lds_sync();
+#pragma unroll
+      for (int p0 = 0; p0 < S / 2; ++p0) {
+        const int p = p0 * kWave + lane;
+        const int r = p / (S / 2), piece = p % (S / 2);
+        if ((mine >> r) & 1ull) {
+          const i64x2 v = {stage[r][2 * piece], stage[r][2 * piece + 1]};
+          __builtin_nontemporal_store(
+              v, reinterpret_cast<i64x2*>(gains + (row0 + r) * k + c0 + 2 * piece));
+        }
+      }
+      wave_lds_sync();
+    }
+  }
+}
+
 template <int WK, int VIEW>
 __global__ __launch_bounds__(kBlock) void k_gains_light(Launch L, long long* __restrict__ gains,
                                                         long long* __restrict__ benefit,
                                                         int* __restrict__ cache, int only_over) {
+  // rows of a multiple of 8 blocks leave through LDS (write_rows_staged)
+  __shared__ long long s_stage[kBlock / kWave][kWave][kStageMax + 1];
   WorkItem fb;
   fb.inst = 0;
   fb.first = (int)xcd_remap(blockIdx.x, gridDim.x);
@@ -34,58 +77,75 @@ __global__ __launch_bounds__(kBlock) void k_gains_light(Launch L, long long* __r
   const InstDesc D = inst_desc(L, wi.inst);
   const int k = D.k;
   const long long u = (long long)wi.first * kBlock + threadIdx.x;
-  if (u >= D.n) return;
-  const int a = D.part[u];
-  long long* row = gains + u * k;
-  if ((unsigned)a >= (unsigned)k) {
-    atomicOr(D.err_flags, kErrPart);
-    if (cache) return;
-    for (int i = 0; i < k; ++i) row[i] = 0;
-    if (benefit) benefit[u] = 0;
-    return;
-  }
-  if (only_over && D.block_w[a] <= D.lmax) return;
-  const long long b0 = D.vptr[u], b1 = D.vptr[u + 1];
-  if (b1 - b0 > kLightLimit) return;                 // heavy: other kernel
+  const bool staged = !cache && gains && k % 8 == 0;
+  // 0: nothing to write here (out of range, heavy, or not asked for);
+  // 1: this lane's row is computed
+  bool done = false, have = false;
+  int a = 0, tot = 0, ben = 0;
   BitCounters<WK> C;
   C.clear();
-  int tot = 0, ben = 0;
-  const int aw = a >> 5;
-  const unsigned abit = 1u << (a & 31);
-  for (long long j = b0; j < b1; j += kUnroll) {
-    unsigned w[kUnroll], S[kUnroll], Lb[kUnroll][WK];
-    bool cut[kUnroll];
-    int e[kUnroll];
-#pragma unroll
-    for (int q = 0; q < kUnroll; ++q) e[q] = global_ptr(D.vnets)[j + q < b1 ? j + q : j];
-#pragma unroll
-    for (int q = 0; q < kUnroll; ++q)
-      read_net<WK, VIEW>(D.netstate, D.rw, D.view_ptr, e[q], aw, w[q], cut[q], Lb[q], S[q]);
-#pragma unroll
-    for (int q = 0; q < kUnroll; ++q) {
-      if (j + q >= b1) {             // past the row end: a repeated slot, masked
-        w[q] = 0;
-        S[q] = 0;
-#pragma unroll
-        for (int x = 0; x < WK; ++x) Lb[q][x] = 0;
+  if (u < D.n) {
+    a = D.part[u];
+    if ((unsigned)a >= (unsigned)k) {
+      atomicOr(D.err_flags, kErrPart);
+      if (!cache) {
+        long long* row = gains + u * k;
+        for (int i = 0; i < k; ++i) row[i] = 0;
+        if (benefit) benefit[u] = 0;
       }
+      done = true;
+    } else if (only_over && D.block_w[a] <= D.lmax) {
+      done = true;
     }
+  } else {
+    done = true;
+  }
+  if (!done) {
+    const long long b0 = D.vptr[u], b1 = D.vptr[u + 1];
+    if (b1 - b0 <= kLightLimit) {                    // longer rows: the heavy kernel
+      const int aw = a >> 5;
+      const unsigned abit = 1u << (a & 31);
+      bool heavy = false;
+      for (long long j = b0; j < b1 && !heavy; j += kUnroll) {
+        unsigned w[kUnroll], S[kUnroll], Lb[kUnroll][WK];
+        bool cut[kUnroll];
+        int e[kUnroll];
 #pragma unroll
-    for (int q = 0; q < kUnroll; ++q) {
-      tot += (int)w[q];
-      if (S[q] & abit) ben += (int)w[q];
-    }
-    if (tot > kLightLimit) return;                  // heavy: other kernel
+        for (int q = 0; q < kUnroll; ++q) e[q] = global_ptr(D.vnets)[j + q < b1 ? j + q : j];
 #pragma unroll
-    for (int q = 0; q < kUnroll; ++q) {
-      if constexpr (VIEW != kViewFull) {
-        C.add_one(Lb[q]);                 // unit nets (masked slots add nothing)
-      } else if (w[q]) {
-        C.add(Lb[q], w[q]);
+        for (int q = 0; q < kUnroll; ++q)
+          read_net<WK, VIEW>(D.netstate, D.rw, D.view_ptr, e[q], aw, w[q], cut[q], Lb[q], S[q]);
+#pragma unroll
+        for (int q = 0; q < kUnroll; ++q) {
+          if (j + q >= b1) {             // past the row end: a repeated slot, masked
+            w[q] = 0;
+            S[q] = 0;
+#pragma unroll
+            for (int x = 0; x < WK; ++x) Lb[q][x] = 0;
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < kUnroll; ++q) {
+          tot += (int)w[q];
+          if (S[q] & abit) ben += (int)w[q];
+        }
+        if (tot > kLightLimit) {
+          heavy = true;                   // heavier rows: the heavy kernel
+          break;
+        }
+#pragma unroll
+        for (int q = 0; q < kUnroll; ++q) {
+          if constexpr (VIEW != kViewFull) {
+            C.add_one(Lb[q]);             // unit nets (masked slots add nothing)
+          } else if (w[q]) {
+            C.add(Lb[q], w[q]);
+          }
+        }
       }
+      have = !heavy;
     }
   }
-  if (cache) {
+  if (have && cache) {
     const long long n = D.n;
     cache[u] = ben;
     cache[n + u] = tot;
@@ -97,29 +157,43 @@ __global__ __launch_bounds__(kBlock) void k_gains_light(Launch L, long long* __r
         if (i >= k) break;
         prow[i] = tot - (int)C.value(w, b);
       }
-    return;
   }
+  if (cache) return;
   const long long base = (long long)ben - tot;
+  if (have && benefit) benefit[u] = ben;
+  if (!staged) {
+    if (!have) return;
+    long long* row = gains + u * k;
 #pragma unroll
-  for (int w = 0; w < WK; ++w) {
-    for (int b = 0; b < 32; b += 2) {
-      const int i = w * 32 + b;
-      if (i >= k) break;
-      long long g0 = i == a ? 0 : base + C.value(w, b);
-      if (i + 1 < k) {
-        long long g1 = i + 1 == a ? 0 : base + C.value(w, b + 1);
-        if ((k & 1) == 0) {
-          *reinterpret_cast<longlong2*>(row + i) = make_longlong2(g0, g1);
+    for (int w = 0; w < WK; ++w) {
+      for (int b = 0; b < 32; b += 2) {
+        const int i = w * 32 + b;
+        if (i >= k) break;
+        long long g0 = i == a ? 0 : base + C.value(w, b);
+        if (i + 1 < k) {
+          long long g1 = i + 1 == a ? 0 : base + C.value(w, b + 1);
+          if ((k & 1) == 0) {
+            *reinterpret_cast<longlong2*>(row + i) = make_longlong2(g0, g1);
+          } else {
+            row[i] = g0;
+            row[i + 1] = g1;
+          }
         } else {
           row[i] = g0;
-          row[i + 1] = g1;
         }
-      } else {
-        row[i] = g0;
       }
     }
+    return;
   }
-  if (benefit) benefit[u] = ben;
+  // staged rows: every lane of the wavefront takes part, writing only the
+  // rows whose lane computed them
+  const unsigned long long mine = __ballot(have);
+  const long long row0 = u - lane_id();             // the wavefront's first vertex
+  long long(*stage)[kStageMax + 1] = s_stage[threadIdx.x / kWave];
+  if (k % 16 == 0)
+    write_rows_staged<16, WK>(stage, gains, k, row0, mine, have, a, base, C);
+  else
+    write_rows_staged<8, WK>(stage, gains, k, row0, mine, have, a, base, C);
 }
 
 // Unit: 4 consecutive heavy-list entries (one per wavefront).

@@ -296,6 +296,13 @@ def test_invalid_inputs_raise(H):
         H.State(g, 8, np.zeros(3, np.int32))
         H.hg_compute_pincounts(g, H.State(g, 8, np.zeros(3, np.int32)))
     assert ei.value.code == H.HG_ERR_WORKSPACE
+    ok = H.State(g, 2, np.array([0, 1, 1], np.int32))
+    H.hg_compute_pincounts(g, ok)
+    buf = torch.zeros(3 * 2 + 1, dtype=torch.int64, device="cuda")
+    with pytest.raises(H.HgError) as ei:                      # gains not 16-byte aligned
+        H.hg_gains(g, 2, ok.part, ok.netstate, gains=buf[1:])
+    assert ei.value.code == H.HG_ERR_INVALID
+    assert "aligned" in str(ei.value)
     st = H.State(g, 2, np.array([0, 5, 1], np.int32))         # partition id out of range
     H.hg_compute_pincounts(g, st)
     with pytest.raises(H.HgError) as ei:
