@@ -171,7 +171,7 @@ size_t build_plans(const std::vector<BatchMember>& mem, const std::vector<int>& 
     if (cp) {
       KindItems* p = variant(pc, (void*)pincount_kernel_g(G));
       add_split(*p, i, ceil_div(g->m, kBlock / G), S.count_chunks * G, home[i]);
-      p->lds = std::max(p->lds, sizeof(int) * (size_t)(kBlock / G) * k);
+      p->lds = std::max(p->lds, pincount_lds(G, k));
       add_split(verts, i, ceil_div(g->n, kBwChunk), 1, home[i]);
     }
     inst.flat.push_back(WorkItem{i, 0, 1, 1});

@@ -158,9 +158,12 @@ __device__ __forceinline__ const __attribute__((address_space(1))) T* global_ptr
   return (const __attribute__((address_space(1))) T*)p;
 }
 
-// Plain vector types for 8- and 16-byte global loads (the HIP vector structs
-// cannot be copied out of another address space).
+// Plain vector types for 8- and 16-byte global loads and nontemporal stores
+// (the HIP vector structs cannot be copied out of another address space, nor
+// passed to the nontemporal builtins).
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef long long i64x2 __attribute__((ext_vector_type(2)));
 
 }  // namespace hg

@@ -27,7 +27,6 @@ namespace hg {
 // whole cache lines (S = 16: one line) instead of touching 64 rows at once.
 // The stores are nontemporal: the rows are not read again by this pass.
 constexpr int kStageMax = 16;
-typedef long long i64x2 __attribute__((ext_vector_type(2)));
 
 template <int S, int WK>
 __device__ __forceinline__ void write_rows_staged(long long (*stage)[kStageMax + 1],

@@ -67,14 +67,6 @@ __device__ __forceinline__ NetBits net_bits(int k, int gl, Get get, Put put) {
   return r;
 }
 
-// Pin counts of one net already in LDS (cnt[0..k)); writes the Phi row.
-template <int G>
-__device__ __forceinline__ void netbits_from_counts(const int* cnt, int k, int gl, NetBits& b,
-                                                    int* phi_row) {
-  b = net_bits<G>(k, gl, [&](int i) { return cnt[i]; },
-                  [&](int i, int v) { phi_row[i] = v; });
-}
-
 // Write a whole record (w in word 0, zero padding); needs G >= record words,
 // which holds for the group sizes chosen per k (G >= 4 = words for k <= 32,
 // G = 64 >= 32 words otherwise).

@@ -30,8 +30,14 @@ __device__ __forceinline__ WorkItem contiguous_units(long long units) {
   return w;
 }
 
+// Pin slots per lane and pass: the pin loads of kCountSlots * G pins, then
+// their block-id loads, are in flight together (the sweep is bound by their
+// latency); slots past the net's end repeat its first pin and are masked.
+constexpr int kCountSlots = 4;
+
 // Unit: kBlock/G consecutive nets (one per group).  G lanes per net (G
-// divides 64); LDS counters: (kBlock/G) groups x k ints.
+// divides 64, G >= the record words); LDS counters: (kBlock/G) groups x k
+// ints.
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_pincounts(Launch L) {
   extern __shared__ int s_cnt[];   // [kBlock/G][k]
@@ -44,26 +50,44 @@ __global__ __launch_bounds__(kBlock) void k_pincounts(Launch L) {
   const int gl = threadIdx.x % G;
   const int k = D.k, m = D.m, rw = D.rw;
   int* cnt = s_cnt + grp * k;
+  // Phi rows leave as 16-byte streaming stores when rows are 16-byte aligned
+  const bool vec_phi = (k & 3) == 0 && ((uintptr_t)D.phi & 15) == 0;
   long long km1_local = 0;
   int err = 0;
   for (int it = 0; it < wi.count; ++it) {
     const long long e = ((long long)wi.first + (long long)it * wi.stride) * kGroups + grp;
+    long long b = 0, t = 0;
     if (e < m) {
+      b = D.eptr[e];
+      t = D.eptr[e + 1];
       for (int i = gl; i < k; i += G) cnt[i] = 0;
     }
     wave_lds_sync();
-    if (e < m) {
-      const long long b = D.eptr[e], t = D.eptr[e + 1];
-      for (long long p = b + gl; p < t; p += G) {
-        const int blk = D.part[D.pins[p]];
-        if ((unsigned)blk < (unsigned)k) atomicAdd(&cnt[blk], 1);
-        else err = kErrPart;
+    for (long long p0 = b + gl; p0 < t; p0 += kCountSlots * G) {
+      int v[kCountSlots];
+#pragma unroll
+      for (int q = 0; q < kCountSlots; ++q) v[q] = D.pins[p0 + q * G < t ? p0 + q * G : p0];
+#pragma unroll
+      for (int q = 0; q < kCountSlots; ++q) v[q] = D.part[v[q]];
+#pragma unroll
+      for (int q = 0; q < kCountSlots; ++q) {
+        if (p0 + q * G < t) {
+          if ((unsigned)v[q] < (unsigned)k) atomicAdd(&cnt[v[q]], 1);
+          else err = kErrPart;
+        }
       }
     }
     wave_lds_sync();
     if (e < m) {
-      NetBits bits;
-      netbits_from_counts<G>(cnt, k, gl, bits, D.phi + e * (long long)k);
+      const NetBits bits = net_bits<G>(k, gl, [&](int i) { return cnt[i]; }, [](int, int) {});
+      int* phi_row = D.phi + e * (long long)k;
+      if (vec_phi) {
+        for (int i = gl; i < (k >> 2); i += G)
+          __builtin_nontemporal_store(reinterpret_cast<const i32x4*>(cnt)[i],
+                                      reinterpret_cast<i32x4*>(phi_row) + i);
+      } else {
+        for (int i = gl; i < k; i += G) phi_row[i] = cnt[i];
+      }
       const int w = D.ewgt ? D.ewgt[e] : 1;
       write_netrec(D.netstate + e * (long long)rw, gl, w, bits, k);
       if (D.view != kViewFull) {
@@ -168,7 +192,17 @@ int group_lanes(int k) {
   return 32;
 }
 
-GroupKernel pincount_kernel(int k) { return pincount_kernel_g(group_lanes(k)); }
+// Lanes per net of the single-instance pin count: 8 (4 for k <= 4), more
+// only where the net record needs them.  Fewer lanes per net than the other
+// net sweeps use: more nets' loads in flight per wavefront.
+static int count_lanes(int k) {
+  if (k <= 4) return 4;
+  return net_words(k) > 8 ? net_words(k) : 8;
+}
+
+size_t pincount_lds(int G, int k) { return sizeof(int) * (size_t)(kBlock / G) * k; }
+
+GroupKernel pincount_kernel(int k) { return pincount_kernel_g(count_lanes(k)); }
 
 GroupKernel pincount_kernel_g(int G) {
   switch (G) {
@@ -184,8 +218,8 @@ void single_count_plan(const InstDesc& d, CountPlan& plan) {
   const Launch L = single_launch(d);
   PlanLaunch pc;
   pc.kernel = (void*)pincount_kernel(d.k);
-  pc.grid = grid_cap(d.m, kBlock / group_lanes(d.k), kStateGrid);
-  pc.lds = sizeof(int) * (size_t)(kBlock / group_lanes(d.k)) * d.k;
+  pc.grid = grid_cap(d.m, kBlock / count_lanes(d.k), kStateGrid);
+  pc.lds = pincount_lds(count_lanes(d.k), d.k);
   pc.L = L;
   plan.pincounts.push_back(pc);
   plan.instances.grid = 1;
