@@ -335,7 +335,7 @@ typedef struct {
   int32_t count_chunks;      /* 256-net chunks per pin-count workgroup, 1..64    */
   int32_t net_lanes;         /* lanes per net in the pin-count and finalize
                                 sweeps: 0 = the minimum for k (4 for k <= 4, 8
-                                for k <= 8, 16 for k <= 128, else 32), or 4, 8,
+                                for k <= 64, 16 for k <= 128, else 32), or 4, 8,
                                 16, 32 (raised to that minimum)                  */
 } hg_schedule;
 

@@ -44,7 +44,7 @@ constexpr int kBwChunk = kBlock * 16;   // vertices per unit of the block-weight
 SelectKernel select_kernel(int k, int view);
 FinalizeKernel finalize_kernel(int k);       // lanes per net: group_lanes(k)
 FinalizeKernel finalize_kernel_g(int G);     // G lanes per net (4, 8, 16 or 32)
-GroupKernel pincount_kernel(int k);          // single instance: its own lanes per net
+GroupKernel pincount_kernel(int k);          // lanes per net: group_lanes(k)
 GroupKernel pincount_kernel_g(int G);        // G lanes per net (4, 8, 16 or 32)
 size_t pincount_lds(int G, int k);           // its dynamic LDS bytes
 GainsKernel gains_kernel(int k, int view);

@@ -1028,7 +1028,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Launch L) {
       }
       // gain cache: the record's Lambda / S words before this round
       const unsigned old_word = D.cache && gl >= 2 && gl < 2 + 2 * wk ? rec[gl] : 0u;
-      NetBits nb = net_bits<G>(k, gl, [&](int i2) { return row[i2]; }, [&](int, int) {});
+      NetBits nb = net_bits<G>(k, gl, [&](int i2) { return row[i2]; });
       if (gl >= 1 && gl < 2 + 2 * wk) rec[gl] = nb.word;
       if (D.view != kViewFull) write_view(D.view_ptr, e, D.view, gl, nb);
       if (gl == 1) dcheck += (long long)(lam_old - nb.lambda) * w;

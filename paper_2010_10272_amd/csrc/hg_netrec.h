@@ -16,9 +16,11 @@ struct NetBits {
   unsigned word;   // record word with index = lane-in-group (valid for 1 <= gl < 2+2W)
 };
 
-// get(i) -> Phi(e,i); put(i, v) stores it (or does nothing).
-template <int G, typename Get, typename Put>
-__device__ __forceinline__ NetBits net_bits(int k, int gl, Get get, Put put) {
+// get(i) -> Phi(e,i).  The first MC chunks' counts are loaded up front,
+// unconditionally (indices past k clamped, values masked), so that their
+// loads are in flight together; further chunks are read one at a time.
+template <int G, int MC, typename Get>
+__device__ __forceinline__ NetBits net_bits_mc(int k, int gl, Get get) {
   const int wk = bit_words(k);
   const int shift = (G == kWave) ? 0 : (lane_id() / G) * G;
   const unsigned long long gmask = (G == kWave) ? ~0ull : ((1ull << (G % kWave)) - 1);
@@ -26,28 +28,25 @@ __device__ __forceinline__ NetBits net_bits(int k, int gl, Get get, Put put) {
   r.lambda = 0;
   r.word = 0;
   const int nchunks = (k + G - 1) / G;
-  // all counts first (independent loads in flight together), then the ballots
-  constexpr int kMaxChunks = (HG_MAX_K + G - 1) / G < 8 ? (HG_MAX_K + G - 1) / G : 8;
-  int cvs[kMaxChunks];
+  int cvs[MC];
 #pragma unroll
-  for (int c = 0; c < kMaxChunks; ++c) {
+  for (int c = 0; c < MC; ++c) {
     const int i = c * G + gl;
-    cvs[c] = get(i < k ? i : k - 1);   // unconditional, so the loads overlap
+    cvs[c] = get(i < k ? i : k - 1);
   }
 #pragma unroll
-  for (int c = 0; c < kMaxChunks; ++c)
+  for (int c = 0; c < MC; ++c)
     if (!(c < nchunks && c * G + gl < k)) cvs[c] = 0;
   for (int c = 0; c < nchunks; ++c) {
     int i = c * G + gl;
     int cv = 0;
-    if (c < kMaxChunks) {
+    if (c < MC) {
 #pragma unroll
-      for (int x = 0; x < kMaxChunks; ++x)
+      for (int x = 0; x < MC; ++x)
         if (x == c) cv = cvs[x];
     } else if (i < k) {
-      cv = get(i);                    // only when k needs more than kMaxChunks chunks
+      cv = get(i);
     }
-    if (i < k) put(i, cv);
     unsigned long long nz = (__ballot(cv > 0) >> shift) & gmask;
     unsigned long long one = (__ballot(cv == 1) >> shift) & gmask;
     r.lambda += __popcll(nz);
@@ -65,6 +64,18 @@ __device__ __forceinline__ NetBits net_bits(int k, int gl, Get get, Put put) {
   }
   if (gl == 1) r.word = (unsigned)r.lambda;
   return r;
+}
+
+// Record bits of one net with G lanes: as many up-front loads as k has
+// chunks of G blocks (1, 2, 4, or 8 and more).  k is the same for every lane
+// of the wavefront, so the branch does not diverge.
+template <int G, typename Get>
+__device__ __forceinline__ NetBits net_bits(int k, int gl, Get get) {
+  const int nchunks = (k + G - 1) / G;
+  if (nchunks <= 1) return net_bits_mc<G, 1>(k, gl, get);
+  if (nchunks <= 2) return net_bits_mc<G, 2>(k, gl, get);
+  if (nchunks <= 4) return net_bits_mc<G, 4>(k, gl, get);
+  return net_bits_mc<G, 8>(k, gl, get);
 }
 
 // Write a whole record (w in word 0, zero padding); needs G >= record words,

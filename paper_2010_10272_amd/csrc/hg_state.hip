@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kBlock) void k_pincounts(Launch L) {
     }
     wave_lds_sync();
     if (e < m) {
-      const NetBits bits = net_bits<G>(k, gl, [&](int i) { return cnt[i]; }, [](int, int) {});
+      const NetBits bits = net_bits<G>(k, gl, [&](int i) { return cnt[i]; });
       int* phi_row = D.phi + e * (long long)k;
       if (vec_phi) {
         for (int i = gl; i < (k >> 2); i += G)
@@ -182,27 +182,19 @@ static unsigned grid_cap(long long items, int per_block, int cap) {
   return (unsigned)b;
 }
 
-// Lanes per net for the net-centric sweeps: enough lanes to hold every word
-// of the net record (2 + 2 * bit_words(k), padded), few enough that a wave
-// works on several nets at once (most nets have only a handful of pins).
+// Lanes per net for the net-centric sweeps (pin counts, finalize): enough
+// lanes to hold every word of the net record (2 + 2 * bit_words(k), padded),
+// and no more than that (but 8 for 4 < k <= 64): most nets have only a
+// handful of pins, so narrower groups put more nets' loads in flight per
+// wavefront.
 int group_lanes(int k) {
-  if (k <= 4) return 4;
-  if (k <= 8) return 8;
-  if (k <= 128) return 16;
-  return 32;
-}
-
-// Lanes per net of the single-instance pin count: 8 (4 for k <= 4), more
-// only where the net record needs them.  Fewer lanes per net than the other
-// net sweeps use: more nets' loads in flight per wavefront.
-static int count_lanes(int k) {
   if (k <= 4) return 4;
   return net_words(k) > 8 ? net_words(k) : 8;
 }
 
 size_t pincount_lds(int G, int k) { return sizeof(int) * (size_t)(kBlock / G) * k; }
 
-GroupKernel pincount_kernel(int k) { return pincount_kernel_g(count_lanes(k)); }
+GroupKernel pincount_kernel(int k) { return pincount_kernel_g(group_lanes(k)); }
 
 GroupKernel pincount_kernel_g(int G) {
   switch (G) {
@@ -218,8 +210,8 @@ void single_count_plan(const InstDesc& d, CountPlan& plan) {
   const Launch L = single_launch(d);
   PlanLaunch pc;
   pc.kernel = (void*)pincount_kernel(d.k);
-  pc.grid = grid_cap(d.m, kBlock / count_lanes(d.k), kStateGrid);
-  pc.lds = pincount_lds(count_lanes(d.k), d.k);
+  pc.grid = grid_cap(d.m, kBlock / group_lanes(d.k), kStateGrid);
+  pc.lds = pincount_lds(group_lanes(d.k), d.k);
   pc.L = L;
   plan.pincounts.push_back(pc);
   plan.instances.grid = 1;
