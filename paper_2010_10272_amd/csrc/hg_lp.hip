@@ -1071,23 +1071,40 @@ __global__ __launch_bounds__(kBlock) void k_round_stats(Launch L) {
   const InstDesc D = inst_desc(L, wi.inst);
   RoundCounters* ctr = D.ctr;
   const int lane = lane_id(), wv = threadIdx.x / kWave;
-  for (int c = wv; c < kNumCounters; c += kBlock / kWave) {
-    long long v = (long long)ctr->slot[c][lane];
-    v = wave_sum(v);
-    if (lane == 0) s_sum[c] = v;
-    ctr->slot[c][lane] = 0;
+  // loads of the counter rows, and of the slot cells 16 at a time, are
+  // issued before the stores that clear them (not one round trip per cell)
+  constexpr int kRows = (kNumCounters + kBlock / kWave - 1) / (kBlock / kWave);
+  unsigned long long v[kRows];
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    const int c = wv + r * (kBlock / kWave);
+    v[r] = c < kNumCounters ? ctr->slot[c][lane] : 0ull;
   }
   long long mx = LLONG_MIN;
   for (int i = threadIdx.x; i < D.k; i += kBlock) {
-    long long d = 0;
-    for (int sl = 0; sl < kSlots; ++sl) {
-      long long* cell = D.bw_slots + (size_t)sl * D.k + i;
-      d += *cell;
-      *cell = 0;
+    long long* col = D.bw_slots + i;
+    const size_t ks = (size_t)D.k;
+    long long d = D.block_w[i];
+    for (int s0 = 0; s0 < kSlots; s0 += 16) {      // 16 loads in flight, then the clears
+      long long cells[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) cells[q] = col[(s0 + q) * ks];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) d += cells[q];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) col[(s0 + q) * ks] = 0;
     }
-    const long long W = D.block_w[i] + d;
-    D.block_w[i] = W;
-    mx = W > mx ? W : mx;
+    D.block_w[i] = d;
+    mx = d > mx ? d : mx;
+  }
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    const int c = wv + r * (kBlock / kWave);
+    if (c < kNumCounters) {
+      const long long sum = wave_sum((long long)v[r]);
+      if (lane == 0) s_sum[c] = sum;
+      ctr->slot[c][lane] = 0;
+    }
   }
   mx = wave_max(mx);
   if (lane == 0) s_max[wv] = mx;
