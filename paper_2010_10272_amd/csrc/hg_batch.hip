@@ -158,7 +158,7 @@ size_t build_plans(const std::vector<BatchMember>& mem, const std::vector<int>& 
     if (rp) {
       add_split(*variant(sel, (void*)select_kernel(k, d.view)), i, ceil_div(g->n, kBlock),
                 S.select_chunks, home[i]);
-      add_split(*variant(fin, (void*)finalize_kernel_g(G)), i, ceil_div(g->m, kFinalChunk),
+      add_split(*variant(fin, (void*)finalize_kernel_g(G, false)), i, ceil_div(g->m, kFinalChunk),
                 S.finalize_chunks, home[i]);
       for (long long h = 0; h < ceil_div(g->info.heavy_count, kHeavyPerGroup); ++h)
         heavy.flat.push_back(WorkItem{i, (int)h, 1, 1});

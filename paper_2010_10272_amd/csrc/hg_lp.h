@@ -42,8 +42,10 @@ struct CountPlan {
 constexpr int kBwChunk = kBlock * 16;   // vertices per unit of the block-weight sweep
 
 SelectKernel select_kernel(int k, int view);
-FinalizeKernel finalize_kernel(int k);       // lanes per net: group_lanes(k)
-FinalizeKernel finalize_kernel_g(int G);     // G lanes per net (4, 8, 16 or 32)
+// lanes per net: group_lanes(k); cache: the variant that also applies the
+// gain-cache deltas (it must be used exactly when the descriptor has a cache)
+FinalizeKernel finalize_kernel(int k, bool cache);
+FinalizeKernel finalize_kernel_g(int G, bool cache);   // G lanes per net (4, 8, 16 or 32)
 GroupKernel pincount_kernel(int k);          // lanes per net: group_lanes(k)
 GroupKernel pincount_kernel_g(int G);        // G lanes per net (4, 8, 16 or 32)
 size_t pincount_lds(int G, int k);           // its dynamic LDS bytes

@@ -993,7 +993,7 @@ __device__ void cache_net_delta(const InstDesc& D, long long e, int wk, int gl, 
   }
 }
 
-template <int G>
+template <int G, bool CACHE>
 __global__ __launch_bounds__(kBlock) void k_finalize(Launch L) {
   __shared__ int s_list[kFinalChunk];
   __shared__ long long s_tmp[kBlock / kWave];
@@ -1027,14 +1027,14 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Launch L) {
         w = (int)rec[0];
       }
       // gain cache: the record's Lambda / S words before this round
-      const unsigned old_word = D.cache && gl >= 2 && gl < 2 + 2 * wk ? rec[gl] : 0u;
+      const unsigned old_word = CACHE && gl >= 2 && gl < 2 + 2 * wk ? rec[gl] : 0u;
       NetBits nb = net_bits<G>(k, gl, [&](int i2) { return row[i2]; });
       if (gl >= 1 && gl < 2 + 2 * wk) rec[gl] = nb.word;
       if (D.view != kViewFull) write_view(D.view_ptr, e, D.view, gl, nb);
       if (gl == 1) dcheck += (long long)(lam_old - nb.lambda) * w;
       if (gl == 0) D.touched[e] = 0;
       const long long b = D.eptr[e], t = D.eptr[e + 1];
-      if (D.cache) {
+      if constexpr (CACHE) {
         cache_net_delta<G>(D, e, wk, gl, old_word, nb.word, b, t);
       } else {
         // every pin eligible; four pin loads in flight before the stores
@@ -1150,14 +1150,16 @@ SelectKernel select_kernel(int k, int view) {
   }
 }
 
-FinalizeKernel finalize_kernel(int k) { return finalize_kernel_g(group_lanes(k)); }
+FinalizeKernel finalize_kernel(int k, bool cache) { return finalize_kernel_g(group_lanes(k), cache); }
 
-FinalizeKernel finalize_kernel_g(int G) {
+// The gain-cache update lives in its own instantiation: the plain one then
+// needs far fewer registers (more workgroups per compute unit).
+FinalizeKernel finalize_kernel_g(int G, bool cache) {
   switch (G) {
-    case 4: return k_finalize<4>;
-    case 8: return k_finalize<8>;
-    case 16: return k_finalize<16>;
-    default: return k_finalize<32>;
+    case 4: return cache ? k_finalize<4, true> : k_finalize<4, false>;
+    case 8: return cache ? k_finalize<8, true> : k_finalize<8, false>;
+    case 16: return cache ? k_finalize<16, true> : k_finalize<16, false>;
+    default: return cache ? k_finalize<32, true> : k_finalize<32, false>;
   }
 }
 
@@ -1235,7 +1237,7 @@ void single_round_plan(const InstDesc& d, RoundPlan& plan) {
   plan.approve.grid = (unsigned)(d.num_tiles + d.k);
   plan.approve.L = L;
   PlanLaunch fin;
-  fin.kernel = (void*)finalize_kernel(d.k);
+  fin.kernel = (void*)finalize_kernel(d.k, d.cache != nullptr);
   long long fchunks = ((long long)d.m + kFinalChunk - 1) / kFinalChunk;
   fin.grid = (unsigned)(fchunks < kFinalizeGrid ? fchunks : kFinalizeGrid);
   fin.L = L;
