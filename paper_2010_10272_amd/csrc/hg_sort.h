@@ -1,8 +1,9 @@
 // hg_sort.h -- stable LSD radix sort of (uint32 key, int32 value) pairs,
-// 8 bits per pass, for the move-sequence, rebalancing and contraction
-// kernels.  A pass is three launches: per-tile digit counts, a scan of each
-// digit's counts over the tiles, and a stable scatter.  Included by each
-// source file that sorts (the kernels have internal linkage there).
+// 8 bits per pass, for the loader, the move-sequence, rebalancing and
+// contraction kernels.  A pass is three launches: per-tile digit counts, a
+// scan of each digit's counts over the tiles, and a stable scatter.
+// Included by each source file that sorts (the kernels have internal
+// linkage there).
 #pragma once
 
 #include "hg_device.h"
@@ -11,7 +12,8 @@
 namespace hg {
 namespace {
 
-constexpr int kSortTile = kTile;            // items per radix-sort workgroup (4 per thread)
+constexpr int kSortTile = 4 * kTile;        // items per radix-sort workgroup (16 per thread)
+constexpr int kSortPer = kSortTile / kBlock;
 constexpr int kDigits = 256;                // 8-bit digits
 
 struct SortPass {
@@ -33,10 +35,15 @@ __global__ __launch_bounds__(kBlock) void k_sort_hist(SortPass P) {
   s_h[threadIdx.x] = 0;
   __syncthreads();
   const long long base = (long long)blockIdx.x * kSortTile;
-  for (int r = 0; r < kSortTile / kBlock; ++r) {
+  unsigned key[kSortPer];
+#pragma unroll
+  for (int r = 0; r < kSortPer; ++r) {
     const long long i = base + r * kBlock + threadIdx.x;
-    if (i < P.n) atomicAdd(&s_h[digit_of(P.key_in[i], P.shift)], 1u);
+    key[r] = i < P.n ? P.key_in[i] : 0u;
   }
+#pragma unroll
+  for (int r = 0; r < kSortPer; ++r)
+    if (base + r * kBlock + threadIdx.x < P.n) atomicAdd(&s_h[digit_of(key[r], P.shift)], 1u);
   __syncthreads();
   P.hist[(size_t)threadIdx.x * P.tiles + blockIdx.x] = s_h[threadIdx.x];
 }
@@ -57,32 +64,49 @@ __global__ __launch_bounds__(kBlock) void k_sort_scan(SortPass P) {
   if (threadIdx.x == 0) P.dtot[blockIdx.x] = (unsigned)carry;
 }
 
-// Stable scatter of one tile: items r*kBlock + threadIdx.x for r = 0..3 in
-// order; ranks among equal digits by wave ballots, waves and rounds in order.
+// Stable scatter of one tile.  The tile is first ranked into LDS in digit
+// order (items r*kBlock + threadIdx.x for r = 0..kSortPer-1 in order; ranks
+// among equal digits by wave ballots, waves and rounds in order), then
+// written out slot by slot, so that each digit's run of the tile leaves as
+// consecutive addresses instead of every store touching many runs.
 __global__ __launch_bounds__(kBlock) void k_sort_scatter(SortPass P) {
-  __shared__ unsigned s_base[kDigits];
+  __shared__ unsigned s_key[kSortTile];
+  __shared__ int s_val[kSortTile];
+  __shared__ unsigned s_run[kDigits];     // next LDS slot of each digit
+  __shared__ unsigned s_gofs[kDigits];    // output index of LDS slot 0 for each digit
   __shared__ unsigned s_wcnt[kBlock / kWave][kDigits];
   __shared__ long long s_tmp[kBlock / kWave];
-  // digit bases: digits below d in full, plus this digit in earlier tiles
-  long long tot;
-  const long long below = block_excl_scan64(P.dtot[threadIdx.x], s_tmp, &tot);
-  s_base[threadIdx.x] = (unsigned)below + P.hist[(size_t)threadIdx.x * P.tiles + blockIdx.x];
-  for (int w = 0; w < kBlock / kWave; ++w) s_wcnt[w][threadIdx.x] = 0;
+  const long long base = (long long)blockIdx.x * kSortTile;
+  // every item of the tile requested before the first wait
+  unsigned key[kSortPer];
+  int val[kSortPer];
+#pragma unroll
+  for (int r = 0; r < kSortPer; ++r) {
+    const long long i = base + r * kBlock + threadIdx.x;
+    key[r] = i < P.n ? P.key_in[i] : 0u;
+    val[r] = i < P.n ? P.val_in[i] : 0;
+  }
+  {
+    // digit d = threadIdx.x: its count in this tile is the difference of the
+    // scanned per-tile offsets; its LDS run starts after the smaller digits'
+    const int d = threadIdx.x;
+    const unsigned here = P.hist[(size_t)d * P.tiles + blockIdx.x];
+    const unsigned next =
+        (int)blockIdx.x + 1 < P.tiles ? P.hist[(size_t)d * P.tiles + blockIdx.x + 1] : P.dtot[d];
+    long long tot;
+    const long long below = block_excl_scan64(P.dtot[d], s_tmp, &tot);
+    const long long loff = block_excl_scan64(next - here, s_tmp, &tot);
+    s_run[d] = (unsigned)loff;
+    s_gofs[d] = (unsigned)(below + here - loff);   // modulo 2^32; slot + this is in range
+    for (int w = 0; w < kBlock / kWave; ++w) s_wcnt[w][d] = 0;
+  }
   __syncthreads();
   const int lane = lane_id(), wv = threadIdx.x / kWave;
   const unsigned long long lt = (1ull << lane) - 1ull;
-  const long long base = (long long)blockIdx.x * kSortTile;
-  for (int r = 0; r < kSortTile / kBlock; ++r) {
-    const long long i = base + r * kBlock + threadIdx.x;
-    const bool live = i < P.n;
-    unsigned key = 0;
-    int val = 0;
-    unsigned d = 0;
-    if (live) {
-      key = P.key_in[i];
-      val = P.val_in[i];
-      d = digit_of(key, P.shift);
-    }
+#pragma unroll
+  for (int r = 0; r < kSortPer; ++r) {
+    const bool live = base + r * kBlock + threadIdx.x < P.n;
+    const unsigned d = digit_of(key[r], P.shift);
     // lanes of this wave with the same digit
     unsigned long long peers = __ballot(live);
 #pragma unroll
@@ -94,10 +118,10 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(SortPass P) {
     if (live && rank == 0) s_wcnt[wv][d] = (unsigned)__popcll(peers);
     __syncthreads();
     if (live) {
-      unsigned pos = s_base[d] + rank;
-      for (int w = 0; w < wv; ++w) pos += s_wcnt[w][d];
-      P.key_out[pos] = key;
-      P.val_out[pos] = val;
+      unsigned slot = s_run[d] + rank;
+      for (int w = 0; w < wv; ++w) slot += s_wcnt[w][d];
+      s_key[slot] = key[r];
+      s_val[slot] = val[r];
     }
     __syncthreads();
     unsigned add = 0;
@@ -105,8 +129,16 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(SortPass P) {
       add += s_wcnt[w][threadIdx.x];
       s_wcnt[w][threadIdx.x] = 0;
     }
-    s_base[threadIdx.x] += add;
+    s_run[threadIdx.x] += add;
     __syncthreads();
+  }
+  const long long left = (long long)P.n - base;
+  const int count = left < kSortTile ? (int)left : kSortTile;
+  for (int j = threadIdx.x; j < count; j += kBlock) {
+    const unsigned k = s_key[j];
+    const unsigned pos = s_gofs[digit_of(k, P.shift)] + (unsigned)j;
+    P.key_out[pos] = k;
+    P.val_out[pos] = s_val[j];
   }
 }
 
