@@ -133,17 +133,27 @@ __global__ __launch_bounds__(kBlock) void k_block_weights(Launch L, int mark_eli
   for (int i = threadIdx.x; i < k; i += kBlock) s_w[i] = 0;
   __syncthreads();
   int err = 0;
+  constexpr int kPer = kBwChunk / kBlock;
   for (int it = 0; it < wi.count; ++it) {
     const long long base = ((long long)wi.first + (long long)it * wi.stride) * kBwChunk;
-    for (int j = 0; j < kBwChunk / kBlock; ++j) {
+    // every vertex's block and weight requested before the first wait
+    int blk[kPer], cw[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
       const long long v = base + (long long)j * kBlock + threadIdx.x;
-      if (v >= n) break;
-      const int blk = D.part[v];
-      if (mark_eligible) D.eligible[v] = 1;
-      if ((unsigned)blk < (unsigned)k)
-        atomicAdd(&s_w[blk], (unsigned long long)(D.vwgt ? D.vwgt[v] : 1));
-      else
-        err = kErrPart;
+      blk[j] = v < n ? D.part[v] : 0;
+      cw[j] = v < n && D.vwgt ? D.vwgt[v] : 1;
+    }
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const long long v = base + (long long)j * kBlock + threadIdx.x;
+      if (v < n) {
+        if (mark_eligible) D.eligible[v] = 1;
+        if ((unsigned)blk[j] < (unsigned)k)
+          atomicAdd(&s_w[blk[j]], (unsigned long long)cw[j]);
+        else
+          err = kErrPart;
+      }
     }
   }
   if (err) atomicOr(D.err_flags, err);
