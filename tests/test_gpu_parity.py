@@ -309,3 +309,33 @@ def test_invalid_inputs_raise(H):
         H.hg_sync_status(g)
     assert ei.value.code == H.HG_ERR_INVALID
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("k", [8, 64])
+def test_pincounts_and_rounds_with_unaligned_phi(H, k):
+    """Phi rows are written with 16-byte stores only when the buffer is
+    16-byte aligned; a buffer 4 bytes off takes the scalar path and must give
+    the same state and rounds."""
+    import torch
+    inst = synth.random_power_law(60 + k, 7000, 6500, k, hi=20, unit=False, rounds=3)
+    h = _oracle_hg(inst)
+    g = H.hg_load_csr(inst.n, inst.eptr, inst.pins, inst.c, inst.w, k_max=k)
+    sizes = H.state_sizes(g.n, g.m, k)
+    views = {f: torch.empty(cnt, dtype=dt, device="cuda") for f, (dt, cnt) in sizes.items()}
+    big = torch.empty(g.m * k + 4, dtype=torch.int32, device="cuda")
+    views["phi"] = big[1:1 + g.m * k]
+    assert views["phi"].data_ptr() % 16 == 4
+    st = H.State(g, k, inst.part, views=views)
+    H.hg_compute_pincounts(g, st)
+    torch.cuda.synchronize()
+    _check_state(H, g, st, h, k, inst.part)
+    L = H.hg_max_block_weight(g, k, inst.eps)
+    stats = torch.zeros(H.STATS_WORDS, dtype=torch.int64, device="cuda")
+    part_o, elig_o = inst.part.copy(), np.ones(inst.n, np.uint8)
+    for r in range(2):
+        H.hg_lp_round(g, st, L, stats)
+        torch.cuda.synchronize()
+        part_o, elig_o, _, st_o = O.lp_round(h, k, L, part_o, elig_o)
+        assert np.array_equal(st.part.cpu().numpy(), part_o), (k, r)
+        _check_state(H, g, st, h, k, part_o)
+    H.hg_sync_status(g)
