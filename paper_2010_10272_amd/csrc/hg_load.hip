@@ -192,9 +192,10 @@ hipError_t load_check(hg_graph_s* g, hipStream_t s) {
 // atomics anywhere (so nothing depends on timing).  Row starts come from
 // where the sorted keys change.
 
-// Each wave expands the pins of 64 consecutive nets, load-balanced.
-__global__ void k_pin_pairs(int m, const long long* eptr, const int* pins, unsigned* key,
-                            int* val) {
+// Each wave expands the pins of 64 consecutive nets, load-balanced, into the
+// net id of every pin position: the pairs' values (their keys are the pins
+// themselves, which the first sort pass reads in place).
+__global__ void k_pin_pairs(int m, const long long* eptr, int* val) {
   __shared__ int s_excl[kBlock / kWave][kWave];
   __shared__ long long s_begin[kBlock / kWave][kWave];
   const int w = threadIdx.x / kWave, lane = lane_id();
@@ -208,10 +209,7 @@ __global__ void k_pin_pairs(int m, const long long* eptr, const int* pins, unsig
   }
   const int first_net = (int)(wave_global * kWave);
   wave_expand(b, len, s_excl[w], s_begin[w], [&](bool act, int owner, long long p) {
-    if (act) {
-      key[p] = (unsigned)pins[p];
-      val[p] = first_net + owner;
-    }
+    if (act) val[p] = first_net + owner;
   });
 }
 
@@ -336,20 +334,22 @@ hipError_t load_build(hg_graph_s* g, hipStream_t s) {
   val[(passes & 1) ^ 1] = scratch;
   const long long waves = ((long long)g->m + kWave - 1) / kWave;
   const unsigned blocks = (unsigned)((waves + kBlock / kWave - 1) / (kBlock / kWave));
-  hipLaunchKernelGGL(k_pin_pairs, dim3(blocks), dim3(kBlock), 0, s, g->m, g->eptr, g->pins,
-                     key[0], val[0]);
+  hipLaunchKernelGGL(k_pin_pairs, dim3(blocks), dim3(kBlock), 0, s, g->m, g->eptr, val[0]);
   SortPass SP;
   SP.hist = (unsigned*)(g->ws + g->lay.lhist);
   SP.dtot = (unsigned*)(g->ws + g->lay.ldtot);
   SP.n = (int)P;
   SP.tiles = sort_tiles(P);
+  // the first pass reads the (validated, non-negative) pins as its keys
+  const unsigned* kin = (const unsigned*)g->pins;
   for (int q = 0; q < passes; ++q) {
-    SP.key_in = key[q & 1];
+    SP.key_in = kin;
     SP.val_in = val[q & 1];
     SP.key_out = key[(q & 1) ^ 1];
     SP.val_out = val[(q & 1) ^ 1];
     SP.shift = 8 * q;
     sort_pass(SP, s);
+    kin = SP.key_out;
   }
   hipLaunchKernelGGL(k_row_starts, dim3((unsigned)((P + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                      s, P, g->n, (const unsigned*)key[passes & 1], g->vptr);
