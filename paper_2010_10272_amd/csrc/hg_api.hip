@@ -13,7 +13,6 @@
 #include "hg_lp.h"
 
 namespace hg {
-hipError_t load_sort_big(hg_graph_s* g, int big_rows, hipStream_t s);
 }
 
 namespace {
@@ -275,10 +274,6 @@ hg_status hg_load_csr(int32_t n, int32_t m, int64_t P, const int64_t* eptr, cons
     return bail(fail(HG_ERR_UNSUPPORTED, "total vertex weight exceeds 2^62"));
   e = hg::load_build(g, s);
   if (e != hipSuccess) return bail(hip_fail(e, "incidence build"));
-  st = read_info(g, s);
-  if (st != HG_OK) return bail(st);
-  e = hg::load_sort_big(g, g->info.big_rows, s);
-  if (e != hipSuccess) return bail(hip_fail(e, "incidence sort"));
   // zero the round state kept in the workspace
   char* ws = g->ws;
   e = hg::fill_u8((unsigned char*)(ws + lay.touched), 0, (long long)hg::touched_bytes(m), s);

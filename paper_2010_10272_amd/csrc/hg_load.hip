@@ -186,6 +186,8 @@ hipError_t load_check(hg_graph_s* g, hipStream_t s) {
   return hipGetLastError();
 }
 
+constexpr int kBigRowGrid = 256;   // workgroups striding over the long rows
+
 // ------------------------------------------------------------------ transpose
 // (pin, net) pairs in net order, stably radix-sorted by pin: the values are
 // then the incidence rows, each listing its nets in increasing id, with no
@@ -290,34 +292,40 @@ __global__ void k_big_row_facts(const long long* vptr, const int* vnets, const i
                                 const int* big_list, int* heavy_list, LoadInfo* info) {
   __shared__ long long s_tmp[kBlock / kWave];
   __shared__ int s_err;
-  const int v = big_list[blockIdx.x];
-  const long long b = vptr[v];
-  const int len = (int)(vptr[v + 1] - b);
-  const int* row = vnets + b;
-  if (threadIdx.x == 0) s_err = 0;
-  __syncthreads();
-  long long tot = 0;
-  int err = 0;
-  for (int i = threadIdx.x; i < len; i += blockDim.x) {
-    if (i > 0 && row[i] == row[i - 1]) err = kErrDuplicate;
-    tot += ewgt ? ewgt[row[i]] : 1;
-  }
-  if (err) atomicOr(&s_err, err);
-  tot = block_sum64(tot, s_tmp);
-  if (threadIdx.x == 0) {
-    if (s_err) atomicOr(&info->err, s_err);
-    const int incw = tot > 0x7fffffffLL ? 0x7fffffff : (int)tot;
-    atomicMax(&info->max_degree, len);
-    atomicMax(&info->max_incident_weight, incw);
-    if (tot > kLightLimit) {
-      const int hi = atomicAdd(&info->heavy_count, 1);
-      heavy_list[hi] = v;
+  // the count comes from the short-row pass (an earlier launch), so the host
+  // need not read it first; a fixed grid strides over the list
+  const int nbig = info->big_rows;
+  for (int bi = blockIdx.x; bi < nbig; bi += gridDim.x) {
+    const int v = big_list[bi];
+    const long long b = vptr[v];
+    const int len = (int)(vptr[v + 1] - b);
+    const int* row = vnets + b;
+    if (threadIdx.x == 0) s_err = 0;
+    __syncthreads();
+    long long tot = 0;
+    int err = 0;
+    for (int i = threadIdx.x; i < len; i += blockDim.x) {
+      if (i > 0 && row[i] == row[i - 1]) err = kErrDuplicate;
+      tot += ewgt ? ewgt[row[i]] : 1;
     }
+    if (err) atomicOr(&s_err, err);
+    tot = block_sum64(tot, s_tmp);
+    if (threadIdx.x == 0) {
+      if (s_err) atomicOr(&info->err, s_err);
+      const int incw = tot > 0x7fffffffLL ? 0x7fffffff : (int)tot;
+      atomicMax(&info->max_degree, len);
+      atomicMax(&info->max_incident_weight, incw);
+      if (tot > kLightLimit) {
+        const int hi = atomicAdd(&info->heavy_count, 1);
+        heavy_list[hi] = v;
+      }
+    }
+    __syncthreads();
   }
 }
 
-// Builds vptr/vnets and the short rows' facts.  The long-row pass needs
-// LoadInfo.big_rows from a synchronized read, so it is load_sort_big.
+// Builds vptr/vnets and the rows' facts (short rows one per thread, long
+// rows one per workgroup).
 hipError_t load_build(hg_graph_s* g, hipStream_t s) {
   LoadInfo* info = (LoadInfo*)(g->ws + g->lay.info);
   int* big = (int*)(g->ws + g->lay.big);
@@ -357,15 +365,7 @@ hipError_t load_build(hg_graph_s* g, hipStream_t s) {
   hipLaunchKernelGGL(k_row_facts, dim3(grid_cap_load(g->n)), dim3(kBlock), 0, s, g->n, g->vptr,
                      g->vnets, g->ewgt, big, heavy, info, part);
   hipLaunchKernelGGL(k_fold_load, dim3(1), dim3(kBlock), 0, s, (const LoadPart*)part, info);
-  return hipGetLastError();
-}
-
-hipError_t load_sort_big(hg_graph_s* g, int big_rows, hipStream_t s) {
-  if (big_rows <= 0) return hipSuccess;
-  LoadInfo* info = (LoadInfo*)(g->ws + g->lay.info);
-  int* big = (int*)(g->ws + g->lay.big);
-  int* heavy = (int*)(g->ws + g->lay.heavy);
-  hipLaunchKernelGGL(k_big_row_facts, dim3(big_rows), dim3(kBlock), 0, s, g->vptr, g->vnets,
+  hipLaunchKernelGGL(k_big_row_facts, dim3(kBigRowGrid), dim3(kBlock), 0, s, g->vptr, g->vnets,
                      g->ewgt, big, heavy, info);
   return hipGetLastError();
 }
