@@ -77,8 +77,9 @@ __global__ __launch_bounds__(kBlock) void k_gains_light(Launch L, long long* __r
   const int k = D.k;
   const long long u = (long long)wi.first * kBlock + threadIdx.x;
   const bool staged = !cache && gains && k % 8 == 0;
-  // 0: nothing to write here (out of range, heavy, or not asked for);
-  // 1: this lane's row is computed
+  // done: nothing to compute for this lane (out of range, invalid block, or
+  // a block within L_max when only overloaded blocks are asked for);
+  // have: this lane's row was computed here (a light vertex)
   bool done = false, have = false;
   int a = 0, tot = 0, ben = 0;
   BitCounters<WK> C;
