@@ -694,7 +694,11 @@ __global__ __launch_bounds__(kBlock) void k_tilesum(Launch L) {
     D.tilesum[(long long)i * D.num_tiles + tile] = (long long)s_sum[i];
 }
 
-// Unit: one target block.
+// Unit: one target block.  Thread i takes kScanPerThread consecutive tiles
+// of each span of kBlock * kScanPerThread tiles (one span covers 2048 tiles,
+// two million vertices): one workgroup scan per span.
+constexpr int kScanPerThread = 8;
+
 __global__ __launch_bounds__(kBlock) void k_tilescan(Launch L) {
   __shared__ long long s_tmp[kBlock / kWave];
   __shared__ int s_tau;
@@ -712,17 +716,36 @@ __global__ __launch_bounds__(kBlock) void k_tilescan(Launch L) {
     s_tau = num_tiles;
     s_remt = 0;
   }
+  const long long* row = D.tilesum + (long long)t * num_tiles;
   long long carry = 0;
-  for (int base = 0; base < num_tiles; base += kBlock) {
-    int i = base + threadIdx.x;
-    long long v = i < num_tiles ? D.tilesum[(long long)t * num_tiles + i] : 0;
+  for (int base = 0; base < num_tiles; base += kBlock * kScanPerThread) {
+    const int first = base + threadIdx.x * kScanPerThread;
+    long long v[kScanPerThread];
+    long long mine = 0;
+#pragma unroll
+    for (int q = 0; q < kScanPerThread; ++q) {
+      v[q] = first + q < num_tiles ? row[first + q] : 0;
+      mine += v[q];
+    }
     long long tot;
-    long long ex = block_excl_scan64(v, s_tmp, &tot);
-    if (i < num_tiles && v > 0 && carry + ex + v > r.rem) atomicMin(&s_tau, i);
+    long long run = carry + block_excl_scan64(mine, s_tmp, &tot);
+    // this thread's first tile whose gain-g* weight overflows the budget,
+    // and the weight before it
+    int hit = -1;
+    long long hit_before = 0;
+#pragma unroll
+    for (int q = 0; q < kScanPerThread; ++q) {
+      if (hit < 0 && v[q] > 0 && run + v[q] > r.rem) {
+        hit = first + q;
+        hit_before = run;
+      }
+      run += v[q];
+    }
+    if (hit >= 0) atomicMin(&s_tau, hit);
     __syncthreads();
     const int f = s_tau;
     if (f < num_tiles) {
-      if (i == f) s_remt = r.rem - (carry + ex);
+      if (hit == f) s_remt = r.rem - hit_before;   // budget left at tile f's start
       break;
     }
     carry += tot;
