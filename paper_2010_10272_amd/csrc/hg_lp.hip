@@ -678,15 +678,20 @@ __global__ __launch_bounds__(kBlock) void k_tilesum(Launch L) {
   __syncthreads();
   const int tile = wi.first;
   const long long base = (long long)tile * kTile;
+  // every candidate word and weight of this thread requested before the first wait
+  long long x[kPerThreadTile];
+  int cw[kPerThreadTile];
+#pragma unroll
   for (int j = 0; j < kPerThreadTile; ++j) {
-    long long u = base + (long long)j * kBlock + threadIdx.x;
-    if (u < D.n) {
-      long long x = D.cand[u];
-      if (x >= 0) {
-        int t = cand_target(x);
-        if (cand_gain(x) == s_g[t])
-          atomicAdd(&s_sum[t], (unsigned long long)(D.vwgt ? D.vwgt[u] : 1));
-      }
+    const long long u = base + (long long)j * kBlock + threadIdx.x;
+    x[j] = u < D.n ? D.cand[u] : -1;
+    cw[j] = u < D.n && D.vwgt ? D.vwgt[u] : 1;
+  }
+#pragma unroll
+  for (int j = 0; j < kPerThreadTile; ++j) {
+    if (x[j] >= 0) {
+      const int t = cand_target(x[j]);
+      if (cand_gain(x[j]) == s_g[t]) atomicAdd(&s_sum[t], (unsigned long long)cw[j]);
     }
   }
   __syncthreads();
@@ -862,17 +867,22 @@ __global__ __launch_bounds__(kBlock) void k_approve_apply(Launch L) {
   if (wi.count >= 0) {
     const int tile = wi.first;
     const long long base = (long long)tile * kTile;
+    long long xs[kPerThreadTile];   // requested before the first wait
+#pragma unroll
+    for (int j = 0; j < kPerThreadTile; ++j) {
+      const long long u = base + (long long)j * kBlock + threadIdx.x;
+      xs[j] = u < n ? cand[u] : -1;
+    }
+#pragma unroll
     for (int j = 0; j < kPerThreadTile; ++j) {
       const long long u = base + (long long)j * kBlock + threadIdx.x;
       bool ok = false;
       int t = 0;
-      if (u < n) {
-        const long long x = cand[u];
-        if (x >= 0) {
-          t = cand_target(x);
-          const int g = cand_gain(x), gs = s_g[t];
-          ok = g > gs || (g == gs && tile < s_tau[t]);
-        }
+      const long long x = xs[j];
+      if (x >= 0) {
+        t = cand_target(x);
+        const int g = cand_gain(x), gs = s_g[t];
+        ok = g > gs || (g == gs && tile < s_tau[t]);
       }
       const int slot = wave_append(&s_count, ok);   // LDS counter, one atomic per wave
       if (ok) {
