@@ -577,12 +577,16 @@ __global__ __launch_bounds__(kBlock) void k_threshold(Launch L) {
   const int t = wi.first;
   const int bucket = kBuckets - 1 - threadIdx.x;
   long long h = 0;
+  unsigned long long* col = D.hist + (size_t)t * kBuckets + bucket;
+  unsigned long long rv[kHistReplicas];
+  // all replicas' cells requested before the stores that clear them
+#pragma unroll
+  for (int rep = 0; rep < kHistReplicas; ++rep)
+    rv[rep] = rep < D.hist_reps ? col[(size_t)rep * D.hist_stride] : 0ull;
 #pragma unroll
   for (int rep = 0; rep < kHistReplicas; ++rep) {
-    if (rep >= D.hist_reps) break;
-    unsigned long long* cell = D.hist + (size_t)rep * D.hist_stride + (size_t)t * kBuckets + bucket;
-    h += (long long)*cell;
-    *cell = 0;
+    h += (long long)rv[rep];
+    if (rep < D.hist_reps) col[(size_t)rep * D.hist_stride] = 0;
   }
   const long long budget = D.lmax - D.block_w[t];
   if (threadIdx.x == 0) s_first = kBlock;
