@@ -4,9 +4,10 @@
 // Section "Preliminaries" defines Phi, Lambda, lambda and km1; subsection
 // "Data Structures for Gain Calculation" keeps Phi and a bitset Lambda per
 // net.  Here one group of G lanes owns one net at a time: it counts the net's
-// pins per block in LDS, writes the Phi row with coalesced stores and builds
-// the bitsets with wave ballots.  No global atomics touch Phi, so the result
-// is deterministic by construction.
+// pins per block in LDS, writes the Phi row (16-byte streaming stores when
+// rows are aligned, coalesced 4-byte stores otherwise) and builds the bitsets
+// with wave ballots.  No global atomics touch Phi, so the result is
+// deterministic by construction.
 #include "hg_device.h"
 #include "hg_internal.h"
 #include "hg_lp.h"
