@@ -76,6 +76,8 @@ typedef struct {
   int64_t km1_delta_recomputed;  /* sum over touched nets of (lambda_old -
                                     lambda_new) * w(e); equals km1_delta           */
   int64_t active_pins;           /* sum of d(u) over active (eligible boundary) u   */
+  int64_t touched_pins;          /* sum of |e| over touched nets (pins made eligible,
+                                    counted with repeats)                          */
 } hg_round_stats;
 
 /* Phases of a label-propagation round measured by hg_timing_collect. */

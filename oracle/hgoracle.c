@@ -44,6 +44,7 @@ typedef struct {
   int64_t km1_after;      /* km1 after the round                              */
   int64_t max_block_weight; /* max_i c(V_i) after the round                   */
   int64_t active_pins;    /* sum of d(u) over active (eligible boundary) u    */
+  int64_t touched_pins;   /* sum of |e| over the touched nets                 */
 } or_round_stats;
 
 /* ------------------------------------------------------------------------ */
@@ -384,6 +385,7 @@ static int lp_round_impl(int32_t n, int32_t m, const int64_t* eptr, const int32_
   for (int32_t e = 0; e < m; ++e) {
     if (!touched[e]) continue;
     st->touched_nets += 1;
+    st->touched_pins += eptr[e + 1] - eptr[e];
     for (int64_t p = eptr[e]; p < eptr[e + 1]; ++p) eligible[pins[p]] = 1;
   }
 
@@ -576,6 +578,7 @@ int or_lp_round_exact(int32_t n, int32_t m, const int64_t* eptr, const int32_t* 
   st->approved = p;
   st->moved_pins = 0;
   st->touched_nets = 0;
+  st->touched_pins = 0;
   int32_t* phi = (int32_t*)malloc(sizeof(int32_t) * (size_t)m * (size_t)k);
   int32_t* lambda = (int32_t*)malloc(sizeof(int32_t) * (size_t)m);
   uint32_t* bits = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)m * (size_t)((k + 31) / 32));
@@ -596,6 +599,7 @@ int or_lp_round_exact(int32_t n, int32_t m, const int64_t* eptr, const int32_t* 
   for (int32_t e = 0; e < m; ++e) {
     if (!touched[e]) continue;
     st->touched_nets += 1;
+    st->touched_pins += eptr[e + 1] - eptr[e];
     for (int64_t q = eptr[e]; q < eptr[e + 1]; ++q) eligible[pins[q]] = 1;
   }
   or_pin_counts(m, eptr, pins, part, k, phi);
@@ -776,6 +780,7 @@ int or_rebalance_round(int32_t n, int32_t m, const int64_t* eptr, const int32_t*
   for (int32_t e = 0; e < m; ++e) {
     if (!touched[e]) continue;
     st->touched_nets += 1;
+    st->touched_pins += eptr[e + 1] - eptr[e];
     for (int64_t p = eptr[e]; p < eptr[e + 1]; ++p) eligible[pins[p]] = 1;
   }
   or_pin_counts(m, eptr, pins, part, k, phi);

@@ -22,7 +22,8 @@ OR_OK = 0
 OR_ERR_INVALID = -1
 
 STATS_FIELDS = ("eligible", "boundary", "candidates", "approved", "moved_pins",
-                "touched_nets", "km1_delta", "km1_after", "max_block_weight", "active_pins")
+                "touched_nets", "km1_delta", "km1_after", "max_block_weight", "active_pins",
+                "touched_pins")
 
 
 class RoundStats(ctypes.Structure):
@@ -32,13 +33,16 @@ class RoundStats(ctypes.Structure):
         return {f: int(getattr(self, f)) for f in STATS_FIELDS}
 
 
+CC = "gcc"
+CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-Wall"]
+
+
 def build(force=False):
     """Compile the oracle with gcc into oracle/libhgoracle.so."""
     if force or not os.path.exists(_LIB_PATH) or \
             os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
         tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared",
-                               "-Wall", "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call([CC] + CFLAGS + ["-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 

@@ -60,6 +60,7 @@ enum CounterId : int {
   kCtrActivePins,
   kCtrTouched,
   kCtrMarked,       // approved moves marked for a monotone round (before the prefix cut)
+  kCtrTouchedPins,  // sum of |e| over touched nets
   kNumCounters
 };
 

@@ -1041,7 +1041,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Launch L) {
   const InstDesc D = inst_desc(L, wi.inst);
   const int grp = threadIdx.x / G, gl = threadIdx.x % G;
   const int k = D.k, wk = bit_words(k), rw = D.rw;
-  long long dcheck = 0, ntouched = 0;
+  long long dcheck = 0, ntouched = 0, tpins = 0;
   for (int it = 0; it < wi.count; ++it) {
     const long long c = (long long)wi.first + (long long)it * wi.stride;
     if (threadIdx.x == 0) s_cnt = 0;
@@ -1069,8 +1069,11 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Launch L) {
       if (gl >= 1 && gl < 2 + 2 * wk) rec[gl] = nb.word;
       if (D.view != kViewFull) write_view(D.view_ptr, e, D.view, gl, nb);
       if (gl == 1) dcheck += (long long)(lam_old - nb.lambda) * w;
-      if (gl == 0) D.touched[e] = 0;
       const long long b = D.eptr[e], t = D.eptr[e + 1];
+      if (gl == 0) {
+        D.touched[e] = 0;
+        tpins += t - b;
+      }
       if constexpr (CACHE) {
         cache_net_delta<G>(D, e, wk, gl, old_word, nb.word, b, t);
       } else {
@@ -1091,10 +1094,12 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Launch L) {
     __syncthreads();
   }
   dcheck = block_sum64(dcheck, s_tmp);
+  tpins = block_sum64(tpins, s_tmp);
   if (threadIdx.x == 0) {
     const int sl = blockIdx.x % kSlots;
     if (dcheck) atomicAdd(&D.ctr->slot[kCtrDeltaCheck][sl], (unsigned long long)dcheck);
     if (ntouched) atomicAdd(&D.ctr->slot[kCtrTouched][sl], (unsigned long long)ntouched);
+    if (tpins) atomicAdd(&D.ctr->slot[kCtrTouchedPins][sl], (unsigned long long)tpins);
   }
 }
 
@@ -1159,6 +1164,7 @@ __global__ __launch_bounds__(kBlock) void k_round_stats(Launch L) {
     st.km1_delta = s_sum[kCtrDeltaAttr];
     st.km1_delta_recomputed = s_sum[kCtrDeltaCheck];
     st.active_pins = s_sum[kCtrActivePins];
+    st.touched_pins = s_sum[kCtrTouchedPins];
     st.km1_after = *D.km1 - st.km1_delta;
     st.max_block_weight = m;
     *D.km1 = st.km1_after;

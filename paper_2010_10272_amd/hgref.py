@@ -12,8 +12,7 @@ import os
 import torch  # loads the HIP runtime that libhgref.so binds to
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# HGREF_LIB names another build of the same library (for side-by-side timing)
-LIB_PATH = os.environ.get("HGREF_LIB") or os.path.join(_HERE, "libhgref.so")
+LIB_PATH = os.path.join(_HERE, "libhgref.so")   # always the in-tree build
 
 HG_OK = 0
 HG_ERR_INVALID = -1
@@ -24,7 +23,7 @@ HG_MAX_K = 256
 
 STATS_FIELDS = ("eligible", "boundary", "candidates", "approved", "moved_pins", "touched_nets",
                 "km1_delta", "km1_after", "max_block_weight", "km1_delta_recomputed",
-                "active_pins")
+                "active_pins", "touched_pins")
 HG_PHASES = ("select", "approve", "finalize")
 STATS_WORDS = len(STATS_FIELDS)
 

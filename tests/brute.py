@@ -57,7 +57,7 @@ def lp_round(nets, n, c, w, k, lmax, part, eligible):
     cw = (lambda v: 1) if c is None else (lambda v: int(c[v]))
     cands = []
     stats = dict(eligible=0, boundary=0, candidates=0, approved=0, moved_pins=0,
-                 touched_nets=0, active_pins=0)
+                 touched_nets=0, active_pins=0, touched_pins=0)
     for u in range(n):
         if not eligible[u]:
             continue
@@ -106,6 +106,7 @@ def lp_round(nets, n, c, w, k, lmax, part, eligible):
     stats["moved_pins"] = sum(len(incident(nets, u)) for u, _ in approved)
     touched = [j for j, e in enumerate(nets) if any(moved[v] for v in e)]
     stats["touched_nets"] = len(touched)
+    stats["touched_pins"] = sum(len(nets[j]) for j in touched)
     nxt = [0] * n
     for j in touched:
         for v in nets[j]:
@@ -129,7 +130,7 @@ def rebalance_round(nets, n, c, w, k, lmax, part, eligible):
     W = [block_weight(part, c, i) for i in range(k)]
     cw = (lambda v: 1) if c is None else (lambda v: int(c[v]))
     stats = dict(eligible=0, boundary=0, candidates=0, approved=0, moved_pins=0,
-                 touched_nets=0, active_pins=0)
+                 touched_nets=0, active_pins=0, touched_pins=0)
     cands = []
     for u in range(n):
         a = part[u]
@@ -167,6 +168,7 @@ def rebalance_round(nets, n, c, w, k, lmax, part, eligible):
     stats["moved_pins"] = sum(len(incident(nets, u)) for u in range(n) if moved[u])
     touched = [j for j, e in enumerate(nets) if any(moved[v] for v in e)]
     stats["touched_nets"] = len(touched)
+    stats["touched_pins"] = sum(len(nets[j]) for j in touched)
     nxt = [int(x) for x in eligible]
     for j in touched:
         for v in nets[j]:
