@@ -1,26 +1,29 @@
 #!/usr/bin/env python3
 """Benchmark of the km1 label-propagation refinement core on one MI355X.
 
-Workload (the sparse-matrix refinement case): the row-net hypergraph of a
-seeded random 1,000,000 x 1,000,000 sparse matrix (about 10M pins, lognormal
-row lengths, 70% banded columns), vertex weight = column degree, refined from
-a random balanced start at k = 8 and at k = 64, eps = 0.03, 10 synchronous LP
-rounds each.
+Headline workload (the largest plain single-GPU case): a seeded VLSI-like
+netlist, 4,000,000 cells on a 2000 x 2000 grid, 4,200,000 nets (sizes 2-5
+with probability 0.9, else 6-200; 99% inside a 16 x 16 window, 1% global),
+about 56.5M pins, cell weights U{1..8}, refined from a horizontal-strip start
+at k = 16, eps = 0.03, 10 synchronous LP rounds.
 
 One step is one pass of the whole hot path on resident device inputs: load
-(incidence CSR + checks), and for each k: pin counts, 10 LP rounds (select /
-approve / apply / finalize), all k-way gains, km1.  The reported value counts
-the nominal pins of every LP round: 2 x 10 x P pins per step, divided by the
-step time (so load, pin counts, gains and km1 are inside the time but add no
-pins).
+(incidence CSR + checks), pin counts, 10 LP rounds (select / approve / apply
+/ finalize), all k-way gains, km1.  The reported value counts the nominal
+pins of every LP round, 10 x P pins per step, divided by the step time (load,
+pin counts, gains and km1 are inside the time but add no pins).
 
-Also reported: per-round latency p50/p99 (each round timed alone with HIP
-events), the recorded-hipGraph refine time, the select kernel's algorithmic
-bandwidth against the 8 TB/s HBM peak (timed live with HIP events on the
-kernel's stream during the timed steps), and the CPU oracle on a bounded
-sample of the same workload.
+Beside it, the same measurement on the sparse-matrix workload (1M x 1M row-net
+matrix, about 10M pins, k = 8 and 64) and on the tiny instance (n = m =
+10,000, k = 2, 5 rounds), then the batched, served, monotone, gain-cache,
+rebalancing and contraction legs.  For each plain workload: the select
+kernel's and the whole round's algorithmic bandwidth against the 8 TB/s HBM
+peak (round records over the library's per-phase HIP events, recorded on the
+kernels' stream during the timed steps), per-round latency p50/p99, the
+recorded-hipGraph refine time, and the CPU oracle on a bounded sample of the
+same rounds, whose records and partitions must equal the timed run's.
 
-usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--legs ...]
 """
 import argparse
 import json
@@ -38,14 +41,35 @@ KS = (8, 64)
 ROUNDS = 10
 
 
+def _w_lambda(k):
+    return 4 * ((k + 31) // 32)
+
+
 def select_bytes(st, n, k):
     """Algorithmic bytes of one select launch: eligible bits n/8, 16 B per
     active vertex (part, offsets, weight), (12 + w_Lambda) B per active
     incidence (net id, w(e), the pin-count/singleton word of the own block,
     the Lambda bitset of ceil(k/32) words), 16 B per candidate written."""
-    w_lambda = 4 * ((k + 31) // 32)
-    return (n / 8.0 + 16.0 * st["boundary"] + (12.0 + w_lambda) * st["active_pins"] +
+    return (n / 8.0 + 16.0 * st["boundary"] + (12.0 + _w_lambda(k)) * st["active_pins"] +
             16.0 * st["candidates"])
+
+
+def approve_bytes(st, n, k):
+    """Approval and apply of one round: 32 B per candidate (its word read by
+    the tile sums and the approval, its weight), 4 B per approved move, and
+    the apply: 16 B per mover (part, offsets, weight, flag), 20 B per moved
+    incidence (net id, two Phi read-modify-writes)."""
+    return 32.0 * st["candidates"] + 20.0 * st["approved"] + 20.0 * st["moved_pins"]
+
+
+def finalize_bytes(st, n, k):
+    """Finalize of one round: 8 B per touched net (offsets, flag, record),
+    4 B per pin of a touched net (the pin ids whose eligibility is set), the
+    next eligible set n/8."""
+    return 8.0 * st["touched_nets"] + 4.0 * st["touched_pins"] + n / 8.0
+
+
+PHASE_BYTES = {"select": select_bytes, "approve": approve_bytes, "finalize": finalize_bytes}
 
 
 def roofline_of(name, alg_bytes, ms):
@@ -62,31 +86,56 @@ def timed_oracle(fn):
     return time.perf_counter() - t0, out
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "plain_sparse_matrix_traffic.md")
+def host_info():
+    """The host the oracle baseline ran on: CPU model, logical CPUs (all and
+    usable by this process), the oracle's compiler and flags."""
+    import subprocess
+    from oracle import oracle as O
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        cc = subprocess.run([O.CC, "--version"], capture_output=True, text=True,
+                            timeout=10).stdout.splitlines()[0]
+    except (OSError, IndexError, subprocess.SubprocessError):
+        cc = None
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "usable_cpus": len(os.sched_getaffinity(0)), "compiler": cc,
+            "flags": " ".join(O.CFLAGS), "threads_used": 1}
 
 
-def measured_select_traffic():
-    """HBM-side bytes per select launch from the committed FETCH_SIZE /
-    WRITE_SIZE profile, or None when the select kernel's sources changed
-    since those counters were taken (their SHA-256 is recorded with them)."""
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def measured_traffic(profile, prefix):
+    """HBM-side bytes per launch of one kernel from a committed rocprofv3
+    counter summary, or None when that kernel's sources changed since the
+    counters were taken (their SHA-256 is recorded with them)."""
     import hashlib
     import re
     try:
-        text = open(TRAFFIC_PROFILE).read()
+        text = open(os.path.join(PROFILES, profile)).read()
     except OSError:
         return None
-    got = dict(re.findall(r"^(select_[a-z_0-9]+): (.+)$", text, re.M))
-    if "select_traffic_bytes_per_launch" not in got:
+    got = dict(re.findall(r"^(%s_[a-z_0-9]+): (.+)$" % prefix, text, re.M))
+    key = prefix + "_traffic_bytes_per_launch"
+    if key not in got:
         return None
     h = hashlib.sha256()
-    for rel in got["select_sources"].split():
+    for rel in got[prefix + "_sources"].split():
         try:
             h.update(open(os.path.join(ROOT, rel), "rb").read())
         except OSError:
             return None
-    if h.hexdigest() != got.get("select_sources_sha256", "").strip():
+    if h.hexdigest() != got.get(prefix + "_sources_sha256", "").strip():
         return None
-    return float(got["select_traffic_bytes_per_launch"])
+    return float(got[key])
 
 
 def percentile(xs, q):
@@ -97,32 +146,6 @@ def percentile(xs, q):
     return xs[i]
 
 
-def cpu_baseline(inst, rounds_per_k):
-    """Oracle (single-threaded C) on a bounded sample: `rounds_per_k` LP rounds
-    at each k of the same workload, timed on this host."""
-    from oracle import oracle as O
-    h = O.Hypergraph(inst.n, inst.eptr, inst.pins, inst.c, inst.w)
-    h.incidence()
-    import numpy as np
-    import synth
-    pins_rounds = 0
-    t_total = 0.0
-    for k in KS:
-        ik = synth.with_k(inst, k)
-        L = O.lmax(O.total_vertex_weight(h), k, inst.eps)
-        part = ik.part.copy()
-        elig = np.ones(inst.n, np.uint8)
-        for _ in range(rounds_per_k):
-            t0 = time.perf_counter()
-            part, elig, _, _ = O.lp_round(h, k, L, part, elig)
-            t_total += time.perf_counter() - t0
-            pins_rounds += inst.P
-    return {"value": pins_rounds / t_total, "unit": "pins/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d LP rounds at k=%s of the same 1M x 1M instance (%d pins), "
-                      "single-threaded C oracle, %.1f s" % (rounds_per_k, "/".join(map(str, KS)),
-                                                           inst.P, t_total)}
-
-
 BATCH_COUNT = 512
 BATCH_ROUNDS = 8
 
@@ -131,29 +154,40 @@ def _events(torch):
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
-def batched_cpu_baseline(insts, budget_s):
+def batched_cpu_baseline(insts, budget_s, members, H):
     """Oracle on a bounded sample of the batch: members in order, every LP
-    round of each, until about `budget_s` seconds of oracle time."""
+    round of each, until about `budget_s` seconds of oracle time; each
+    sampled member's round records and final partition must equal the
+    batched run's."""
     from oracle import oracle as O
     import numpy as np
     t_total, pin_rounds, done = 0.0, 0, 0
-    for inst in insts:
+    for inst, mb in zip(insts, members):
         h = O.Hypergraph(inst.n, inst.eptr, inst.pins, inst.c, inst.w)
         h.incidence()
         L = O.lmax(O.total_vertex_weight(h), inst.k, inst.eps)
         part = inst.part.copy()
         elig = np.ones(inst.n, np.uint8)
+        recs = []
         for _ in range(inst.rounds):
             t0 = time.perf_counter()
-            part, elig, _, _ = O.lp_round(h, inst.k, L, part, elig)
+            part, elig, _, st = O.lp_round(h, inst.k, L, part, elig)
             t_total += time.perf_counter() - t0
             pin_rounds += inst.P
+            recs.append(st)
+        got = H.stats_to_dicts(mb.stats)
+        for r, want in enumerate(recs):
+            got[r].pop("km1_delta_recomputed")
+            assert got[r] == want, "batch member %d round %d differs from the oracle" % (done, r)
+        assert np.array_equal(mb.st.part.cpu().numpy(), part), "batch member %d differs" % done
         done += 1
         if t_total >= budget_s:
             break
     return {"value": pin_rounds / t_total, "unit": "pins/s", "cores": 1, "kind": "oracle",
+            "host": host_info(),
             "sample": "all %d rounds of the first %d of the %d batch members (%d pin-rounds), "
-                      "single-threaded C oracle, %.1f s" % (insts[0].rounds, done, len(insts),
+                      "single-threaded C oracle, %.1f s; their records and partitions equal "
+                      "the batched run's" % (insts[0].rounds, done, len(insts),
                                                            pin_rounds, t_total)}
 
 
@@ -261,7 +295,7 @@ def batched_leg(args, H, dev):
                  "512 sequential hg_refine calls",
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = batched_cpu_baseline(insts, args.batch_cpu_s)
+        out["cpu_baseline"] = batched_cpu_baseline(insts, args.batch_cpu_s, members, H)
     for mb in members:
         mb.g.free()
     del members, ar
@@ -495,6 +529,7 @@ def monotone_leg(args, H, dev):
             assert np.array_equal(want, gains.cpu().numpy()), "move gains differ from the oracle"
             res["move_gains"]["cpu_baseline"] = {
                 "value": deg / dt, "unit": "incidences/s", "cores": 1, "kind": "oracle",
+                "host": host_info(),
                 "sample": "the same %d-move sequence, once" % t}
         out["k%d" % k] = res
         g.free()
@@ -507,6 +542,7 @@ def cached_leg(args, H, dev):
     sparse-matrix workload at k = 8 and 64, 10 rounds from the same start;
     both must give the same partition and round records.  Per-phase times
     come from the library's own event timing."""
+    import numpy as np
     import torch
     import synth
     inst = sparse_instance()
@@ -561,11 +597,19 @@ def cached_leg(args, H, dev):
             from oracle import oracle as O
             h = O.Hypergraph(inst.n, inst.eptr, inst.pins, inst.c, inst.w)
             L = H.hg_max_block_weight(g, k, inst.eps)
-            dt, (p1, _, _) = timed_oracle(lambda: O.refine(h, k, L, 1, ik.part))
+            dt, (p1, s1, _) = timed_oracle(lambda: O.refine(h, k, L, 1, ik.part))
+            # one cached round from the same start must equal the oracle's round
+            st.part.copy_(part0)
+            one = torch.zeros(H.STATS_WORDS, dtype=torch.int64, device=dev)
+            H.hg_refine_cached(g, st, inst.eps, 1, one, cache)
+            got = H.stats_to_dicts(one)[0]
+            got.pop("km1_delta_recomputed")
+            assert got == s1[0], "cached round record differs from the oracle"
+            assert np.array_equal(st.part.cpu().numpy(), p1), "cached round differs from oracle"
             res["cpu_baseline"] = {"value": inst.P / dt, "unit": "pins/s", "cores": 1,
-                                   "kind": "oracle",
-                                   "sample": "one label-propagation round (the cached round's "
-                                             "result), k = %d" % k}
+                                   "kind": "oracle", "host": host_info(),
+                                   "sample": "one label-propagation round, k = %d (equal to the "
+                                             "GPU's cached round: partition and record)" % k}
         out["k%d" % k] = res
         g.free()
     return out
@@ -626,11 +670,23 @@ def rebalance_leg(args, H, dev):
             from oracle import oracle as O
             h = O.Hypergraph(inst.n, inst.eptr, inst.pins, inst.c, inst.w)
             h.incidence()
-            dt, (p1, _, _, s1) = timed_oracle(lambda: O.rebalance_round(
+            dt, (p1, e1, _, s1) = timed_oracle(lambda: O.rebalance_round(
                 h, k, L, part0, np.zeros(inst.n, np.uint8)))
-            assert s1["approved"] == recs[0]["approved"], "rebalancing differs from the oracle"
+            # the first round from the same start, compared element by element
+            st.part.copy_(p0)
+            st.eligible.zero_()
+            H.hg_compute_pincounts(g, st)
+            one = torch.zeros(H.STATS_WORDS, dtype=torch.int64, device=dev)
+            H.hg_rebalance(g, st, L, 1, one, ws)
+            got = H.stats_to_dicts(one)[0]
+            got.pop("km1_delta_recomputed")
+            assert got == s1, "rebalancing record differs from the oracle"
+            assert np.array_equal(st.part.cpu().numpy(), p1), "rebalancing differs from oracle"
+            assert np.array_equal(st.eligible.cpu().numpy(), e1), "rebalancing eligible differs"
             base = {"value": inst.P / dt, "unit": "pins/s", "cores": 1, "kind": "oracle",
-                    "sample": "the first rebalancing round, k = %d" % k}
+                    "host": host_info(),
+                    "sample": "the first rebalancing round, k = %d (equal to the GPU's: "
+                              "partition, eligible set and record)" % k}
         out["k%d" % k] = {"roofline": roofline_of("rebalancing round (all kernels)", rb_bytes,
                                                   ms),
                           "cpu_baseline": base,
@@ -678,50 +734,114 @@ def contract_leg(args, H, dev):
            "roofline": roofline_of("contraction (all kernels)", alg, ms)}
     if not args.no_cpu:
         from oracle import oracle as O
+        import numpy as np
         h = O.Hypergraph(inst.n, inst.eptr, inst.pins, inst.c, inst.w)
         t0 = time.perf_counter()
-        O.contract(h, cl)
+        mp_o, hc = O.contract(h, cl)
         dt = time.perf_counter() - t0
+        assert (nc, mc, pc) == (hc.n, hc.m, hc.P), "coarse sizes differ from the oracle"
+        mp, cv, ce, cpn, cw = (x.cpu().numpy() for x in out.views())
+        for got, want, what in ((mp, mp_o, "map"), (cv, hc.c, "vertex weights"),
+                                (ce, hc.eptr, "net offsets"), (cpn, hc.pins, "pins"),
+                                (cw, hc.w, "net weights")):
+            assert np.array_equal(got, want), "contraction %s differ from the oracle" % what
         res["cpu_baseline"] = {"value": inst.P / dt, "unit": "pins/s", "cores": 1,
-                               "kind": "oracle", "sample": "the whole contraction, once"}
+                               "kind": "oracle", "host": host_info(),
+                               "sample": "the whole contraction, once (equal to the GPU's "
+                                         "output)"}
     g.free()
     return res
 
 
-def plain_leg(args, H, dev):
-    """The plain workload (module docstring): returns the JSON record."""
+def copy_bandwidth(torch, dev, nbytes=1 << 30, reps=5):
+    """A plain device-to-device copy of `nbytes` on the same GPU, as a
+    measured reference beside the 8 TB/s peak: (read + write) bytes / time."""
+    src = torch.ones(nbytes // 4, dtype=torch.int32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    xs = []
+    for _ in range(reps):
+        a, b = _events(torch)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        xs.append(a.elapsed_time(b))
+    del src, dst
+    ms = percentile(xs, 50)
+    return {"bytes": 2 * nbytes, "ms": ms, "gbs": 2 * nbytes / (ms / 1e3) / 1e9}
+
+
+def oracle_rounds(inst, ks, plan):
+    """The oracle on the host (one thread): for each k, plan[k] LP rounds
+    from the workload's start.  Returns ({k: (part, records)}, baseline)."""
+    import numpy as np
+    import synth
+    from oracle import oracle as O
+    h = O.Hypergraph(inst.n, inst.eptr, inst.pins, inst.c, inst.w)
+    h.incidence()
+    out, t_total, pin_rounds = {}, 0.0, 0
+    for k in ks:
+        ik = synth.with_k(inst, k)
+        L = O.lmax(O.total_vertex_weight(h), k, inst.eps)
+        part = ik.part.copy()
+        elig = np.ones(inst.n, np.uint8)
+        recs = []
+        for _ in range(plan[k]):
+            t0 = time.perf_counter()
+            part, elig, _, st = O.lp_round(h, k, L, part, elig)
+            t_total += time.perf_counter() - t0
+            pin_rounds += inst.P
+            recs.append(st)
+        out[k] = (part, recs)
+    base = {"value": pin_rounds / t_total, "unit": "pins/s", "cores": 1, "kind": "oracle",
+            "sample": "the first %s LP rounds at k = %s of the same instance (%d pins), "
+                      "single-threaded C oracle, %.1f s; every round record and the partition "
+                      "after the last sampled round equal the GPU's"
+                      % ("/".join(str(plan[k]) for k in ks), "/".join(map(str, ks)), inst.P,
+                         t_total),
+            "seconds": t_total, "host": host_info()}
+    return out, base
+
+
+def plain_workload(args, H, dev, inst, ks, rounds, label, cpu_plan, roofline=True):
+    """One plain workload: a step is load + for every k (pin counts, `rounds`
+    LP rounds, all k-way gains, km1), timed over args.steps steps with the
+    inputs resident in HBM.  Value = len(ks) x rounds x P pins per step over
+    the step time.  Beside it: per-phase and whole-round rooflines from the
+    round records over the library's per-phase HIP events, per-round
+    latency, the recorded-graph refine time and the oracle on a sample of
+    the same rounds, checked record by record."""
+    import numpy as np
     import torch
     import synth
-    print("generating workload ...", file=sys.stderr, flush=True)
-    inst = sparse_instance()
     n, m, P = inst.n, inst.m, inst.P
-    parts = {k: torch.as_tensor(synth.with_k(inst, k).part).to(dev) for k in KS}
+    parts = {k: torch.as_tensor(synth.with_k(inst, k).part).to(dev) for k in ks}
     eptr = torch.as_tensor(inst.eptr).to(dev)
     pins = torch.as_tensor(inst.pins).to(dev)
     c = torch.as_tensor(inst.c).to(dev)
     w = torch.as_tensor(inst.w).to(dev)
-    kmax = max(KS)
+    kmax = max(ks)
     ws_bytes = H.hg_workspace_size(n, m, P, kmax)
     bufs = (torch.empty(n + 1, dtype=torch.int64, device=dev),
             torch.empty(P, dtype=torch.int32, device=dev),
             torch.empty(ws_bytes, dtype=torch.uint8, device=dev))
     g0 = H.hg_load_csr(n, eptr, pins, c, w, k_max=kmax, device=dev, out=bufs)
-    states = {k: H.State(g0, k, parts[k]) for k in KS}
+    states = {k: H.State(g0, k, parts[k]) for k in ks}
     g0.free()
-    stats = {k: torch.zeros(ROUNDS * H.STATS_WORDS, dtype=torch.int64, device=dev) for k in KS}
+    stats = {k: torch.zeros(rounds * H.STATS_WORDS, dtype=torch.int64, device=dev) for k in ks}
     gains = torch.empty(n * kmax, dtype=torch.int64, device=dev)
     km1_out = torch.empty(1, dtype=torch.int64, device=dev)
-
     phase_ms = {p: 0.0 for p in H.HG_PHASES}
     timed_rounds = [0]
 
     def step(collect):
         g = H.hg_load_csr(n, eptr, pins, c, w, k_max=kmax, device=dev, out=bufs)
         H.hg_timing_enable(g, True)
-        for k in KS:
+        for k in ks:
             st = states[k]
             st.part.copy_(parts[k])
-            H.hg_refine(g, st, inst.eps, ROUNDS, stats[k], use_graph=False)
+            H.hg_refine(g, st, inst.eps, rounds, stats[k], use_graph=False)
             H.hg_gains(g, k, st.part, st.netstate, gains=gains[:n * k])
             H.hg_km1(g, k, st.netstate, out=km1_out)
         ms, r = H.hg_timing_collect(g)     # waits for the step's last round
@@ -731,13 +851,12 @@ def plain_leg(args, H, dev):
             timed_rounds[0] += r
         g.free()
 
-    print("warmup ...", file=sys.stderr, flush=True)
+    print("%s: warmup ..." % label, file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
-    print("timing %d steps ..." % args.steps, file=sys.stderr, flush=True)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    print("%s: timing %d steps ..." % (label, args.steps), file=sys.stderr, flush=True)
+    e0, e1 = _events(torch)
     t0 = time.perf_counter()
     e0.record()
     for _ in range(args.steps):
@@ -748,106 +867,193 @@ def plain_leg(args, H, dev):
     gpu_ms = e0.elapsed_time(e1)
     elapsed = max(wall, gpu_ms / 1e3)
     ms_per_step = elapsed * 1e3 / args.steps
-    value = len(KS) * ROUNDS * P * args.steps / elapsed
-
-    per_k = {k: H.stats_to_dicts(stats[k]) for k in KS}
-    for k in KS:
+    value = len(ks) * rounds * P * args.steps / elapsed
+    per_k = {k: H.stats_to_dicts(stats[k]) for k in ks}
+    final_parts = {k: states[k].part.cpu().numpy() for k in ks}
+    for k in ks:
         for s in per_k[k]:
             assert s["km1_delta"] == s["km1_delta_recomputed"], "attributed km1 mismatch"
-    sel_bytes_step = sum(select_bytes(s, n, k) for k in KS for s in per_k[k])
-    sel_launches_step = len(KS) * ROUNDS
-    sel_ms_avg = phase_ms["select"] / max(1, timed_rounds[0])
-    achieved = (sel_bytes_step / sel_launches_step) / (sel_ms_avg / 1e3) / 1e9
+
+    # rooflines: bytes of the step's rounds (records) over the phase times
+    launches = len(ks) * rounds
+    assert timed_rounds[0] == launches * args.steps, "phase timing lost rounds"
+    phase_bytes = {p: sum(f(s, n, k) for k in ks for s in per_k[k]) / launches
+                   for p, f in PHASE_BYTES.items()}
+    phase_avg = {p: phase_ms[p] / timed_rounds[0] for p in H.HG_PHASES}
+    phases = {p: roofline_of(p, phase_bytes[p], phase_avg[p]) for p in H.HG_PHASES}
+    round_ms = sum(phase_avg.values())
+    whole = roofline_of("LP round (select + approve/apply + finalize)",
+                        sum(phase_bytes.values()), round_ms)
+
+    # per-k phase times from an untimed profile pass (same kernels)
+    g = H.hg_load_csr(n, eptr, pins, c, w, k_max=kmax, device=dev, out=bufs)
+    per_k_out = {}
+    for k in ks:
+        st = states[k]
+        H.hg_timing_enable(g, True)
+        for _ in range(args.latency_reps):
+            st.part.copy_(parts[k])
+            H.hg_refine(g, st, inst.eps, rounds, stats[k], use_graph=False)
+        ms, r = H.hg_timing_collect(g)
+        H.hg_timing_enable(g, False)
+        avg = {p: ms[p] / r for p in H.HG_PHASES}
+        by = {p: sum(f(s, n, k) for s in per_k[k]) / rounds for p, f in PHASE_BYTES.items()}
+        per_k_out["k%d" % k] = {
+            "phase_ms_per_round": avg,
+            "phase_frac": {p: roofline_of(p, by[p], avg[p])["frac"] for p in H.HG_PHASES},
+            "round_frac": roofline_of("round", sum(by.values()), sum(avg.values()))["frac"],
+            "round_bytes": sum(by.values()),
+            "records": per_k[k],
+        }
 
     # per-round latency: each round timed alone (events around hg_lp_round)
     lat = {}
-    g = H.hg_load_csr(n, eptr, pins, c, w, k_max=kmax, device=dev, out=bufs)
     one = torch.zeros(H.STATS_WORDS, dtype=torch.int64, device=dev)
-    for k in KS:
+    for k in ks:
         st = states[k]
         L = H.hg_max_block_weight(g, k, inst.eps)
-        xs = []
+        xs, first = [], []
         for _ in range(args.latency_reps):
             st.part.copy_(parts[k])
             H.hg_compute_pincounts(g, st)
             st.eligible.fill_(1)
-            for r in range(ROUNDS):
-                a = torch.cuda.Event(enable_timing=True)
-                b = torch.cuda.Event(enable_timing=True)
+            for r in range(rounds):
+                a, b = _events(torch)
                 a.record()
                 H.hg_lp_round(g, st, L, one, moved=False)
                 b.record()
                 b.synchronize()
                 xs.append(a.elapsed_time(b))
-        lat["k%d" % k] = {"p50_ms": percentile(xs, 50), "p99_ms": percentile(xs, 99)}
+                if r == 0:
+                    first.append(xs[-1])
+        lat["k%d" % k] = {"p50_ms": percentile(xs, 50), "p99_ms": percentile(xs, 99),
+                          "round1_p50_ms": percentile(first, 50),
+                          "pins_per_s_p50": P / (percentile(xs, 50) / 1e3)}
     # recorded hipGraph replay of the same refinement
     graph_ms = {}
-    for k in KS:
+    for k in ks:
         st = states[k]
         xs = []
         for _ in range(args.latency_reps + 1):
             st.part.copy_(parts[k])
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
+            a, b = _events(torch)
             a.record()
-            H.hg_refine(g, st, inst.eps, ROUNDS, stats[k], use_graph=True)
+            H.hg_refine(g, st, inst.eps, rounds, stats[k], use_graph=True)
             b.record()
             b.synchronize()
             xs.append(a.elapsed_time(b))
         graph_ms["k%d" % k] = percentile(xs[1:], 50)       # first call records the graph
         assert H.stats_to_dicts(stats[k]) == per_k[k], "graph replay differs"
-    g.free()
 
     out = {
-        "metric": METRIC,
         "value": value,
+        "unit": "pins/s",
+        "ms_per_step": ms_per_step,
+        "n": n, "m": m, "P": P, "k": list(ks), "rounds": rounds, "eps": inst.eps,
+        "roofline": {
+            "kernel": "k_select_light (LP select sweep)",
+            "bound": "hbm",
+            "achieved": phases["select"]["achieved"],
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": phases["select"]["frac"],
+            "avg_launch_us": phase_avg["select"] * 1e3,
+            "alg_bytes_per_launch": phase_bytes["select"],
+            "round": whole,
+            "phases": phases,
+        },
+        "per_k": per_k_out,
+        "round_latency": lat,
+        "graph_refine_ms": graph_ms,
+        "km1_final": {"k%d" % k: per_k[k][-1]["km1_after"] for k in ks},
+    }
+    if not roofline:
+        out["roofline"]["note"] = ("launch-bound instance (about a megabyte per round): "
+                                   "no roofline claim")
+
+    if not args.no_cpu:
+        print("%s: oracle rounds ..." % label, file=sys.stderr, flush=True)
+        want, base = oracle_rounds(inst, ks, cpu_plan)
+        for k in ks:
+            part_o, recs_o = want[k]
+            R = len(recs_o)
+            for r in range(R):
+                got = dict(per_k[k][r])
+                got.pop("km1_delta_recomputed")
+                assert got == recs_o[r], "%s k=%d round %d differs from the oracle" % (
+                    label, k, r)
+            if R == rounds:
+                got_part = final_parts[k]
+            else:
+                st = states[k]
+                st.part.copy_(parts[k])
+                H.hg_refine(g, st, inst.eps, R, stats[k][:R * H.STATS_WORDS], use_graph=False)
+                got_part = st.part.cpu().numpy()
+            assert np.array_equal(got_part, part_o), "%s k=%d partition differs" % (label, k)
+        out["cpu_baseline"] = base
+        out["check"] = ("round records of the timed steps equal the oracle's for the sampled "
+                        "rounds, and the partitions after them")
+    g.free()
+    del states, bufs, gains
+    torch.cuda.empty_cache()
+    return out
+
+
+def headline(args, rec, workload, config_extra):
+    """The benchmark line's top-level fields from one plain workload."""
+    out = {
+        "metric": METRIC,
+        "value": rec["value"],
         "unit": "pins/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": rec["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {
-            "workload": "sparse-matrix row-net hypergraph 1M x 1M (%d pins), k=8 and k=64, "
-                        "eps=0.03, 10 synchronous LP rounds per k; one step = load + "
-                        "(pin counts + 10 rounds + gains + km1) per k" % P,
-            "n": n, "m": m, "P": P, "k": list(KS), "rounds": ROUNDS, "eps": inst.eps,
-            "seed": 2, "parallelism": "single GPU",
-        },
-        "roofline": {
-            "kernel": "k_select_light (LP select sweep)",
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_select_traffic(),
-            "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated; "
-                            "profiles/plain_sparse_matrix_traffic.md)",
-            "avg_launch_us": sel_ms_avg * 1e3,
-            "alg_bytes_per_launch": sel_bytes_step / sel_launches_step,
-        },
-        "phase_ms_per_round": {p: phase_ms[p] / max(1, timed_rounds[0]) for p in phase_ms},
-        "round_latency": lat,
-        "graph_refine_ms": graph_ms,
-        "km1_final": {"k%d" % k: per_k[k][-1]["km1_after"] for k in KS},
+        "config": dict({"workload": workload, "parallelism": "single GPU"}, **config_extra),
+        "roofline": rec["roofline"],
     }
-    if args.calibrate_copy > 0:
-        nb = args.calibrate_copy << 20
-        src = torch.ones(nb // 4, dtype=torch.int32, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        out["calibrate_copy_bytes"] = nb
-        del src, dst
-    if not args.no_cpu:
-        print("cpu baseline ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_rounds)
+    if "cpu_baseline" in rec:
+        out["cpu_baseline"] = rec["cpu_baseline"]
+    return out
+
+
+def plain_legs(args, H, dev):
+    """The plain workloads: the VLSI-like netlist (the headline), the
+    sparse matrix and the tiny instance."""
+    import torch
+    import synth
+    print("generating the VLSI-like netlist ...", file=sys.stderr, flush=True)
+    vl = synth.vlsi_grid()
+    rec = plain_workload(args, H, dev, vl, (vl.k,), ROUNDS, "vlsi", {vl.k: args.cpu_rounds})
+    rec["roofline"]["traffic"] = measured_traffic("plain_vlsi_traffic.md", "select")
+    rec["roofline"]["traffic_unit"] = ("bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated "
+                                       "by a plain copy; profiles/plain_vlsi_traffic.md)")
+    rec["roofline"]["copy_reference"] = copy_bandwidth(torch, dev)
+    out = headline(args, rec, "VLSI-like netlist: 2000 x 2000 grid, n = %d cells, m = %d nets, "
+                   "%d pins, k = %d, eps = 0.03, 10 synchronous LP rounds; one step = load + "
+                   "pin counts + 10 rounds + gains + km1" % (vl.n, vl.m, vl.P, vl.k),
+                   {"n": vl.n, "m": vl.m, "P": vl.P, "k": [vl.k], "rounds": ROUNDS,
+                    "eps": vl.eps, "seed": 3})
+    out["vlsi"] = {x: rec[x] for x in ("per_k", "round_latency", "graph_refine_ms",
+                                        "km1_final", "check") if x in rec}
+    del vl
+    sp = sparse_instance()
+    srec = plain_workload(args, H, dev, sp, KS, ROUNDS, "sparse",
+                          {8: ROUNDS, 64: args.cpu_rounds_k64})
+    srec["roofline"]["traffic"] = measured_traffic("plain_sparse_matrix_traffic.md", "select")
+    srec["config"] = ("sparse-matrix row-net hypergraph 1M x 1M (%d pins), k = 8 and k = 64, "
+                      "eps = 0.03, 10 synchronous LP rounds per k; one step = load + (pin counts "
+                      "+ 10 rounds + gains + km1) per k" % sp.P)
+    out["sparse_matrix"] = srec
+    tiny = synth.tiny_plain()
+    trec = plain_workload(args, H, dev, tiny, (2,), 5, "tiny", {2: 5}, roofline=False)
+    trec["config"] = "tiny power-law hypergraph n = m = 10,000 (%d pins), k = 2, 5 rounds" % tiny.P
+    out["tiny"] = trec
     return out
 
 
@@ -857,7 +1063,10 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-rounds", type=int, default=4)
+    ap.add_argument("--cpu-rounds", type=int, default=4,
+                    help="oracle rounds sampled on the VLSI-like netlist")
+    ap.add_argument("--cpu-rounds-k64", type=int, default=3,
+                    help="oracle rounds sampled on the sparse matrix at k = 64 (all 10 at k = 8)")
     ap.add_argument("--latency-reps", type=int, default=5)
     ap.add_argument("--legs", default="plain,batched,served,monotone,cached,rebalance,contract",
                     help="comma list of plain, batched, served, monotone, cached, rebalance, "
@@ -885,7 +1094,16 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda:0")
     legs = set(args.legs.split(","))
-    out = plain_leg(args, H, dev) if "plain" in legs else {"metric": METRIC}
+    out = plain_legs(args, H, dev) if "plain" in legs else {"metric": METRIC}
+    if args.calibrate_copy > 0:
+        nb = args.calibrate_copy << 20
+        src = torch.ones(nb // 4, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibrate_copy_bytes"] = nb
+        del src, dst
     if "batched" in legs:
         torch.cuda.empty_cache()
         out["batched"] = batched_leg(args, H, dev)
