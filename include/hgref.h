@@ -219,6 +219,25 @@ hg_status hg_lp_round(hg_graph g, int32_t k, int64_t max_block_w, int32_t* part,
                       uint8_t* eligible, uint8_t* moved, int64_t* km1,
                       hg_round_stats* stats, void* stream);
 
+/* hg_lp_round for callers that cannot allocate device memory at call time
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, kernels and results as hg_lp_round; the round
+ * scratch (candidate words, touched-net flags, gain histograms, thresholds,
+ * tile sums, counter and block-weight slots) comes from a fixed device array
+ * inside the library (about 15 MB, one copy per GPU, held until the process
+ * ends) instead of the graph's workspace, and the call allocates nothing.
+ * Limits: n <= 2^20 and m <= 2^20 (HG_ERR_UNSUPPORTED beyond, nothing
+ * enqueued); any k the graph supports.  `stream` must belong to the current
+ * device.  Every call on one GPU shares that GPU's array and clears what
+ * must start at zero (with fill kernels, no memset nodes), so calls whose
+ * work overlaps on one GPU (other streams or host threads) race and give
+ * undefined results; calls on one stream are ordered and safe.  Per-phase
+ * timing (hg_timing_enable) does not apply to this call. */
+hg_status hg_lp_round_noalloc(hg_graph g, int32_t k, int64_t max_block_w, int32_t* part,
+                              int32_t* phi, uint32_t* netstate, int64_t* block_w,
+                              uint8_t* eligible, uint8_t* moved, int64_t* km1,
+                              hg_round_stats* stats, void* stream);
+
 /* Refinement driver: hg_compute_pincounts from `part`, every vertex
  * eligible, then `rounds` label-propagation rounds with
  * L_max = hg_max_block_weight(g, k, eps).  Rounds after convergence record

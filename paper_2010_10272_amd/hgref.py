@@ -113,6 +113,8 @@ def _load():
     lib.hg_gains.restype = i32
     lib.hg_lp_round.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.hg_lp_round.restype = i32
+    lib.hg_lp_round_noalloc.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.hg_lp_round_noalloc.restype = i32
     lib.hg_refine.argtypes = [vp, i32, dbl, i32, vp, vp, vp, vp, vp, vp, vp, i32, vp]
     lib.hg_refine.restype = i32
     lib.hg_timing_enable.argtypes = [vp, i32]
@@ -373,6 +375,15 @@ def hg_lp_round(g, st, max_block_w, stats, moved=True, stream=None):
                             _ptr(st.netstate), _ptr(st.block_w), _ptr(st.eligible),
                             _ptr(st.moved) if moved else None, _ptr(st.km1), _ptr(stats),
                             _stream(stream)))
+
+
+def hg_lp_round_noalloc(g, st, max_block_w, stats, moved=True, stream=None):
+    """hg_lp_round with the round scratch in the library's fixed device array
+    (allocates nothing; n, m <= 2^20)."""
+    _check(_lib.hg_lp_round_noalloc(g.handle, st.k, int(max_block_w), _ptr(st.part),
+                                    _ptr(st.phi), _ptr(st.netstate), _ptr(st.block_w),
+                                    _ptr(st.eligible), _ptr(st.moved) if moved else None,
+                                    _ptr(st.km1), _ptr(stats), _stream(stream)))
 
 
 def hg_refine(g, st, eps, rounds, stats, use_graph=True, stream=None):
