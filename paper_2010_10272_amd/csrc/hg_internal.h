@@ -27,7 +27,7 @@ constexpr int kNumXcd = 8;             // MI355X: 8 XCDs, each with its own L2
 constexpr int kLdsHistEntries = 2048;  // per-workgroup LDS gain histogram (k * buckets)
 constexpr int kSelectGrid = 2048;      // persistent workgroups of the select sweep
 constexpr int kUnroll = 4;             // record gathers in flight per thread in the sweeps
-constexpr int kFinalizeGrid = 16384;   // persistent workgroups of the finalize sweep
+constexpr int kFinalizeGrid = 2048;    // persistent workgroups of the finalize sweep
 
 // Validation bits raised on the device.
 enum : int {

@@ -215,20 +215,25 @@ __global__ void k_pin_pairs(int m, const long long* eptr, int* val) {
   });
 }
 
-// vptr[v] = the first sorted position with key >= v; vptr[n] = P.
-__global__ void k_row_starts(long long P, int n, const unsigned* key, long long* vptr) {
+// vptr[v] = the first sorted position with key >= v; vptr[n] = P.  A pair
+// equal to its predecessor (same pin, same net) is a vertex listed twice in
+// one net: the stable sort puts such pairs side by side.
+__global__ void k_row_starts(long long P, int n, const unsigned* key, const int* val,
+                             long long* vptr, LoadInfo* info) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= P) return;
   const long long cur = key[i];
   const long long prev = i == 0 ? -1 : (long long)key[i - 1];
+  if (cur == prev && val[i] == val[i - 1]) atomicOr(&info->err, kErrDuplicate);
   for (long long v = prev + 1; v <= cur; ++v) vptr[v] = i;
   if (i == P - 1)
     for (long long v = cur + 1; v <= n; ++v) vptr[v] = P;
 }
 
-// Per-vertex facts of the sorted rows (one thread per row up to kSmallRow
-// incidences; longer rows are listed for k_big_row_facts): repeated nets
-// (a vertex twice in a net), degree, w(I(v)), the heavy list.
+// Per-vertex facts of the sorted rows: degree, w(I(v)), the heavy list.
+// With unit net weights (ewgt == NULL) w(I(v)) is the degree and only the
+// offsets are read.  Otherwise one thread sums a row of up to kSmallRow
+// incidences; longer rows are listed for k_big_row_facts.
 __global__ __launch_bounds__(kBlock) void k_row_facts(int n, const long long* vptr,
                                                       const int* vnets, const int* ewgt,
                                                       int* big_list, int* heavy_list,
@@ -236,7 +241,7 @@ __global__ __launch_bounds__(kBlock) void k_row_facts(int n, const long long* vp
   __shared__ int s_imax[kBlock / kWave];
   __shared__ unsigned s_big, s_heavy, s_big_base, s_heavy_base;
   __shared__ int s_bigv[kBlock], s_heavyv[kBlock];
-  int err = 0, maxdeg = 0, maxincw = 0;
+  int maxdeg = 0, maxincw = 0;
   const long long stride = (long long)gridDim.x * kBlock;
   const long long rounds = ((long long)n + stride - 1) / stride;
   for (long long r = 0; r < rounds; ++r) {
@@ -248,17 +253,25 @@ __global__ __launch_bounds__(kBlock) void k_row_facts(int n, const long long* vp
       const long long b = vptr[v];
       const int deg = (int)(vptr[v + 1] - b);
       maxdeg = deg > maxdeg ? deg : maxdeg;
-      if (deg > kSmallRow) {
+      if (!ewgt) {
+        maxincw = deg > maxincw ? deg : maxincw;
+        heavy = deg > kLightLimit;
+      } else if (deg > kSmallRow) {
         big = true;
       } else {
+        // the row's entries in groups of four, loaded before their weights
         const int* row = vnets + b;
         long long tot = 0;
-        int prev = -1;
-        for (int i = 0; i < deg; ++i) {
-          const int x = row[i];
-          if (x == prev) err = kErrDuplicate;
-          prev = x;
-          tot += ewgt ? ewgt[x] : 1;
+        for (int i0 = 0; i0 < deg; i0 += 4) {
+          int x[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) x[q] = row[i0 + q < deg ? i0 + q : i0];
+          int wq[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) wq[q] = ewgt[x[q]];
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (i0 + q < deg) tot += wq[q];
         }
         const int incw = tot > 0x7fffffffLL ? 0x7fffffff : (int)tot;
         maxincw = incw > maxincw ? incw : maxincw;
@@ -277,7 +290,6 @@ __global__ __launch_bounds__(kBlock) void k_row_facts(int n, const long long* vp
     if (threadIdx.x < s_heavy) heavy_list[s_heavy_base + threadIdx.x] = s_heavyv[threadIdx.x];
     __syncthreads();
   }
-  if (err) atomicOr(&info->err, err);
   const int md = block_max_int(maxdeg, s_imax);
   const int mi = block_max_int(maxincw, s_imax);
   if (threadIdx.x == 0) {
@@ -291,7 +303,6 @@ __global__ __launch_bounds__(kBlock) void k_row_facts(int n, const long long* vp
 __global__ void k_big_row_facts(const long long* vptr, const int* vnets, const int* ewgt,
                                 const int* big_list, int* heavy_list, LoadInfo* info) {
   __shared__ long long s_tmp[kBlock / kWave];
-  __shared__ int s_err;
   // the count comes from the short-row pass (an earlier launch), so the host
   // need not read it first; a fixed grid strides over the list
   const int nbig = info->big_rows;
@@ -300,18 +311,10 @@ __global__ void k_big_row_facts(const long long* vptr, const int* vnets, const i
     const long long b = vptr[v];
     const int len = (int)(vptr[v + 1] - b);
     const int* row = vnets + b;
-    if (threadIdx.x == 0) s_err = 0;
-    __syncthreads();
     long long tot = 0;
-    int err = 0;
-    for (int i = threadIdx.x; i < len; i += blockDim.x) {
-      if (i > 0 && row[i] == row[i - 1]) err = kErrDuplicate;
-      tot += ewgt ? ewgt[row[i]] : 1;
-    }
-    if (err) atomicOr(&s_err, err);
+    for (int i = threadIdx.x; i < len; i += blockDim.x) tot += ewgt[row[i]];
     tot = block_sum64(tot, s_tmp);
     if (threadIdx.x == 0) {
-      if (s_err) atomicOr(&info->err, s_err);
       const int incw = tot > 0x7fffffffLL ? 0x7fffffff : (int)tot;
       atomicMax(&info->max_degree, len);
       atomicMax(&info->max_incident_weight, incw);
@@ -360,13 +363,17 @@ hipError_t load_build(hg_graph_s* g, hipStream_t s) {
     kin = SP.key_out;
   }
   hipLaunchKernelGGL(k_row_starts, dim3((unsigned)((P + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                     s, P, g->n, (const unsigned*)key[passes & 1], g->vptr);
+                     s, P, g->n, (const unsigned*)key[passes & 1], (const int*)g->vnets, g->vptr,
+                     info);
+  // all net weights 1 (the checks summed them to m): rows need no weights
+  const int* ew = g->info.total_net_weight == (unsigned long long)g->m ? nullptr : g->ewgt;
   LoadPart* part = (LoadPart*)(g->ws + g->lay.lpart);
   hipLaunchKernelGGL(k_row_facts, dim3(grid_cap_load(g->n)), dim3(kBlock), 0, s, g->n, g->vptr,
-                     g->vnets, g->ewgt, big, heavy, info, part);
+                     g->vnets, ew, big, heavy, info, part);
   hipLaunchKernelGGL(k_fold_load, dim3(1), dim3(kBlock), 0, s, (const LoadPart*)part, info);
-  hipLaunchKernelGGL(k_big_row_facts, dim3(kBigRowGrid), dim3(kBlock), 0, s, g->vptr, g->vnets,
-                     g->ewgt, big, heavy, info);
+  if (ew)
+    hipLaunchKernelGGL(k_big_row_facts, dim3(kBigRowGrid), dim3(kBlock), 0, s, g->vptr, g->vnets,
+                       ew, big, heavy, info);
   return hipGetLastError();
 }
 

@@ -8,7 +8,7 @@
 
 namespace hg {
 
-constexpr int kFinalChunk = kBlock;   // nets per unit of the finalize sweep
+constexpr int kFinalChunk = 4 * kBlock;   // nets per unit of the finalize sweep (4 flags per thread)
 
 typedef void (*SelectKernel)(Launch);
 typedef void (*FinalizeKernel)(Launch);

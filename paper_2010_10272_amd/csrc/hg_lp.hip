@@ -1030,12 +1030,28 @@ __device__ void cache_net_delta(const InstDesc& D, long long e, int wk, int gl, 
   }
 }
 
+// Unit: a block of kFinalChunk (1024) nets.  Every thread reads four touched
+// flags with one load; the touched nets of the block are listed in LDS.
+// Groups of G lanes then rebuild each listed net's Lambda, S and lambda from
+// its final Phi row and clear its flag; the lane that rewrites lambda(e)
+// reads the old value first, so the drop (lambda_old - lambda_new) * w(e)
+// summed over touched nets checks the attributed total.  Last, the pins of
+// all listed nets are made eligible as one flattened list spread over the
+// whole workgroup (offsets by a prefix sum, owner by binary search), so a
+// long net does not serialize on one group.  With the gain cache the group
+// walks its net's pins itself (cache_net_delta marks them too).  Single
+// instance: contiguous XCD-aware runs of blocks.
+constexpr int kMarkSlots = 4;   // pin positions per thread in flight in the marks
+
 template <int G, bool CACHE>
 __global__ __launch_bounds__(kBlock) void k_finalize(Launch L) {
   __shared__ int s_list[kFinalChunk];
+  __shared__ int s_off[kFinalChunk];        // first flattened pin position of each listed net
+  __shared__ int s_beg[kFinalChunk];        // eptr of each listed net (P < 2^31)
   __shared__ long long s_tmp[kBlock / kWave];
   __shared__ unsigned s_cnt;
   constexpr int kGroups = kBlock / G;
+  constexpr int kFlags = kFinalChunk / kBlock;   // 4
   const WorkItem wi = work_item(L, xcd_block((L.one.m + kFinalChunk - 1) / kFinalChunk));
   if (wi.count == 0) return;
   const InstDesc D = inst_desc(L, wi.inst);
@@ -1046,11 +1062,20 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Launch L) {
     const long long c = (long long)wi.first + (long long)it * wi.stride;
     if (threadIdx.x == 0) s_cnt = 0;
     __syncthreads();
-    // one flag per thread (the flag array is padded to whole chunks, zero past m)
-    const long long e0 = c * kFinalChunk + threadIdx.x;
-    const bool t0 = D.touched[e0] != 0;
-    const int slot = wave_append(&s_cnt, t0);
-    if (t0) s_list[slot] = (int)e0;
+    // four flags per thread in one load (the flag array is padded to whole
+    // blocks and zero past m; the workspace keeps it 4-byte aligned)
+    const long long e0 = c * kFinalChunk + (long long)threadIdx.x * kFlags;
+    const unsigned f4 = *reinterpret_cast<const unsigned*>(D.touched + e0);
+    int mine = 0;
+#pragma unroll
+    for (int q = 0; q < kFlags; ++q) mine += ((f4 >> (8 * q)) & 0xffu) != 0;
+    const int incl = wave_incl_scan(mine);
+    int base = 0;
+    if (lane_id() == kWave - 1 && incl) base = (int)atomicAdd(&s_cnt, (unsigned)incl);
+    base = __shfl(base, kWave - 1) + incl - mine;
+#pragma unroll
+    for (int q = 0; q < kFlags; ++q)
+      if ((f4 >> (8 * q)) & 0xffu) s_list[base++] = (int)(e0 + q);
     __syncthreads();
     const int cnt = (int)s_cnt;
     ntouched += cnt;
@@ -1065,30 +1090,60 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Launch L) {
       }
       // gain cache: the record's Lambda / S words before this round
       const unsigned old_word = CACHE && gl >= 2 && gl < 2 + 2 * wk ? rec[gl] : 0u;
+      const long long b = D.eptr[e], t = D.eptr[e + 1];
       NetBits nb = net_bits<G>(k, gl, [&](int i2) { return row[i2]; });
       if (gl >= 1 && gl < 2 + 2 * wk) rec[gl] = nb.word;
       if (D.view != kViewFull) write_view(D.view_ptr, e, D.view, gl, nb);
       if (gl == 1) dcheck += (long long)(lam_old - nb.lambda) * w;
-      const long long b = D.eptr[e], t = D.eptr[e + 1];
       if (gl == 0) {
         D.touched[e] = 0;
         tpins += t - b;
+        s_beg[i] = (int)b;
+        s_off[i] = (int)(t - b);          // the length, until the scan below
       }
-      if constexpr (CACHE) {
-        cache_net_delta<G>(D, e, wk, gl, old_word, nb.word, b, t);
-      } else {
-        // every pin eligible; four pin loads in flight before the stores
-        for (long long p0 = b + gl; p0 < t; p0 += 4 * G) {
-          int v[4];
+      if constexpr (CACHE) cache_net_delta<G>(D, e, wk, gl, old_word, nb.word, b, t);
+    }
+    if constexpr (!CACHE) {
+      __syncthreads();
+      // flattened pin positions: exclusive prefix of the lengths (four list
+      // entries per thread)
+      int len[kFlags];
+      long long sum = 0;
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const long long p = p0 + r * G;
-            v[r] = D.pins[p < t ? p : p0];
+      for (int q = 0; q < kFlags; ++q) {
+        const int i = threadIdx.x * kFlags + q;
+        len[q] = i < cnt ? s_off[i] : 0;
+        sum += len[q];
+      }
+      long long total64;
+      long long off = block_excl_scan64(sum, s_tmp, &total64);
+#pragma unroll
+      for (int q = 0; q < kFlags; ++q) {
+        const int i = threadIdx.x * kFlags + q;
+        if (i < cnt) s_off[i] = (int)off;
+        off += len[q];
+      }
+      __syncthreads();
+      const int total = (int)total64;     // at most P < 2^31
+      for (int j0 = threadIdx.x; j0 < total; j0 += kBlock * kMarkSlots) {
+        int at[kMarkSlots];
+#pragma unroll
+        for (int q = 0; q < kMarkSlots; ++q) {
+          const int j = j0 + q * kBlock < total ? j0 + q * kBlock : j0;
+          // owner: the last listed net whose first position is <= j
+          int lo = 0, hi = cnt - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] <= j) lo = mid; else hi = mid - 1;
           }
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            if (p0 + r * G < t) D.eligible[v[r]] = 1;
+          at[q] = s_beg[lo] + (j - s_off[lo]);
         }
+        int v[kMarkSlots];
+#pragma unroll
+        for (int q = 0; q < kMarkSlots; ++q) v[q] = D.pins[at[q]];
+#pragma unroll
+        for (int q = 0; q < kMarkSlots; ++q)
+          if (j0 + q * kBlock < total) D.eligible[v[q]] = 1;
       }
     }
     __syncthreads();
