@@ -89,12 +89,15 @@ __device__ __forceinline__ WorkItem single_unit(int unit) {
 // records stay in that XCD's L2).  Candidate weights go to an LDS histogram
 // (buckets [0, B) per target block, B = min(256, 2048/k)); higher gains and
 // the final flush go to the histogram replica of this workgroup's XCD.
+constexpr int kDenseWave = 3 * kWave / 4;   // eligible lanes that make a wave's slice dense
+
 template <int WK, int VIEW>
 __global__ __launch_bounds__(kBlock) void k_select_light(Launch L) {
   __shared__ long long s_W[HG_MAX_K];
   __shared__ unsigned s_open[WK];
   __shared__ unsigned long long s_hist[kLdsHistEntries];
   __shared__ long long s_tmp[kBlock / kWave];
+  __shared__ int s_q[kBlock / kWave][2 * kWave];   // per-wave queues of eligible vertices
   const InstDesc D0 = L.one;
   const WorkItem wi = work_item(L, xcd_sweep((D0.n + kBlock - 1) / kBlock));
   if (wi.count == 0) return;
@@ -124,25 +127,23 @@ __global__ __launch_bounds__(kBlock) void k_select_light(Launch L) {
   const unsigned* __restrict__ netstate = D.netstate;
   const unsigned* __restrict__ view = D.view_ptr;
   const int rw = D.rw;
-  for (int it = 0; it < wi.count; ++it) {
-    const long long c = (long long)wi.first + (long long)it * wi.stride;
-    const long long u = c * kBlock + threadIdx.x;
-    if (u >= n) continue;
-    if (D.moved) D.moved[u] = 0;
-    const unsigned char el = D.eligible[u];
-    if (!el) {
-      D.cand[u] = -1;
-      continue;
-    }
+  // Each wave queues the eligible vertices of its 64-vertex slices in LDS
+  // and processes them 64 at a time, so that later rounds (few eligible
+  // vertices) run full waves instead of mostly idle ones; slices that are
+  // mostly eligible (every vertex in round 1) are processed in place.  No
+  // workgroup barrier is involved, so waves keep sweeping independently.
+  // Every vertex gets its moved flag cleared, and the non-eligible ones
+  // their "no candidate" word, when its slice is read.
+  auto one_vertex = [&](const long long u) {
     const int a = D.part[u];
     if ((unsigned)a >= (unsigned)k) {
       atomicOr(D.err_flags, kErrPart);
       D.cand[u] = -1;
       D.eligible[u] = 0;
-      continue;
+      return;
     }
     const long long b0 = vptr[u], b1 = vptr[u + 1];
-    if (b1 - b0 > kLightLimit) continue;        // heavy vertex: the wavefront kernel owns it
+    if (b1 - b0 > kLightLimit) return;        // heavy vertex: the wavefront kernel owns it
     BitCounters<WK> C;
     C.clear();
     int tot = 0, ben = 0;
@@ -199,7 +200,7 @@ __global__ __launch_bounds__(kBlock) void k_select_light(Launch L) {
       }
     }
     if constexpr (VIEW != kViewFull) tot = deg;
-    if (heavy) continue;
+    if (heavy) return;
     D.eligible[u] = 0;
     n_elig += 1;
     long long out = -1;
@@ -254,6 +255,45 @@ __global__ __launch_bounds__(kBlock) void k_select_light(Launch L) {
       }
     }
     D.cand[u] = out;
+  };
+  const int lane = lane_id();
+  int* my_q = s_q[threadIdx.x / kWave];
+  int qn = 0;                                  // this wave's queue length (wave-uniform)
+  // one call site of one_vertex (the select body is large): the extra last
+  // iteration flushes the queue
+  for (int it = 0; it <= wi.count; ++it) {
+    long long todo = -1;
+    if (it < wi.count) {
+      const long long c = (long long)wi.first + (long long)it * wi.stride;
+      const long long u = c * kBlock + threadIdx.x;
+      bool el = false;
+      if (u < n) {
+        if (D.moved) D.moved[u] = 0;
+        el = D.eligible[u] != 0;
+        if (!el) D.cand[u] = -1;
+      }
+      const unsigned long long mask = __ballot(el);
+      const int cnt = __popcll(mask);
+      if (cnt >= kDenseWave) {                 // mostly eligible: in place
+        todo = el ? u : -1;
+      } else {
+        if (el) my_q[qn + __popcll(mask & ((1ull << lane) - 1))] = (int)u;
+        qn += cnt;                             // < 2 * kWave
+        wave_lds_sync();
+        if (qn >= kWave) {
+          todo = my_q[lane];
+          const int rest = qn - kWave;
+          const int keep = lane < rest ? my_q[kWave + lane] : 0;
+          wave_lds_sync();
+          if (lane < rest) my_q[lane] = keep;
+          qn = rest;
+          wave_lds_sync();
+        }
+      }
+    } else if (lane < qn) {
+      todo = my_q[lane];
+    }
+    if (todo >= 0) one_vertex(todo);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < k * B; i += kBlock) {
@@ -1248,7 +1288,13 @@ SelectKernel select_kernel(int k, int view) {
   }
 }
 
-FinalizeKernel finalize_kernel(int k, bool cache) { return finalize_kernel_g(group_lanes(k), cache); }
+// The plain finalize reads one Phi row and writes one record per net: for
+// k <= 16 four lanes hold the record and the row's counts, and narrower
+// groups put twice as many nets in flight per wave (its pins are marked by
+// the whole workgroup).  The cache variant walks the pins in the group.
+FinalizeKernel finalize_kernel(int k, bool cache) {
+  return finalize_kernel_g(!cache && k <= 16 ? 4 : group_lanes(k), cache);
+}
 
 // The gain-cache update lives in its own instantiation: the plain one then
 // needs far fewer registers (more workgroups per compute unit).
