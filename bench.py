@@ -1072,8 +1072,8 @@ def main():
                     help="comma list of plain, batched, served, monotone, cached, rebalance, "
                          "contract")
     ap.add_argument("--mono-reps", type=int, default=3)
-    ap.add_argument("--served-seconds", type=float, default=10.0,
-                    help="length of the open-loop request trace")
+    ap.add_argument("--served-seconds", type=float, default=60.0,
+                    help="length of the open-loop request trace (60 s: about 12,000 requests)")
     ap.add_argument("--batch-count", type=int, default=BATCH_COUNT)
     ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--batch-cpu-s", type=float, default=8.0)

@@ -17,7 +17,7 @@ namespace hg {
 
 constexpr int kWave = 64;
 constexpr int kBlock = 256;            // threads per workgroup in every kernel
-constexpr int kTile = 1024;            // vertices per approval tile (256 threads x 4)
+constexpr int kTile = 512;             // vertices per approval tile (256 threads x 2)
 constexpr int kPerThreadTile = kTile / kBlock;
 constexpr int kBuckets = 256;          // gain buckets per target block (0..254 exact, 255 = ">=255")
 constexpr int kLightLimit = 255;       // w(I(v)) <= 255: bit-sliced register path

@@ -9,7 +9,7 @@
 //   threshold  per target block: the highest gain g* at which the cumulative
 //              candidate weight (from the top gain down) overflows
 //              L_max - c(V_t); gains above g* are approved whole.
-//   tilesum    per tile of 1024 vertices: weight of gain-g* candidates per
+//   tilesum    per tile of 512 vertices: weight of gain-g* candidates per
 //              target block (vertex id order is tile order).
 //   tilescan   per target block: the tile where the budget runs out.
 //   approve    per tile: decide every candidate; the one boundary tile per
@@ -745,7 +745,7 @@ __global__ __launch_bounds__(kBlock) void k_tilesum(Launch L) {
 
 // Unit: one target block.  Thread i takes kScanPerThread consecutive tiles
 // of each span of kBlock * kScanPerThread tiles (one span covers 2048 tiles,
-// two million vertices): one workgroup scan per span.
+// about a million vertices): one workgroup scan per span.
 constexpr int kScanPerThread = 8;
 
 __global__ __launch_bounds__(kBlock) void k_tilescan(Launch L) {

@@ -32,6 +32,8 @@
 #include <limits.h>
 #include <string.h>
 
+#include <algorithm>
+
 #include "hg_device.h"
 #include "hg_internal.h"
 #include "hg_lp.h"
@@ -40,7 +42,7 @@
 namespace hg {
 namespace {
 
-constexpr int kPrefixChunk = kTile;         // moves per prefix-scan workgroup
+constexpr int kPrefixChunk = 4 * kBlock;    // moves per prefix-scan workgroup
 
 // Layout of the caller's move-sequence workspace.
 struct MovesLayout {
@@ -106,14 +108,6 @@ struct Seq {
 
 __device__ __forceinline__ int seq_len(const Seq& S) { return S.t_dev ? *S.t_dev : S.t; }
 
-// The number of marked moves (sum of the kCtrMarked slots) -> *t.
-__global__ void k_count_marked(const unsigned long long* slots, int* t) {
-  const int lane = lane_id();
-  long long v = (long long)slots[lane];
-  v = wave_sum(v);
-  if (lane == 0) *t = (int)v;
-}
-
 // Source and target of move j, or false for a move the checks reject.
 __device__ __forceinline__ bool seq_move(const Seq& S, int j, int& u, int& a, int& b) {
   u = S.mu[j];
@@ -123,20 +117,21 @@ __device__ __forceinline__ bool seq_move(const Seq& S, int j, int& u, int& a, in
   return (unsigned)b < (unsigned)S.k && (unsigned)a < (unsigned)S.k && a != b;
 }
 
-// Every incidence (move j, net e) of the workgroup's kBlock moves, spread
-// over all threads (prefix sum of the movers' degrees, owner by binary
-// search in LDS).  f(j, u, a, b, e) is called once per incidence.  A
-// workgroup owns kSeqTile moves, so a short sequence still spreads over
-// many workgroups.
+// Every incidence (move j, net e) of the kSeqTile moves of tile `tile`,
+// spread over all threads of the workgroup (prefix sum of the movers'
+// degrees, owner by binary search in LDS).  f(j, u, a, b, e) is called once
+// per incidence.  Tiles are short, so a short sequence still spreads over
+// many workgroups; the kernels below loop over tiles with a grid stride.
 constexpr int kSeqTile = 64;
+constexpr int kSeqGrid = 1024;   // persistent workgroups of the monotone round's sequence kernels
 
 template <typename F>
-__device__ void for_incidences(const Seq& S, int t, F f) {
+__device__ void for_incidences(const Seq& S, int t, int tile, F f) {
   __shared__ long long s_beg[kBlock];
   __shared__ int s_off[kBlock + 1];
   __shared__ int s_u[kBlock], s_a[kBlock], s_b[kBlock];
   __shared__ long long s_tmp[kBlock / kWave];
-  const int j = blockIdx.x * kSeqTile + threadIdx.x;
+  const int j = tile * kSeqTile + threadIdx.x;
   int u = -1, a = 0, b = 0;
   long long len = 0, beg = 0;
   if (threadIdx.x < kSeqTile && j < t && seq_move(S, j, u, a, b)) {
@@ -161,8 +156,9 @@ __device__ void for_incidences(const Seq& S, int t, F f) {
     }
     // slots without a move have length 0, so the owner always holds one
     const int e = S.vnets[s_beg[lo] + (x - s_off[lo])];
-    f(blockIdx.x * kSeqTile + lo, s_u[lo], s_a[lo], s_b[lo], e);
+    f(tile * kSeqTile + lo, s_u[lo], s_a[lo], s_b[lo], e);
   }
+  __syncthreads();   // the LDS lists are reused by the workgroup's next tile
 }
 
 // Checks of an explicit sequence: vertex and target in range, target !=
@@ -188,69 +184,114 @@ __global__ __launch_bounds__(kBlock) void k_seq_clear(Seq S) {
 // Cells (e, a) and (e, b) of every incidence start empty.
 __global__ __launch_bounds__(kBlock) void k_seq_init(Seq S) {
   const int t = seq_len(S);
-  if ((int)(blockIdx.x * kSeqTile) >= t) return;
-  for_incidences(S, t, [&](int, int, int a, int b, int e) {
-    const size_t ca = (size_t)e * S.k + a, cb = (size_t)e * S.k + b;
-    S.cell[ca] = make_int4(0, INT_MAX, 0, 0);
-    S.cell[cb] = make_int4(0, INT_MAX, 0, 0);
-  });
+  for (int tile = blockIdx.x; tile * kSeqTile < t; tile += gridDim.x)
+    for_incidences(S, t, tile, [&](int, int, int a, int b, int e) {
+      const size_t ca = (size_t)e * S.k + a, cb = (size_t)e * S.k + b;
+      S.cell[ca] = make_int4(0, INT_MAX, 0, 0);
+      S.cell[cb] = make_int4(0, INT_MAX, 0, 0);
+    });
 }
 
 __global__ __launch_bounds__(kBlock) void k_seq_collect(Seq S) {
   const int t = seq_len(S);
-  if ((int)(blockIdx.x * kSeqTile) >= t) return;
-  for_incidences(S, t, [&](int j, int, int a, int b, int e) {
-    const size_t ca = (size_t)e * S.k + a, cb = (size_t)e * S.k + b;
-    atomicMax(&S.cell[ca].x, j + 1);
-    atomicAdd(&S.cell[ca].z, 1);
-    atomicMin(&S.cell[cb].y, j + 1);
-  });
+  for (int tile = blockIdx.x; tile * kSeqTile < t; tile += gridDim.x)
+    for_incidences(S, t, tile, [&](int j, int, int a, int b, int e) {
+      const size_t ca = (size_t)e * S.k + a, cb = (size_t)e * S.k + b;
+      atomicMax(&S.cell[ca].x, j + 1);
+      atomicAdd(&S.cell[ca].z, 1);
+      atomicMin(&S.cell[cb].y, j + 1);
+    });
 }
 
 // gains[j] = exact gain of move j (the Lemma).
 __global__ __launch_bounds__(kBlock) void k_seq_gains(Seq S, long long* gains) {
   __shared__ long long s_gain[kSeqTile];
   const int t = seq_len(S);
-  if ((int)(blockIdx.x * kSeqTile) >= t) return;
-  if (threadIdx.x < kSeqTile) s_gain[threadIdx.x] = 0;
-  __syncthreads();
-  for_incidences(S, t, [&](int j, int, int a, int b, int e) {
-    const int J = j + 1;
-    const size_t ca = (size_t)e * S.k + a, cb = (size_t)e * S.k + b;
-    // all four reads first (no short-circuit: loads in branches would not overlap)
-    const int4 A = S.cell[ca], B = S.cell[cb];
-    const int pa = S.phi[ca], pb = S.phi[cb];
-    const bool last_out = (pa - A.z == 0) & (A.x == J) & (A.y > J);
-    const bool first_in = (pb - B.z == 0) & (B.y == J) & (B.x < J);
-    if (last_out != first_in) {
-      const long long w = S.ewgt ? S.ewgt[e] : 1;
-      atomicAdd((unsigned long long*)&s_gain[j - blockIdx.x * kSeqTile],
-                (unsigned long long)(last_out ? w : -w));
-    }
-  });
-  __syncthreads();
-  const int j = blockIdx.x * kSeqTile + threadIdx.x;
-  if (threadIdx.x < kSeqTile && j < t) gains[j] = s_gain[threadIdx.x];
+  for (int tile = blockIdx.x; tile * kSeqTile < t; tile += gridDim.x) {
+    if (threadIdx.x < kSeqTile) s_gain[threadIdx.x] = 0;
+    __syncthreads();
+    for_incidences(S, t, tile, [&](int j, int, int a, int b, int e) {
+      const int J = j + 1;
+      const size_t ca = (size_t)e * S.k + a, cb = (size_t)e * S.k + b;
+      // all four reads first (no short-circuit: loads in branches would not overlap)
+      const int4 A = S.cell[ca], B = S.cell[cb];
+      const int pa = S.phi[ca], pb = S.phi[cb];
+      const bool last_out = (pa - A.z == 0) & (A.x == J) & (A.y > J);
+      const bool first_in = (pb - B.z == 0) & (B.y == J) & (B.x < J);
+      if (last_out != first_in) {
+        const long long w = S.ewgt ? S.ewgt[e] : 1;
+        atomicAdd((unsigned long long*)&s_gain[j - tile * kSeqTile],
+                  (unsigned long long)(last_out ? w : -w));
+      }
+    });
+    const int j = tile * kSeqTile + threadIdx.x;
+    if (threadIdx.x < kSeqTile && j < t) gains[j] = s_gain[threadIdx.x];
+    __syncthreads();
+  }
 }
 
-// Pass input of a monotone round: key = top - gain for marked vertices (so
-// that ascending keys are descending gains) and `none` for the rest; value =
-// id.  With every gain <= top < 255, top = 254 and none = 255 make one 8-bit
-// pass enough; otherwise top = 0x7fffffff, none = 0xffffffff.  The marks are
-// cleared for the next round.
-__global__ __launch_bounds__(kBlock) void k_sort_keys(int n, const long long* cand,
-                                                      unsigned char* appr, unsigned top,
-                                                      unsigned none, unsigned* key, int* val) {
-  const long long u = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (u >= n) return;
-  unsigned k = none;
-  if (appr[u]) {
-    const int g = (int)(cand[u] >> 32);   // select gain, 0 <= g <= top
-    k = top - (unsigned)g;
-    appr[u] = 0;
+// Compaction of a monotone round's marked moves, in vertex-id order (the
+// sort below is stable, so equal gains stay in id order): per chunk of
+// kMarkChunk vertices the number of marks, one workgroup's exclusive scan of
+// those counts (the total is the sequence length), then every marked vertex
+// u writes key = top - select gain (ascending keys are descending gains)
+// and value u at its position, and clears its mark for the next round.
+constexpr int kMarkChunk = 4 * kBlock;
+// the compaction's chunk sums and offsets reuse the prefix scan's arrays
+static_assert(kMarkChunk >= kPrefixChunk, "mark chunks must not outnumber prefix chunks");
+
+__global__ __launch_bounds__(kBlock) void k_mark_count(int n, const unsigned char* appr,
+                                                       long long* csum) {
+  __shared__ long long s_tmp[kBlock / kWave];
+  const long long base = (long long)blockIdx.x * kMarkChunk + (long long)threadIdx.x * 4;
+  int c = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (base + q < n && appr[base + q]) ++c;
+  const long long tot = block_sum64(c, s_tmp);
+  if (threadIdx.x == 0) csum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_mark_offsets(const long long* csum, long long* coff,
+                                                         int chunks, int* t) {
+  __shared__ long long s_tmp[kBlock / kWave];
+  long long carry = 0;
+  for (int b = 0; b < chunks; b += kBlock) {
+    const int i = b + threadIdx.x;
+    const long long v = i < chunks ? csum[i] : 0;
+    long long tot;
+    const long long ex = block_excl_scan64(v, s_tmp, &tot);
+    if (i < chunks) coff[i] = carry + ex;
+    carry += tot;
   }
-  key[u] = k;
-  val[u] = (int)u;
+  if (threadIdx.x == 0) *t = (int)carry;
+}
+
+__global__ __launch_bounds__(kBlock) void k_mark_write(int n, unsigned char* appr,
+                                                       const long long* cand,
+                                                       const long long* coff, unsigned top,
+                                                       unsigned* key, int* val) {
+  __shared__ long long s_tmp[kBlock / kWave];
+  const long long base = (long long)blockIdx.x * kMarkChunk + (long long)threadIdx.x * 4;
+  bool mk[4];
+  int c = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    mk[q] = base + q < n && appr[base + q];
+    c += mk[q];
+  }
+  long long tot;
+  long long pos = coff[blockIdx.x] + block_excl_scan64(c, s_tmp, &tot);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (!mk[q]) continue;
+    const long long u = base + q;
+    const int g = (int)(cand[u] >> 32);   // select gain, 0 <= g <= top
+    key[pos] = top - (unsigned)g;
+    val[pos] = (int)u;
+    appr[u] = 0;
+    ++pos;
+  }
 }
 
 // ------------------------------------------------------------ best prefix
@@ -392,35 +433,37 @@ __global__ __launch_bounds__(kBlock) void k_apply_prefix(Seq S, const long long*
   for (int i = threadIdx.x; i < k; i += kBlock) s_dW[i] = 0;
   __syncthreads();
   long long delta = 0, moved_pins = 0, approved = 0;
-  {
-    const int j = blockIdx.x * kSeqTile + threadIdx.x;
-    int u, a, b;
-    if (threadIdx.x < kSeqTile && j < p && seq_move(S, j, u, a, b)) {
-      const long long cu = D.vwgt ? D.vwgt[u] : 1;
-      atomicAdd(&s_dW[b], (unsigned long long)cu);
-      atomicAdd(&s_dW[a], (unsigned long long)(-cu));
-      approved = 1;
-      moved_pins = D.vptr[u + 1] - D.vptr[u];
-      if (D.moved) D.moved[u] = 1;
+  for (int tile = blockIdx.x; tile * kSeqTile < p; tile += gridDim.x) {
+    {
+      const int j = tile * kSeqTile + threadIdx.x;
+      int u, a, b;
+      if (threadIdx.x < kSeqTile && j < p && seq_move(S, j, u, a, b)) {
+        const long long cu = D.vwgt ? D.vwgt[u] : 1;
+        atomicAdd(&s_dW[b], (unsigned long long)cu);
+        atomicAdd(&s_dW[a], (unsigned long long)(-cu));
+        approved += 1;
+        moved_pins += D.vptr[u + 1] - D.vptr[u];
+        if (D.moved) D.moved[u] = 1;
+      }
+    }
+    // part is read by for_incidences (source blocks): update it only after
+    for_incidences(S, p, tile, [&](int, int, int a, int b, int e) {
+      const int oa = atomicSub(&D.phi[(long long)e * k + a], 1);
+      const int ot = atomicAdd(&D.phi[(long long)e * k + b], 1);
+      if (oa == 1 || ot == 0) {
+        const int w = D.ewgt ? D.ewgt[e] : 1;
+        if (oa == 1) delta += w;
+        if (ot == 0) delta -= w;
+      }
+      D.touched[e] = 1;
+    });
+    {
+      const int j = tile * kSeqTile + threadIdx.x;
+      int u, a, b;
+      if (threadIdx.x < kSeqTile && j < p && seq_move(S, j, u, a, b)) D.part[u] = b;
     }
   }
-  // part is read by for_incidences (source blocks): update it only after
-  for_incidences(S, p, [&](int, int, int a, int b, int e) {
-    const int oa = atomicSub(&D.phi[(long long)e * k + a], 1);
-    const int ot = atomicAdd(&D.phi[(long long)e * k + b], 1);
-    if (oa == 1 || ot == 0) {
-      const int w = D.ewgt ? D.ewgt[e] : 1;
-      if (oa == 1) delta += w;
-      if (ot == 0) delta -= w;
-    }
-    D.touched[e] = 1;
-  });
   __syncthreads();
-  {
-    const int j = blockIdx.x * kSeqTile + threadIdx.x;
-    int u, a, b;
-    if (threadIdx.x < kSeqTile && j < p && seq_move(S, j, u, a, b)) D.part[u] = b;
-  }
   long long* my_dw = D.bw_slots + (size_t)(blockIdx.x % kSlots) * k;
   for (int i = threadIdx.x; i < k; i += kBlock)
     if (s_dW[i]) atomicAdd((unsigned long long*)&my_dw[i], s_dW[i]);
@@ -885,14 +928,21 @@ hipError_t launch_round_exact(hg_graph_s* g, InstDesc d, int round, char* ws, hi
   hipError_t e = fill_u8(d.appr, 0, g->n, s);   // approval marks start cleared
   if (e == hipSuccess) e = launch_round_front(plan, s, nullptr);
   if (e != hipSuccess) return e;
-  // order the marked moves: keys of all n vertices, 8-bit passes over the
-  // bits a gain can occupy (gains are at most the largest incident weight)
+  // the marked moves compacted in id order, then ordered by a stable radix
+  // sort of their keys (8-bit passes over the bits a gain can occupy: gains
+  // are at most the largest incident weight); the count t lives on the device
   const int n = g->n;
   const long long maxw = g->info.max_incident_weight;   // bounds every gain
   const bool one_pass = maxw < 255;
-  hipLaunchKernelGGL(k_sort_keys, dim3(grid_of(n, kBlock)), dim3(kBlock), 0, s, n, d.cand,
-                     d.appr, one_pass ? 254u : 0x7fffffffu, one_pass ? 255u : 0xffffffffu,
-                     (unsigned*)(ws + L.key[0]), (int*)(ws + L.val[0]));
+  int* tdev = (int*)(ws + L.tdev);
+  const int mchunks = (int)((n + kMarkChunk - 1) / kMarkChunk);
+  long long* msum = (long long*)(ws + L.csum);     // L.chunks >= mchunks
+  long long* moff = (long long*)(ws + L.coff);
+  hipLaunchKernelGGL(k_mark_count, dim3(mchunks), dim3(kBlock), 0, s, n, d.appr, msum);
+  hipLaunchKernelGGL(k_mark_offsets, dim3(1), dim3(kBlock), 0, s, msum, moff, mchunks, tdev);
+  hipLaunchKernelGGL(k_mark_write, dim3(mchunks), dim3(kBlock), 0, s, n, d.appr, d.cand, moff,
+                     one_pass ? 254u : 0x7fffffffu, (unsigned*)(ws + L.key[0]),
+                     (int*)(ws + L.val[0]));
   int bits = 1;
   while (bits < 31 && (1ll << bits) <= maxw) ++bits;
   int cur = 0;
@@ -905,6 +955,7 @@ hipError_t launch_round_exact(hg_graph_s* g, InstDesc d, int round, char* ws, hi
     P.hist = (unsigned*)(ws + L.hist);
     P.dtot = (unsigned*)(ws + L.dtot);
     P.n = n;
+    P.n_dev = tdev;
     P.tiles = L.sort_tiles;
     P.shift = shift;
     hipLaunchKernelGGL(k_sort_hist, dim3(L.sort_tiles), dim3(kBlock), 0, s, P);
@@ -915,19 +966,17 @@ hipError_t launch_round_exact(hg_graph_s* g, InstDesc d, int round, char* ws, hi
   if (one_pass) {
     pass(0);
   } else {
-    // keys 0x7fffffff - g differ from 0x7fffffff only in the low `bits`
-    // bits, unmarked keys (all ones) in bit 31: the low bits, then bit 31
+    // keys 0x7fffffff - g differ from 0x7fffffff only in the low `bits` bits
     for (int shift = 0; shift < bits; shift += 8) pass(shift);
-    pass(24);
   }
   // exact gains of the sorted sequence, best prefix, apply it
   Seq S = make_seq(g, d.k, ws, L, d.part, d.phi, (const int*)(ws + L.val[cur]), nullptr, 0);
   S.cand = d.cand;
-  int* tdev = (int*)(ws + L.tdev);
   S.t_dev = tdev;
-  hipLaunchKernelGGL(k_count_marked, dim3(1), dim3(kWave), 0, s, d.ctr->slot[kCtrMarked], tdev);
   long long* gains = (long long*)(ws + L.gains);
-  const unsigned tiles = grid_of(n, kSeqTile);
+  // persistent grids: the kernels stride over the sequence's tiles, whose
+  // count is known only on the device
+  const unsigned tiles = std::min(grid_of(n, kSeqTile), (unsigned)kSeqGrid);
   hipLaunchKernelGGL(k_seq_init, dim3(tiles), dim3(kBlock), 0, s, S);
   hipLaunchKernelGGL(k_seq_collect, dim3(tiles), dim3(kBlock), 0, s, S);
   hipLaunchKernelGGL(k_seq_gains, dim3(tiles), dim3(kBlock), 0, s, S, gains);

@@ -1,7 +1,7 @@
 // hg_scan.h -- exclusive prefix sums (int64) of n values f(0) .. f(n-1)
 // given by a device functor, in three launches: per-chunk sums, one
 // workgroup scanning the chunk sums (and writing the grand total), and the
-// chunk scans plus their offsets.  A chunk is kTile values, four consecutive
+// chunk scans plus their offsets.  A chunk is 1024 values, four consecutive
 // ones per thread.  Included by each source file that scans (the kernels
 // have internal linkage there).
 #pragma once
@@ -12,7 +12,7 @@
 namespace hg {
 namespace {
 
-constexpr int kScanChunk = kTile;
+constexpr int kScanChunk = 4 * kBlock;
 constexpr int kScanPer = kScanChunk / kBlock;
 
 template <class F>

@@ -12,7 +12,7 @@
 namespace hg {
 namespace {
 
-constexpr int kSortTile = 4 * kTile;        // items per radix-sort workgroup (16 per thread)
+constexpr int kSortTile = 16 * kBlock;      // items per radix-sort workgroup (16 per thread)
 constexpr int kSortPer = kSortTile / kBlock;
 constexpr int kDigits = 256;                // 8-bit digits
 
@@ -24,7 +24,12 @@ struct SortPass {
   unsigned* hist;   // [kDigits][tiles], digit-major
   unsigned* dtot;   // [kDigits]
   int n, tiles, shift;
+  // when set, the item count is *n_dev (known only on the device, at most n;
+  // tiles past it are empty)
+  const int* n_dev = nullptr;
 };
+
+__device__ __forceinline__ int sort_items(const SortPass& P) { return P.n_dev ? *P.n_dev : P.n; }
 
 __device__ __forceinline__ unsigned digit_of(unsigned key, int shift) {
   return (key >> shift) & (kDigits - 1);
@@ -32,6 +37,7 @@ __device__ __forceinline__ unsigned digit_of(unsigned key, int shift) {
 
 __global__ __launch_bounds__(kBlock) void k_sort_hist(SortPass P) {
   __shared__ unsigned s_h[kDigits];
+  const int n = sort_items(P);
   s_h[threadIdx.x] = 0;
   __syncthreads();
   const long long base = (long long)blockIdx.x * kSortTile;
@@ -39,11 +45,11 @@ __global__ __launch_bounds__(kBlock) void k_sort_hist(SortPass P) {
 #pragma unroll
   for (int r = 0; r < kSortPer; ++r) {
     const long long i = base + r * kBlock + threadIdx.x;
-    key[r] = i < P.n ? P.key_in[i] : 0u;
+    key[r] = i < n ? P.key_in[i] : 0u;
   }
 #pragma unroll
   for (int r = 0; r < kSortPer; ++r)
-    if (base + r * kBlock + threadIdx.x < P.n) atomicAdd(&s_h[digit_of(key[r], P.shift)], 1u);
+    if (base + r * kBlock + threadIdx.x < n) atomicAdd(&s_h[digit_of(key[r], P.shift)], 1u);
   __syncthreads();
   P.hist[(size_t)threadIdx.x * P.tiles + blockIdx.x] = s_h[threadIdx.x];
 }
@@ -77,14 +83,16 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(SortPass P) {
   __shared__ unsigned s_wcnt[kBlock / kWave][kDigits];
   __shared__ long long s_tmp[kBlock / kWave];
   const long long base = (long long)blockIdx.x * kSortTile;
+  const int n = sort_items(P);
+  if (base >= n) return;                  // an empty tile (device-side count)
   // every item of the tile requested before the first wait
   unsigned key[kSortPer];
   int val[kSortPer];
 #pragma unroll
   for (int r = 0; r < kSortPer; ++r) {
     const long long i = base + r * kBlock + threadIdx.x;
-    key[r] = i < P.n ? P.key_in[i] : 0u;
-    val[r] = i < P.n ? P.val_in[i] : 0;
+    key[r] = i < n ? P.key_in[i] : 0u;
+    val[r] = i < n ? P.val_in[i] : 0;
   }
   {
     // digit d = threadIdx.x: its count in this tile is the difference of the
@@ -105,7 +113,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(SortPass P) {
   const unsigned long long lt = (1ull << lane) - 1ull;
 #pragma unroll
   for (int r = 0; r < kSortPer; ++r) {
-    const bool live = base + r * kBlock + threadIdx.x < P.n;
+    const bool live = base + r * kBlock + threadIdx.x < n;
     const unsigned d = digit_of(key[r], P.shift);
     // lanes of this wave with the same digit
     unsigned long long peers = __ballot(live);
@@ -132,7 +140,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(SortPass P) {
     s_run[threadIdx.x] += add;
     __syncthreads();
   }
-  const long long left = (long long)P.n - base;
+  const long long left = (long long)n - base;
   const int count = left < kSortTile ? (int)left : kSortTile;
   for (int j = threadIdx.x; j < count; j += kBlock) {
     const unsigned k = s_key[j];

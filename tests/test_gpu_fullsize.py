@@ -4,16 +4,17 @@ The sparse-matrix workload (1M x 1M, about 10M pins) at k = 8 and k = 64
 and the VLSI-like netlist (4M cells, 4.2M nets, about 56.5M pins) at k = 16
 run round by round through hg_lp_round, in the launch configuration the
 benchmark times (one persistent select grid sweeping many 256-vertex chunks
-per workgroup; 977 and 3,907 approval tiles, so the tile scan carries its
-sum from one 2,048-tile span into the next).  After every round the
+per workgroup; 1,954 and 7,813 approval tiles of 512 vertices, so the tile
+scan carries its sum across 2,048-tile spans).  After every round the
 partition, the moved and eligible flags and the round record must equal the
 oracle's; the whole state (Phi, the net records, block weights) is checked
 after the first and the last round; then hg_refine (direct launches, as
 timed) must reach the same final partition and records.
 
 Two constructed cases reach approval paths the benchmark workloads do not:
-a 2.2M-vertex instance whose approval boundary lies in the second span of
-the tile scan, and heavy vertices whose gains (>= 255) share the top gain
+a 2.2M-vertex instance whose approval boundary lies in the third span of
+the tile scan (its budget crosses two spans first), and heavy vertices
+whose gains (>= 255) share the top gain
 bucket while their target's budget runs out inside that bucket (the exact
 threshold is then found by bisection over the candidates).
 """
@@ -112,8 +113,8 @@ def test_sparse_matrix_k64_three_rounds(H):
 def test_vlsi_netlist_k16_all_rounds(H):
     inst = synth.vlsi_grid()
     assert inst.n == 4_000_000 and inst.m == 4_200_000 and inst.k == 16
-    # 3,907 approval tiles: the tile scan crosses into its second span
-    assert (inst.n + 1023) // 1024 > 2048
+    # 7,813 approval tiles: the tile scan crosses several 2,048-tile spans
+    assert (inst.n + 511) // 512 > 3 * 2048
     _, recs = _rounds_vs_oracle(H, inst, 10, {0, 9})
     assert sum(r["approved"] for r in recs) > 0
 
@@ -139,10 +140,11 @@ def _pairs_instance(n, us, budget):
                           np.ones(len(nets), np.int32), part, 2, 0.03, 1)
 
 
-def test_tile_scan_second_span_boundary(H):
-    """n = 2.2M: 2,149 approval tiles.  Block 1 admits 500 of its 800
-    gain-1 candidates: 400 lie in the first 2,048 tiles, so the boundary is
-    the 100th candidate of the second span."""
+def test_tile_scan_later_span_boundary(H):
+    """n = 2.2M: 4,297 approval tiles of 512 vertices.  Block 1 admits 500
+    of its 800 gain-1 candidates: 400 lie below vertex 2M (the first two
+    2,048-tile spans), so the boundary is the 100th candidate of the third
+    span."""
     import torch
     n = 2_200_000
     rng = np.random.default_rng(21)
@@ -159,7 +161,7 @@ def test_tile_scan_second_span_boundary(H):
     torch.cuda.synchronize()
     part_o, elig_o, moved_o, st_o = O.lp_round(h, 2, L, inst.part, np.ones(n, np.uint8))
     # the oracle itself: exactly 500 of the block-0 candidates moved, the
-    # first 400 plus the first 100 of the second span
+    # first 400 plus the first 100 of those past vertex 2.1M
     moved_u = np.flatnonzero(moved_o & (inst.part == 0))
     assert moved_u.tolist() == lo + hi[:100]
     sg = H.stats_to_dicts(stats)[0]
