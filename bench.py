@@ -363,18 +363,27 @@ def served_leg(args, H, dev):
             h["parts"][req.k] = pinned(synth.with_k(h["inst"], req.k).part, torch.int32)
         return h
 
-    def outputs(n, rounds):
-        return (torch.empty(n, dtype=torch.int32, pin_memory=True),
-                torch.zeros(rounds * H.STATS_WORDS, dtype=torch.int64, pin_memory=True),
-                torch.zeros(1, dtype=torch.int64, pin_memory=True))
-
     reqs = [(r, host_of(r)) for r in trace]
+    # every request's results in three page-locked slabs (one allocation each
+    # instead of three per request), cleared before each run
+    n_off = np.cumsum([0] + [h["inst"].n for r, h in reqs])
+    s_off = np.cumsum([0] + [r.rounds * H.STATS_WORDS for r, h in reqs])
+    slab = (torch.zeros(int(n_off[-1]), dtype=torch.int32, pin_memory=True),
+            torch.zeros(int(s_off[-1]), dtype=torch.int64, pin_memory=True),
+            torch.zeros(len(reqs), dtype=torch.int64, pin_memory=True))
+
+    def outputs_all():
+        for x in slab:
+            x.zero_()
+        return [(slab[0][n_off[i]:n_off[i + 1]], slab[1][s_off[i]:s_off[i + 1]],
+                 slab[2][i:i + 1]) for i in range(len(reqs))]
+
     pin_rounds = sum(h["inst"].P * r.rounds for r, h in reqs)
     print("served: %d requests (%d big), %.2e pin-rounds" % (
         len(reqs), sum(r.big for r in trace), pin_rounds), file=sys.stderr, flush=True)
 
     def run_served(burst):
-        outs = [outputs(h["inst"].n, r.rounds) for r, h in reqs]
+        outs = outputs_all()
         srv = H.hg_server_create(SERVED_BUDGET + SERVED_TABLE, table_bytes=SERVED_TABLE,
                                  max_active=256, device=dev, big_pins=SERVED_BIG_PINS)
         clock = lambda: H.hg_server_now_ms(srv)          # noqa: E731
@@ -399,7 +408,7 @@ def served_leg(args, H, dev):
         return res, outs
 
     def run_plain(burst):
-        outs = [outputs(h["inst"].n, r.rounds) for r, h in reqs]
+        outs = outputs_all()
         clock = lambda: time.perf_counter() * 1e3        # noqa: E731
         start = clock() + 20.0
         lat, t_last = [], start
@@ -429,13 +438,14 @@ def served_leg(args, H, dev):
     for mode in ("open_loop", "burst"):
         burst = mode == "burst"
         print("served: %s, server ..." % mode, file=sys.stderr, flush=True)
-        srv_res, srv_out = run_served(burst)
+        srv_res, _ = run_served(burst)
+        served = [x.numpy().copy() for x in slab]
         print("served: %s, plain one-at-a-time ..." % mode, file=sys.stderr, flush=True)
-        pl_res, pl_out = run_plain(burst)
-        for (r, h), a, b in zip(reqs, srv_out, pl_out):
-            n = h["inst"].n
-            assert torch.equal(a[0][:n], b[0][:n]), "served partition differs from plain"
-            assert torch.equal(a[1], b[1]) and torch.equal(a[2], b[2]), "served stats differ"
+        pl_res, _ = run_plain(burst)
+        assert np.array_equal(served[0], slab[0].numpy()), "served partition differs from plain"
+        assert np.array_equal(served[1], slab[1].numpy()), "served round records differ"
+        assert np.array_equal(served[2], slab[2].numpy()), "served km1 differs"
+        del served
         res[mode] = {"served": srv_res, "plain": pl_res}
     res["check"] = ("every served request's partition, round records and km1 identical to the "
                     "plain one-at-a-time path, in both modes")
@@ -1025,6 +1035,31 @@ def headline(args, rec, workload, config_extra):
 def plain_legs(args, H, dev):
     """The plain workloads: the VLSI-like netlist (the headline), the
     sparse matrix and the tiny instance."""
+    import synth
+    which = set(args.plain_workloads.split(","))
+    out = {"metric": METRIC}
+    if "vlsi" in which:
+        out = vlsi_headline(args, H, dev)
+    if "sparse" in which:
+        sp = sparse_instance()
+        srec = plain_workload(args, H, dev, sp, KS, ROUNDS, "sparse",
+                              {8: ROUNDS, 64: args.cpu_rounds_k64})
+        srec["roofline"]["traffic"] = measured_traffic("plain_sparse_matrix_traffic.md", "select")
+        srec["config"] = ("sparse-matrix row-net hypergraph 1M x 1M (%d pins), k = 8 and k = 64, "
+                          "eps = 0.03, 10 synchronous LP rounds per k; one step = load + (pin "
+                          "counts + 10 rounds + gains + km1) per k" % sp.P)
+        out["sparse_matrix"] = srec
+        del sp
+    if "tiny" in which:
+        tiny = synth.tiny_plain()
+        trec = plain_workload(args, H, dev, tiny, (2,), 5, "tiny", {2: 5}, roofline=False)
+        trec["config"] = "tiny power-law hypergraph n = m = 10,000 (%d pins), k = 2, 5 rounds" % tiny.P
+        out["tiny"] = trec
+    return out
+
+
+def vlsi_headline(args, H, dev):
+    """The headline line: the VLSI-like netlist at its own k."""
     import torch
     import synth
     print("generating the VLSI-like netlist ...", file=sys.stderr, flush=True)
@@ -1041,19 +1076,6 @@ def plain_legs(args, H, dev):
                     "eps": vl.eps, "seed": 3})
     out["vlsi"] = {x: rec[x] for x in ("per_k", "round_latency", "graph_refine_ms",
                                         "km1_final", "check") if x in rec}
-    del vl
-    sp = sparse_instance()
-    srec = plain_workload(args, H, dev, sp, KS, ROUNDS, "sparse",
-                          {8: ROUNDS, 64: args.cpu_rounds_k64})
-    srec["roofline"]["traffic"] = measured_traffic("plain_sparse_matrix_traffic.md", "select")
-    srec["config"] = ("sparse-matrix row-net hypergraph 1M x 1M (%d pins), k = 8 and k = 64, "
-                      "eps = 0.03, 10 synchronous LP rounds per k; one step = load + (pin counts "
-                      "+ 10 rounds + gains + km1) per k" % sp.P)
-    out["sparse_matrix"] = srec
-    tiny = synth.tiny_plain()
-    trec = plain_workload(args, H, dev, tiny, (2,), 5, "tiny", {2: 5}, roofline=False)
-    trec["config"] = "tiny power-law hypergraph n = m = 10,000 (%d pins), k = 2, 5 rounds" % tiny.P
-    out["tiny"] = trec
     return out
 
 
@@ -1071,6 +1093,9 @@ def main():
     ap.add_argument("--legs", default="plain,batched,served,monotone,cached,rebalance,contract",
                     help="comma list of plain, batched, served, monotone, cached, rebalance, "
                          "contract")
+    ap.add_argument("--plain-workloads", default="vlsi,sparse,tiny",
+                    help="comma list of the plain leg's workloads: vlsi (the headline line), "
+                         "sparse, tiny")
     ap.add_argument("--mono-reps", type=int, default=3)
     ap.add_argument("--served-seconds", type=float, default=60.0,
                     help="length of the open-loop request trace (60 s: about 12,000 requests)")

@@ -156,7 +156,7 @@ size_t build_plans(const std::vector<BatchMember>& mem, const std::vector<int>& 
     const int k = M.k;
     const int G = net_lanes(k, S.net_lanes);
     if (rp) {
-      add_split(*variant(sel, (void*)select_kernel(k, d.view)), i, ceil_div(g->n, kBlock),
+      add_split(*variant(sel, (void*)select_kernel(k, d.view, d.P, d.n)), i, ceil_div(g->n, kBlock),
                 S.select_chunks, home[i]);
       add_split(*variant(fin, (void*)finalize_kernel_g(G, false)), i, ceil_div(g->m, kFinalChunk),
                 S.finalize_chunks, home[i]);

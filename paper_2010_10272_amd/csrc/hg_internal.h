@@ -26,7 +26,7 @@ constexpr int kSmallRow = 64;          // incidence rows up to this length sort 
 constexpr int kNumXcd = 8;             // MI355X: 8 XCDs, each with its own L2
 constexpr int kLdsHistEntries = 2048;  // per-workgroup LDS gain histogram (k * buckets)
 constexpr int kSelectGrid = 2048;      // persistent workgroups of the select sweep
-constexpr int kUnroll = 4;             // record gathers in flight per thread in the sweeps
+constexpr int kUnroll = 4;             // record gathers in flight per thread in the gains sweep
 constexpr int kFinalizeGrid = 2048;    // persistent workgroups of the finalize sweep
 
 // Validation bits raised on the device.
@@ -142,6 +142,7 @@ struct InstDesc {
   unsigned long long* red;
   long long* bw_slots;           // kSlots x k block-weight deltas of a round's moves
   unsigned char* appr;           // monotone rounds: approve marks moves here instead of applying
+  int4* seq_cell;                // monotone rounds: per (net, block) cells the marking sets empty
   int* cache;                    // gain cache (b[n], w(I)[n], p[n*k]); null: none
 };
 

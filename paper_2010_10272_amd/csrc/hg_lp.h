@@ -41,7 +41,7 @@ struct CountPlan {
 
 constexpr int kBwChunk = kBlock * 16;   // vertices per unit of the block-weight sweep
 
-SelectKernel select_kernel(int k, int view);
+SelectKernel select_kernel(int k, int view, long long P, int n);
 // lanes per net: group_lanes(k); cache: the variant that also applies the
 // gain-cache deltas (it must be used exactly when the descriptor has a cache)
 FinalizeKernel finalize_kernel(int k, bool cache);

@@ -91,7 +91,7 @@ __device__ __forceinline__ WorkItem single_unit(int unit) {
 // the final flush go to the histogram replica of this workgroup's XCD.
 constexpr int kDenseWave = 3 * kWave / 4;   // eligible lanes that make a wave's slice dense
 
-template <int WK, int VIEW>
+template <int WK, int VIEW, int U>
 __global__ __launch_bounds__(kBlock) void k_select_light(Launch L) {
   __shared__ long long s_W[HG_MAX_K];
   __shared__ unsigned s_open[WK];
@@ -150,25 +150,26 @@ __global__ __launch_bounds__(kBlock) void k_select_light(Launch L) {
     bool bnd = false, heavy = false;
     const int aw = a >> 5;
     const unsigned abit = 1u << (a & 31);
-    // Software-pipelined sweep: issue kUnroll independent record gathers
-    // before consuming any of them.  Slots past the row end load the row's
+    // Software-pipelined sweep: issue U independent record gathers before
+    // consuming any of them (U = 8 for average degrees of 12 and more, else
+    // 4).  Slots past the row end load the row's
     // first entry again (always valid) and are masked afterwards, so no load
     // sits in a branch of its own.  With unit nets w(I(u)) is the degree,
     // which the row length already bounds, so only weighted nets are
     // watched for the heavy limit.
     const int deg = (int)(b1 - b0);
     const auto row = global_ptr(vnets + b0);
-    for (int jj = 0; jj < deg; jj += kUnroll) {
-      unsigned w[kUnroll], S[kUnroll], Lb[kUnroll][WK];
-      bool cut[kUnroll];
-      int e[kUnroll];
+    for (int jj = 0; jj < deg; jj += U) {
+      unsigned w[U], S[U], Lb[U][WK];
+      bool cut[U];
+      int e[U];
 #pragma unroll
-      for (int q = 0; q < kUnroll; ++q) e[q] = row[jj + q < deg ? jj + q : jj];
+      for (int q = 0; q < U; ++q) e[q] = row[jj + q < deg ? jj + q : jj];
 #pragma unroll
-      for (int q = 0; q < kUnroll; ++q)
+      for (int q = 0; q < U; ++q)
         read_net<WK, VIEW>(netstate, rw, view, e[q], aw, w[q], cut[q], Lb[q], S[q]);
 #pragma unroll
-      for (int q = 0; q < kUnroll; ++q) {
+      for (int q = 0; q < U; ++q) {
         if (jj + q >= deg) {
           w[q] = 0;
           cut[q] = false;
@@ -178,20 +179,20 @@ __global__ __launch_bounds__(kBlock) void k_select_light(Launch L) {
         }
       }
 #pragma unroll
-      for (int q = 0; q < kUnroll; ++q) {
+      for (int q = 0; q < U; ++q) {
         bnd |= cut[q];
         if (S[q] & abit) ben += (int)w[q];
       }
       if constexpr (VIEW == kViewFull) {
 #pragma unroll
-        for (int q = 0; q < kUnroll; ++q) tot += (int)w[q];
+        for (int q = 0; q < U; ++q) tot += (int)w[q];
         if (tot > kLightLimit) {
           heavy = true;
           break;
         }
       }
 #pragma unroll
-      for (int q = 0; q < kUnroll; ++q) {
+      for (int q = 0; q < U; ++q) {
         if constexpr (VIEW != kViewFull) {
           C.add_one(Lb[q]);               // unit nets (masked slots add nothing)
         } else if (w[q]) {
@@ -816,6 +817,17 @@ __global__ __launch_bounds__(kBlock) void k_tilescan(Launch L) {
 // spread over the workgroup).  Phi is updated with integer atomics whose old
 // values give the attributed km1 change; every incident net gets its touched
 // flag (a plain byte store: all writers store the same value).
+// The mover owning flattened incidence j: the largest i < count with
+// s_off[i] <= j.
+__device__ __forceinline__ int list_owner(const int* s_off, int count, long long j) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (s_off[mid] <= j) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 __device__ void apply_list(const InstDesc& D, const int* s_list, const int* s_tgt, int count,
                            int* s_from, long long* s_beg, int* s_off, long long* s_tmp,
                            unsigned long long* s_dW, long long& delta, long long& moved_pins,
@@ -856,12 +868,7 @@ __device__ void apply_list(const InstDesc& D, const int* s_list, const int* s_tg
   __syncthreads();
   const int k = D.k;
   for (long long j = threadIdx.x; j < total; j += kBlock) {
-    // owner: largest i < count with s_off[i] <= j
-    int lo = 0, hi = count - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (s_off[mid] <= j) lo = mid; else hi = mid - 1;
-    }
+    const int lo = list_owner(s_off, count, j);
     const int e = D.vnets[s_beg[lo] + (j - s_off[lo])];
     const int ao = s_from[lo], to = s_tgt[lo];
     const int oa = atomicSub(&D.phi[(long long)e * k + ao], 1);
@@ -872,6 +879,47 @@ __device__ void apply_list(const InstDesc& D, const int* s_list, const int* s_tg
       if (ot == 0) delta -= w;    // Phi(e, t) rises from zero
     }
     D.touched[e] = 1;
+  }
+}
+
+// Monotone rounds: mark the approved moves, and set the cells (e, source) and
+// (e, target) of their incident nets empty for the exact-gain kernels that
+// follow (out_max 0, in_min "none", out_cnt 0); the incidences are spread
+// over the workgroup as in apply_list.
+__device__ void mark_list(const InstDesc& D, const int* s_list, const int* s_tgt, int count,
+                          int* s_from, long long* s_beg, int* s_off, long long* s_tmp) {
+  long long my_len = 0;
+  int lens[kPerThreadTile];
+  const int first = threadIdx.x * kPerThreadTile;
+#pragma unroll
+  for (int q = 0; q < kPerThreadTile; ++q) {
+    const int i = first + q;
+    lens[q] = 0;
+    if (i < count) {
+      const int u = s_list[i];
+      const long long b = D.vptr[u];
+      D.appr[u] = 1;
+      s_from[i] = D.part[u];
+      s_beg[i] = b;
+      lens[q] = (int)(D.vptr[u + 1] - b);
+      my_len += lens[q];
+    }
+  }
+  long long total;
+  long long off = block_excl_scan64(my_len, s_tmp, &total);
+#pragma unroll
+  for (int q = 0; q < kPerThreadTile; ++q) {
+    if (first + q < count) s_off[first + q] = (int)off;
+    off += lens[q];
+  }
+  __syncthreads();
+  const int k = D.k;
+  const int4 empty = make_int4(0, 0x7fffffff, 0, 0);
+  for (long long j = threadIdx.x; j < total; j += kBlock) {
+    const int lo = list_owner(s_off, count, j);
+    const long long e = D.vnets[s_beg[lo] + (j - s_off[lo])];
+    D.seq_cell[e * k + s_from[lo]] = empty;
+    D.seq_cell[e * k + s_tgt[lo]] = empty;
   }
 }
 
@@ -974,7 +1022,7 @@ __global__ __launch_bounds__(kBlock) void k_approve_apply(Launch L) {
   long long delta = 0, moved_pins = 0, approved = 0;
   if (count > 0 && D.appr) {
     // monotone round: only mark; the moves are ordered, re-gained and cut later
-    for (int i = threadIdx.x; i < count; i += kBlock) D.appr[s_list[i]] = 1;
+    mark_list(D, s_list, s_tgt, count, s_from, s_beg, s_off, s_tmp);
     if (threadIdx.x == 0)
       atomicAdd(&D.ctr->slot[kCtrMarked][blockIdx.x % kSlots], (unsigned long long)count);
   } else if (count > 0) {
@@ -1070,6 +1118,72 @@ __device__ void cache_net_delta(const InstDesc& D, long long e, int wk, int gl, 
   }
 }
 
+// Gain-cache rounds: the same record rebuild, with the cache deltas of each
+// touched net applied by its group while it walks the net's pins (and marks
+// them eligible).  Unit: a chunk of kCachedChunk nets, one touched flag per
+// thread; many small units keep the atomics-heavy pin walks spread over
+// the whole GPU.
+constexpr int kCachedChunk = kBlock;
+constexpr int kCachedGrid = 16384;   // persistent workgroups of the cached finalize
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_finalize_cached(Launch L) {
+  __shared__ int s_list[kCachedChunk];
+  __shared__ long long s_tmp[kBlock / kWave];
+  __shared__ unsigned s_cnt;
+  constexpr int kGroups = kBlock / G;
+  const WorkItem wi = work_item(L, xcd_block((L.one.m + kCachedChunk - 1) / kCachedChunk));
+  if (wi.count == 0) return;
+  const InstDesc D = inst_desc(L, wi.inst);
+  const int grp = threadIdx.x / G, gl = threadIdx.x % G;
+  const int k = D.k, wk = bit_words(k), rw = D.rw;
+  long long dcheck = 0, ntouched = 0, tpins = 0;
+  for (int it = 0; it < wi.count; ++it) {
+    const long long c = (long long)wi.first + (long long)it * wi.stride;
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
+    // one flag per thread (the flag array is padded to whole chunks, zero past m)
+    const long long e0 = c * kCachedChunk + threadIdx.x;
+    const bool t0 = D.touched[e0] != 0;
+    const int slot = wave_append(&s_cnt, t0);
+    if (t0) s_list[slot] = (int)e0;
+    __syncthreads();
+    const int cnt = (int)s_cnt;
+    ntouched += cnt;
+    for (int i = grp; i < cnt; i += kGroups) {
+      const int e = s_list[i];
+      const int* row = D.phi + (long long)e * k;
+      unsigned* rec = D.netstate + (long long)e * rw;
+      int lam_old = 0, w = 0;
+      if (gl == 1) {
+        lam_old = (int)rec[1];
+        w = (int)rec[0];
+      }
+      // the record's Lambda / S words before this round
+      const unsigned old_word = gl >= 2 && gl < 2 + 2 * wk ? rec[gl] : 0u;
+      NetBits nb = net_bits<G>(k, gl, [&](int i2) { return row[i2]; });
+      if (gl >= 1 && gl < 2 + 2 * wk) rec[gl] = nb.word;
+      if (D.view != kViewFull) write_view(D.view_ptr, e, D.view, gl, nb);
+      if (gl == 1) dcheck += (long long)(lam_old - nb.lambda) * w;
+      const long long b = D.eptr[e], t = D.eptr[e + 1];
+      if (gl == 0) {
+        D.touched[e] = 0;
+        tpins += t - b;
+      }
+      cache_net_delta<G>(D, e, wk, gl, old_word, nb.word, b, t);
+    }
+    __syncthreads();
+  }
+  dcheck = block_sum64(dcheck, s_tmp);
+  tpins = block_sum64(tpins, s_tmp);
+  if (threadIdx.x == 0) {
+    const int sl = blockIdx.x % kSlots;
+    if (dcheck) atomicAdd(&D.ctr->slot[kCtrDeltaCheck][sl], (unsigned long long)dcheck);
+    if (ntouched) atomicAdd(&D.ctr->slot[kCtrTouched][sl], (unsigned long long)ntouched);
+    if (tpins) atomicAdd(&D.ctr->slot[kCtrTouchedPins][sl], (unsigned long long)tpins);
+  }
+}
+
 // Unit: a block of kFinalChunk (1024) nets.  Every thread reads four touched
 // flags with one load; the touched nets of the block are listed in LDS.
 // Groups of G lanes then rebuild each listed net's Lambda, S and lambda from
@@ -1083,7 +1197,7 @@ __device__ void cache_net_delta(const InstDesc& D, long long e, int wk, int gl, 
 // instance: contiguous XCD-aware runs of blocks.
 constexpr int kMarkSlots = 4;   // pin positions per thread in flight in the marks
 
-template <int G, bool CACHE>
+template <int G>
 __global__ __launch_bounds__(kBlock) void k_finalize(Launch L) {
   __shared__ int s_list[kFinalChunk];
   __shared__ int s_off[kFinalChunk];        // first flattened pin position of each listed net
@@ -1128,8 +1242,6 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Launch L) {
         lam_old = (int)rec[1];
         w = (int)rec[0];
       }
-      // gain cache: the record's Lambda / S words before this round
-      const unsigned old_word = CACHE && gl >= 2 && gl < 2 + 2 * wk ? rec[gl] : 0u;
       const long long b = D.eptr[e], t = D.eptr[e + 1];
       NetBits nb = net_bits<G>(k, gl, [&](int i2) { return row[i2]; });
       if (gl >= 1 && gl < 2 + 2 * wk) rec[gl] = nb.word;
@@ -1141,9 +1253,8 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Launch L) {
         s_beg[i] = (int)b;
         s_off[i] = (int)(t - b);          // the length, until the scan below
       }
-      if constexpr (CACHE) cache_net_delta<G>(D, e, wk, gl, old_word, nb.word, b, t);
     }
-    if constexpr (!CACHE) {
+    {
       __syncthreads();
       // flattened pin positions: exclusive prefix of the lengths (four list
       // entries per thread)
@@ -1273,19 +1384,27 @@ __global__ __launch_bounds__(kBlock) void k_round_stats(Launch L) {
 int group_lanes(int k);
 
 // Kernel selection per instance shape (shared with the batch planner).
-SelectKernel select_kernel(int k, int view) {
+// Record gathers in flight per vertex: eight where the average degree is
+// 12 or more (half the dependent load steps for the typical vertex), four
+// below (eight would mostly load padding slots).
+template <int U>
+SelectKernel select_kernel_u(int k, int view) {
   switch (view) {
-    case kView16: return k_select_light<1, kView16>;
-    case kView32: return k_select_light<1, kView32>;
-    case kView64: return k_select_light<2, kView64>;
+    case kView16: return k_select_light<1, kView16, U>;
+    case kView32: return k_select_light<1, kView32, U>;
+    case kView64: return k_select_light<2, kView64, U>;
     default: break;
   }
   switch (bit_words(k)) {
-    case 1: return k_select_light<1, kViewFull>;
-    case 2: return k_select_light<2, kViewFull>;
-    case 4: return k_select_light<4, kViewFull>;
-    default: return k_select_light<8, kViewFull>;
+    case 1: return k_select_light<1, kViewFull, U>;
+    case 2: return k_select_light<2, kViewFull, U>;
+    case 4: return k_select_light<4, kViewFull, U>;
+    default: return k_select_light<8, kViewFull, U>;
   }
+}
+
+SelectKernel select_kernel(int k, int view, long long P, int n) {
+  return P >= 12LL * n ? select_kernel_u<8>(k, view) : select_kernel_u<4>(k, view);
 }
 
 // The plain finalize reads one Phi row and writes one record per net: for
@@ -1300,10 +1419,10 @@ FinalizeKernel finalize_kernel(int k, bool cache) {
 // needs far fewer registers (more workgroups per compute unit).
 FinalizeKernel finalize_kernel_g(int G, bool cache) {
   switch (G) {
-    case 4: return cache ? k_finalize<4, true> : k_finalize<4, false>;
-    case 8: return cache ? k_finalize<8, true> : k_finalize<8, false>;
-    case 16: return cache ? k_finalize<16, true> : k_finalize<16, false>;
-    default: return cache ? k_finalize<32, true> : k_finalize<32, false>;
+    case 4: return cache ? k_finalize_cached<4> : k_finalize<4>;
+    case 8: return cache ? k_finalize_cached<8> : k_finalize<8>;
+    case 16: return cache ? k_finalize_cached<16> : k_finalize<16>;
+    default: return cache ? k_finalize_cached<32> : k_finalize<32>;
   }
 }
 
@@ -1363,7 +1482,7 @@ void single_round_plan(const InstDesc& d, RoundPlan& plan) {
   const Launch L = single_launch(d);
   const long long chunks = ((long long)d.n + kBlock - 1) / kBlock;
   PlanLaunch sel;
-  sel.kernel = (void*)select_kernel(d.k, d.view);
+  sel.kernel = (void*)select_kernel(d.k, d.view, d.P, d.n);
   sel.grid = (unsigned)(chunks < kSelectGrid ? chunks : kSelectGrid);
   sel.L = L;
   plan.select.push_back(sel);
@@ -1382,8 +1501,10 @@ void single_round_plan(const InstDesc& d, RoundPlan& plan) {
   plan.approve.L = L;
   PlanLaunch fin;
   fin.kernel = (void*)finalize_kernel(d.k, d.cache != nullptr);
-  long long fchunks = ((long long)d.m + kFinalChunk - 1) / kFinalChunk;
-  fin.grid = (unsigned)(fchunks < kFinalizeGrid ? fchunks : kFinalizeGrid);
+  const long long unit = d.cache ? kCachedChunk : kFinalChunk;
+  const long long cap = d.cache ? kCachedGrid : kFinalizeGrid;
+  long long fchunks = ((long long)d.m + unit - 1) / unit;
+  fin.grid = (unsigned)(fchunks < cap ? fchunks : cap);
   fin.L = L;
   plan.finalize.push_back(fin);
   plan.stats.grid = 1;

@@ -10,8 +10,11 @@
 //   in_min(e, i)   the smallest J moving a pin of e into i     (INT_MAX if none)
 //   out_cnt(e, i)  how many moves take a pin of e out of i
 // with integer atomics (max, min, add: order-independent) on one 16-byte cell
-// per (net, block), so a move touches one cache line per cell, and then, per move
-// and incident net e, Psi(e, i) = Phi(e, i) - out_cnt(e, i) and the Lemma:
+// per (net, block), so a move touches one cache line per cell.  A cell with
+// Phi(e, i) = 1 has at most one mover out of i, which stores out_max with a
+// plain store; its out_cnt is then (out_max > 0) and is never counted.  Then,
+// per move and incident net e, Psi(e, i) = Phi(e, i) - out_cnt(e, i) and the
+// Lemma:
 //   Phi(e, a) = 1 just before move J  iff  Psi(e,a) = 0, out_max(e,a) = J,
 //                                          in_min(e,a) > J
 //   Phi(e, b) = 0 just before move J  iff  Psi(e,b) = 0, in_min(e,b) = J,
@@ -21,11 +24,14 @@
 // never need a full clear.
 //
 // Monotone round.  Select and approval run as in a plain round, but approve
-// only marks the approved moves.  A stable radix sort orders them by (select
-// gain desc, vertex id asc) -- the keys of all n vertices, unmarked ones last
-// -- their exact gains in that order come from the kernels above, a prefix
-// scan picks the prefix with the largest total (ties: the longer), and only
-// that prefix is applied; finalize and the round record follow as usual.
+// only marks the approved moves (and sets their cells empty).  A stable radix
+// sort of the marked vertices orders them by (select gain desc, vertex id
+// asc): its first pass reads the marks and candidate words directly, so the
+// moves are compacted and ordered in one pass when gains fit 8 bits.  Their
+// exact gains in that order come from the kernels above, each 64-move tile
+// leaves its sum and its best prefix, one workgroup scans those for the
+// prefix with the largest total (ties: the longer), and only that prefix is
+// applied; finalize and the round record follow as usual.
 // Every prefix of approved moves respects L_max (the approval budgets each
 // target for all of its moves; moves out of a block only lower it), so the
 // cut needs no balance test, and km1 never increases.
@@ -42,13 +48,16 @@
 namespace hg {
 namespace {
 
-constexpr int kPrefixChunk = 4 * kBlock;    // moves per prefix-scan workgroup
+// Moves per tile of the sequence kernels (one wavefront's worth: a tile's
+// gains are scanned by one wave), and their persistent grid.
+constexpr int kSeqTile = kWave;
+constexpr int kSeqGrid = 1024;
 
 // Layout of the caller's move-sequence workspace.
 struct MovesLayout {
-  size_t cell, seen, appr, key[2], val[2], hist, dtot, gains, csum, coff,
-      cbest_v, cbest_i, best, tdev, total;
-  int sort_tiles, chunks;
+  size_t cell, seen, appr, key[2], val[2], hist, dtot, gains, tsum, tbest_v, tbest_i, best, tdev,
+      total;
+  int sort_tiles, seq_tiles;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -63,7 +72,7 @@ MovesLayout moves_layout(long long n, long long m, int k) {
   };
   const size_t cells = (size_t)m * (size_t)k;
   L.sort_tiles = (int)((n + kSortTile - 1) / kSortTile);
-  L.chunks = (int)((n + kPrefixChunk - 1) / kPrefixChunk);
+  L.seq_tiles = (int)((n + kSeqTile - 1) / kSeqTile);
   L.cell = take(sizeof(int4) * cells);
   L.seen = take(sizeof(int) * (size_t)n);
   L.appr = take((size_t)n);
@@ -74,10 +83,9 @@ MovesLayout moves_layout(long long n, long long m, int k) {
   L.hist = take(sizeof(unsigned) * (size_t)kDigits * L.sort_tiles);
   L.dtot = take(sizeof(unsigned) * kDigits);
   L.gains = take(sizeof(long long) * (size_t)n);
-  L.csum = take(sizeof(long long) * (size_t)L.chunks);
-  L.coff = take(sizeof(long long) * (size_t)L.chunks);
-  L.cbest_v = take(sizeof(long long) * (size_t)L.chunks);
-  L.cbest_i = take(sizeof(int) * (size_t)L.chunks);
+  L.tsum = take(sizeof(long long) * (size_t)L.seq_tiles);
+  L.tbest_v = take(sizeof(long long) * (size_t)L.seq_tiles);
+  L.tbest_i = take(sizeof(int) * (size_t)L.seq_tiles);
   L.best = take(sizeof(long long) * 2);
   L.tdev = take(sizeof(int));
   L.total = off;
@@ -122,8 +130,6 @@ __device__ __forceinline__ bool seq_move(const Seq& S, int j, int& u, int& a, in
 // degrees, owner by binary search in LDS).  f(j, u, a, b, e) is called once
 // per incidence.  Tiles are short, so a short sequence still spreads over
 // many workgroups; the kernels below loop over tiles with a grid stride.
-constexpr int kSeqTile = 64;
-constexpr int kSeqGrid = 1024;   // persistent workgroups of the monotone round's sequence kernels
 
 template <typename F>
 __device__ void for_incidences(const Seq& S, int t, int tile, F f) {
@@ -197,14 +203,26 @@ __global__ __launch_bounds__(kBlock) void k_seq_collect(Seq S) {
   for (int tile = blockIdx.x; tile * kSeqTile < t; tile += gridDim.x)
     for_incidences(S, t, tile, [&](int j, int, int a, int b, int e) {
       const size_t ca = (size_t)e * S.k + a, cb = (size_t)e * S.k + b;
-      atomicMax(&S.cell[ca].x, j + 1);
-      atomicAdd(&S.cell[ca].z, 1);
       atomicMin(&S.cell[cb].y, j + 1);
+      if (S.phi[ca] == 1) {
+        S.cell[ca].x = j + 1;   // the only pin of e in a: the cell's only mover out
+      } else {
+        atomicMax(&S.cell[ca].x, j + 1);
+        atomicAdd(&S.cell[ca].z, 1);
+      }
     });
 }
 
-// gains[j] = exact gain of move j (the Lemma).
-__global__ __launch_bounds__(kBlock) void k_seq_gains(Seq S, long long* gains) {
+// Best (total, length) of two prefixes; ties to the longer.
+__device__ __forceinline__ bool better(long long v, int p, long long bv, int bp) {
+  return v > bv || (v == bv && p > bp);
+}
+
+// gains[j] = exact gain of move j (the Lemma).  With tsum set, each tile also
+// leaves its gain total and the best prefix ending inside it (value relative
+// to the tile's start, length counted from the sequence start).
+__global__ __launch_bounds__(kBlock) void k_seq_gains(Seq S, long long* gains, long long* tsum,
+                                                      long long* tbest_v, int* tbest_i) {
   __shared__ long long s_gain[kSeqTile];
   const int t = seq_len(S);
   for (int tile = blockIdx.x; tile * kSeqTile < t; tile += gridDim.x) {
@@ -216,8 +234,11 @@ __global__ __launch_bounds__(kBlock) void k_seq_gains(Seq S, long long* gains) {
       // all four reads first (no short-circuit: loads in branches would not overlap)
       const int4 A = S.cell[ca], B = S.cell[cb];
       const int pa = S.phi[ca], pb = S.phi[cb];
-      const bool last_out = (pa - A.z == 0) & (A.x == J) & (A.y > J);
-      const bool first_in = (pb - B.z == 0) & (B.y == J) & (B.x < J);
+      // out counts; a cell with one pin records only whether it moved
+      const int za = pa == 1 ? (A.x > 0) : A.z;
+      const int zb = pb == 1 ? (B.x > 0) : B.z;
+      const bool last_out = (pa - za == 0) & (A.x == J) & (A.y > J);
+      const bool first_in = (pb - zb == 0) & (B.y == J) & (B.x < J);
       if (last_out != first_in) {
         const long long w = S.ewgt ? S.ewgt[e] : 1;
         atomicAdd((unsigned long long*)&s_gain[j - tile * kSeqTile],
@@ -225,91 +246,36 @@ __global__ __launch_bounds__(kBlock) void k_seq_gains(Seq S, long long* gains) {
       }
     });
     const int j = tile * kSeqTile + threadIdx.x;
-    if (threadIdx.x < kSeqTile && j < t) gains[j] = s_gain[threadIdx.x];
+    if (threadIdx.x < kSeqTile) {
+      const bool in = j < t;
+      const long long g = in ? s_gain[threadIdx.x] : 0;
+      if (in) gains[j] = g;
+      if (tsum) {
+        // one wavefront: scan of the tile's gains, argmax of the prefixes
+        const long long incl = wave_incl_scan64(g);
+        long long bv = in ? incl : LLONG_MIN;
+        int bp = in ? j + 1 : -1;
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) {
+          const long long ov = __shfl_xor(bv, o);
+          const int op = __shfl_xor(bp, o);
+          if (better(ov, op, bv, bp)) {
+            bv = ov;
+            bp = op;
+          }
+        }
+        if (threadIdx.x == kSeqTile - 1) tsum[tile] = incl;
+        if (threadIdx.x == 0) {
+          tbest_v[tile] = bv;
+          tbest_i[tile] = bp;
+        }
+      }
+    }
     __syncthreads();
   }
 }
 
-// Compaction of a monotone round's marked moves, in vertex-id order (the
-// sort below is stable, so equal gains stay in id order): per chunk of
-// kMarkChunk vertices the number of marks, one workgroup's exclusive scan of
-// those counts (the total is the sequence length), then every marked vertex
-// u writes key = top - select gain (ascending keys are descending gains)
-// and value u at its position, and clears its mark for the next round.
-constexpr int kMarkChunk = 4 * kBlock;
-// the compaction's chunk sums and offsets reuse the prefix scan's arrays
-static_assert(kMarkChunk >= kPrefixChunk, "mark chunks must not outnumber prefix chunks");
-
-__global__ __launch_bounds__(kBlock) void k_mark_count(int n, const unsigned char* appr,
-                                                       long long* csum) {
-  __shared__ long long s_tmp[kBlock / kWave];
-  const long long base = (long long)blockIdx.x * kMarkChunk + (long long)threadIdx.x * 4;
-  int c = 0;
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-    if (base + q < n && appr[base + q]) ++c;
-  const long long tot = block_sum64(c, s_tmp);
-  if (threadIdx.x == 0) csum[blockIdx.x] = tot;
-}
-
-__global__ __launch_bounds__(kBlock) void k_mark_offsets(const long long* csum, long long* coff,
-                                                         int chunks, int* t) {
-  __shared__ long long s_tmp[kBlock / kWave];
-  long long carry = 0;
-  for (int b = 0; b < chunks; b += kBlock) {
-    const int i = b + threadIdx.x;
-    const long long v = i < chunks ? csum[i] : 0;
-    long long tot;
-    const long long ex = block_excl_scan64(v, s_tmp, &tot);
-    if (i < chunks) coff[i] = carry + ex;
-    carry += tot;
-  }
-  if (threadIdx.x == 0) *t = (int)carry;
-}
-
-__global__ __launch_bounds__(kBlock) void k_mark_write(int n, unsigned char* appr,
-                                                       const long long* cand,
-                                                       const long long* coff, unsigned top,
-                                                       unsigned* key, int* val) {
-  __shared__ long long s_tmp[kBlock / kWave];
-  const long long base = (long long)blockIdx.x * kMarkChunk + (long long)threadIdx.x * 4;
-  bool mk[4];
-  int c = 0;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    mk[q] = base + q < n && appr[base + q];
-    c += mk[q];
-  }
-  long long tot;
-  long long pos = coff[blockIdx.x] + block_excl_scan64(c, s_tmp, &tot);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    if (!mk[q]) continue;
-    const long long u = base + q;
-    const int g = (int)(cand[u] >> 32);   // select gain, 0 <= g <= top
-    key[pos] = top - (unsigned)g;
-    val[pos] = (int)u;
-    appr[u] = 0;
-    ++pos;
-  }
-}
-
 // ------------------------------------------------------------ best prefix
-
-// Per chunk of moves: sum of the exact gains.
-__global__ __launch_bounds__(kBlock) void k_prefix_sums(Seq S, const long long* gains,
-                                                        long long* csum) {
-  __shared__ long long s_tmp[kBlock / kWave];
-  const int t = seq_len(S);
-  const long long base = (long long)blockIdx.x * kPrefixChunk;
-  long long v = 0;
-  for (int r = 0; r < kPrefixChunk / kBlock; ++r) {
-    const long long j = base + r * kBlock + threadIdx.x;
-    if (j < t) v += gains[j];
-  }
-  v = block_sum64(v, s_tmp);
-  if (threadIdx.x == 0) csum[blockIdx.x] = v;
-}
 
 // One workgroup: exclusive scan of the chunk sums.
 __global__ __launch_bounds__(kBlock) void k_prefix_top(const long long* csum, long long* coff,
@@ -326,74 +292,29 @@ __global__ __launch_bounds__(kBlock) void k_prefix_top(const long long* csum, lo
   }
 }
 
-// Best (total, length) of the prefixes ending in a chunk; ties to the longer.
-__device__ __forceinline__ bool better(long long v, int p, long long bv, int bp) {
-  return v > bv || (v == bv && p > bp);
-}
-
-__global__ __launch_bounds__(kBlock) void k_prefix_best(Seq S, const long long* gains,
-                                                        const long long* coff,
-                                                        long long* cbest_v, int* cbest_i) {
+// One workgroup: the best prefix of the whole sequence from the tiles'
+// summaries (exclusive scan of the tile totals plus each tile's best), and
+// the empty prefix -> best[0] (total), best[1] (length); ties to the longer.
+__global__ __launch_bounds__(kBlock) void k_prefix_pick(const int* t_dev, const long long* tsum,
+                                                        const long long* tbest_v,
+                                                        const int* tbest_i, long long* best) {
   __shared__ long long s_tmp[kBlock / kWave];
   __shared__ long long s_bv[kBlock / kWave];
   __shared__ int s_bp[kBlock / kWave];
-  const int t = seq_len(S);
-  const long long base = (long long)blockIdx.x * kPrefixChunk;
-  long long carry = coff[blockIdx.x];
-  long long bv = LLONG_MIN;
-  int bp = -1;
-  for (int r = 0; r < kPrefixChunk / kBlock; ++r) {
-    const long long j = base + r * kBlock + threadIdx.x;
-    const long long g = j < t ? gains[j] : 0;
+  const int tiles = (*t_dev + kSeqTile - 1) / kSeqTile;
+  long long bv = 0, carry = 0;
+  int bp = 0;   // the empty prefix
+  for (int b = 0; b < tiles; b += kBlock) {
+    const int i = b + threadIdx.x;
+    const long long v = i < tiles ? tsum[i] : 0;
     long long tot;
-    const long long incl = block_excl_scan64(g, s_tmp, &tot) + g;
-    if (j < t && better(carry + incl, (int)j + 1, bv, bp)) {
-      bv = carry + incl;
-      bp = (int)j + 1;
+    const long long ex = block_excl_scan64(v, s_tmp, &tot);
+    if (i < tiles && better(carry + ex + tbest_v[i], tbest_i[i], bv, bp)) {
+      bv = carry + ex + tbest_v[i];
+      bp = tbest_i[i];
     }
     carry += tot;
   }
-  // workgroup argmax
-  const int lane = lane_id(), wv = threadIdx.x / kWave;
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) {
-    const long long ov = __shfl_xor(bv, o);
-    const int op = __shfl_xor(bp, o);
-    if (better(ov, op, bv, bp)) {
-      bv = ov;
-      bp = op;
-    }
-  }
-  if (lane == 0) {
-    s_bv[wv] = bv;
-    s_bp[wv] = bp;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 1; w < kBlock / kWave; ++w)
-      if (better(s_bv[w], s_bp[w], bv, bp)) {
-        bv = s_bv[w];
-        bp = s_bp[w];
-      }
-    cbest_v[blockIdx.x] = bv;
-    cbest_i[blockIdx.x] = bp;
-  }
-}
-
-// One workgroup: the best over all chunks and the empty prefix -> best[0]
-// (total), best[1] (length).
-__global__ __launch_bounds__(kBlock) void k_prefix_final(const long long* cbest_v,
-                                                         const int* cbest_i, int chunks,
-                                                         long long* best) {
-  __shared__ long long s_bv[kBlock / kWave];
-  __shared__ int s_bp[kBlock / kWave];
-  long long bv = 0;
-  int bp = 0;   // the empty prefix
-  for (int i = threadIdx.x; i < chunks; i += kBlock)
-    if (cbest_i[i] > 0 && better(cbest_v[i], cbest_i[i], bv, bp)) {
-      bv = cbest_v[i];
-      bp = cbest_i[i];
-    }
   const int lane = lane_id(), wv = threadIdx.x / kWave;
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) {
@@ -899,7 +820,8 @@ hipError_t launch_move_gains(hg_graph_s* g, int k, const int* part, const int* p
   const unsigned tiles = grid_of(t, kSeqTile);
   hipLaunchKernelGGL(k_seq_init, dim3(tiles), dim3(kBlock), 0, s, S);
   hipLaunchKernelGGL(k_seq_collect, dim3(tiles), dim3(kBlock), 0, s, S);
-  hipLaunchKernelGGL(k_seq_gains, dim3(tiles), dim3(kBlock), 0, s, S, gains);
+  hipLaunchKernelGGL(k_seq_gains, dim3(tiles), dim3(kBlock), 0, s, S, gains, nullptr, nullptr,
+                     nullptr);
   hipLaunchKernelGGL(k_seq_clear, dim3(grid), dim3(kBlock), 0, s, S);
   return hipGetLastError();
 }
@@ -919,34 +841,32 @@ hipError_t launch_best_prefix(hg_graph_s* g, int k, long long lmax, const int* p
   return hipGetLastError();
 }
 
-// One monotone round of a single instance (see the file comment).
-hipError_t launch_round_exact(hg_graph_s* g, InstDesc d, int round, char* ws, hipStream_t s) {
+// One monotone round of a single instance (see the file comment).  With
+// marks_clear the caller knows the approval marks are all zero (a previous
+// round of the same workspace cleared them).
+hipError_t launch_round_exact(hg_graph_s* g, InstDesc d, int round, char* ws, bool marks_clear,
+                              hipStream_t s) {
   const MovesLayout L = moves_layout(g->n, g->m, d.k);
   d.appr = (unsigned char*)(ws + L.appr);
+  d.seq_cell = (int4*)(ws + L.cell);
   RoundPlan plan;
   single_round_plan(d, plan);
-  hipError_t e = fill_u8(d.appr, 0, g->n, s);   // approval marks start cleared
+  hipError_t e = hipSuccess;
+  if (!marks_clear) e = fill_u8(d.appr, 0, g->n, s);
   if (e == hipSuccess) e = launch_round_front(plan, s, nullptr);
   if (e != hipSuccess) return e;
-  // the marked moves compacted in id order, then ordered by a stable radix
-  // sort of their keys (8-bit passes over the bits a gain can occupy: gains
-  // are at most the largest incident weight); the count t lives on the device
+  // the marked moves ordered by a stable radix sort of keys top - gain (gains
+  // are at most the largest incident weight): 8-bit passes over the bits a
+  // gain can occupy, the first one reading the marks and clearing them (the
+  // count t lives on the device)
   const int n = g->n;
   const long long maxw = g->info.max_incident_weight;   // bounds every gain
   const bool one_pass = maxw < 255;
   int* tdev = (int*)(ws + L.tdev);
-  const int mchunks = (int)((n + kMarkChunk - 1) / kMarkChunk);
-  long long* msum = (long long*)(ws + L.csum);     // L.chunks >= mchunks
-  long long* moff = (long long*)(ws + L.coff);
-  hipLaunchKernelGGL(k_mark_count, dim3(mchunks), dim3(kBlock), 0, s, n, d.appr, msum);
-  hipLaunchKernelGGL(k_mark_offsets, dim3(1), dim3(kBlock), 0, s, msum, moff, mchunks, tdev);
-  hipLaunchKernelGGL(k_mark_write, dim3(mchunks), dim3(kBlock), 0, s, n, d.appr, d.cand, moff,
-                     one_pass ? 254u : 0x7fffffffu, (unsigned*)(ws + L.key[0]),
-                     (int*)(ws + L.val[0]));
   int bits = 1;
   while (bits < 31 && (1ll << bits) <= maxw) ++bits;
   int cur = 0;
-  auto pass = [&](int shift) {
+  for (int shift = 0; shift < (one_pass ? 8 : bits); shift += 8) {
     SortPass P;
     P.key_in = (const unsigned*)(ws + L.key[cur]);
     P.val_in = (const int*)(ws + L.val[cur]);
@@ -955,40 +875,36 @@ hipError_t launch_round_exact(hg_graph_s* g, InstDesc d, int round, char* ws, hi
     P.hist = (unsigned*)(ws + L.hist);
     P.dtot = (unsigned*)(ws + L.dtot);
     P.n = n;
-    P.n_dev = tdev;
     P.tiles = L.sort_tiles;
     P.shift = shift;
-    hipLaunchKernelGGL(k_sort_hist, dim3(L.sort_tiles), dim3(kBlock), 0, s, P);
-    hipLaunchKernelGGL(k_sort_scan, dim3(kDigits), dim3(kBlock), 0, s, P);
-    hipLaunchKernelGGL(k_sort_scatter, dim3(L.sort_tiles), dim3(kBlock), 0, s, P);
+    if (shift == 0) {
+      P.marks = d.appr;
+      P.cand = d.cand;
+      // keys 0x7fffffff - g differ from 0x7fffffff only in the low `bits` bits
+      P.top = one_pass ? 254u : 0x7fffffffu;
+      P.count_out = tdev;
+    } else {
+      P.n_dev = tdev;
+    }
+    sort_pass(P, s);
     cur ^= 1;
-  };
-  if (one_pass) {
-    pass(0);
-  } else {
-    // keys 0x7fffffff - g differ from 0x7fffffff only in the low `bits` bits
-    for (int shift = 0; shift < bits; shift += 8) pass(shift);
   }
-  // exact gains of the sorted sequence, best prefix, apply it
+  // exact gains of the sorted sequence (its cells were set empty by the
+  // approval), best prefix, apply it
   Seq S = make_seq(g, d.k, ws, L, d.part, d.phi, (const int*)(ws + L.val[cur]), nullptr, 0);
   S.cand = d.cand;
   S.t_dev = tdev;
   long long* gains = (long long*)(ws + L.gains);
+  long long* tsum = (long long*)(ws + L.tsum);
+  long long* tbv = (long long*)(ws + L.tbest_v);
+  int* tbi = (int*)(ws + L.tbest_i);
+  long long* best = (long long*)(ws + L.best);
   // persistent grids: the kernels stride over the sequence's tiles, whose
   // count is known only on the device
   const unsigned tiles = std::min(grid_of(n, kSeqTile), (unsigned)kSeqGrid);
-  hipLaunchKernelGGL(k_seq_init, dim3(tiles), dim3(kBlock), 0, s, S);
   hipLaunchKernelGGL(k_seq_collect, dim3(tiles), dim3(kBlock), 0, s, S);
-  hipLaunchKernelGGL(k_seq_gains, dim3(tiles), dim3(kBlock), 0, s, S, gains);
-  long long* csum = (long long*)(ws + L.csum);
-  long long* coff = (long long*)(ws + L.coff);
-  long long* cbv = (long long*)(ws + L.cbest_v);
-  int* cbi = (int*)(ws + L.cbest_i);
-  long long* best = (long long*)(ws + L.best);
-  hipLaunchKernelGGL(k_prefix_sums, dim3(L.chunks), dim3(kBlock), 0, s, S, gains, csum);
-  hipLaunchKernelGGL(k_prefix_top, dim3(1), dim3(kBlock), 0, s, csum, coff, L.chunks);
-  hipLaunchKernelGGL(k_prefix_best, dim3(L.chunks), dim3(kBlock), 0, s, S, gains, coff, cbv, cbi);
-  hipLaunchKernelGGL(k_prefix_final, dim3(1), dim3(kBlock), 0, s, cbv, cbi, L.chunks, best);
+  hipLaunchKernelGGL(k_seq_gains, dim3(tiles), dim3(kBlock), 0, s, S, gains, tsum, tbv, tbi);
+  hipLaunchKernelGGL(k_prefix_pick, dim3(1), dim3(kBlock), 0, s, tdev, tsum, tbv, tbi, best);
   hipLaunchKernelGGL(k_apply_prefix, dim3(tiles), dim3(kBlock), 0, s, S, best, d);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -1226,7 +1142,7 @@ hg_status hg_lp_round_exact(hg_graph g, int32_t k, int64_t max_block_w, int32_t*
   if (st != HG_OK) return st;
   hg::InstDesc d = hg::make_desc(g, k, max_block_w, part, phi, netstate, (long long*)block_w,
                                  eligible, moved, (long long*)km1, stats);
-  HG_TRY(hg::launch_round_exact(g, d, 0, (char*)workspace, (hipStream_t)stream),
+  HG_TRY(hg::launch_round_exact(g, d, 0, (char*)workspace, false, (hipStream_t)stream),
          "monotone round");
   return HG_OK;
 }
@@ -1253,7 +1169,8 @@ hg_status hg_refine_exact(hg_graph g, int32_t k, double eps, int32_t rounds, int
   HG_TRY(hg::launch_counts(cplan, true, true, s), "pin counts");
   for (int r = 0; r < rounds; ++r) {
     d.stats = stats + r;
-    HG_TRY(hg::launch_round_exact(g, d, 0, (char*)workspace, s), "monotone round");
+    // every round after the first finds the marks cleared by its predecessor
+    HG_TRY(hg::launch_round_exact(g, d, 0, (char*)workspace, r > 0, s), "monotone round");
   }
   return HG_OK;
 }

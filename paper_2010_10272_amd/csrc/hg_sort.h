@@ -27,9 +27,53 @@ struct SortPass {
   // when set, the item count is *n_dev (known only on the device, at most n;
   // tiles past it are empty)
   const int* n_dev = nullptr;
+  // Marks mode (the first pass of a monotone round's move order): item i is
+  // vertex i, present only where marks[i] != 0, with key top - gain(cand[i])
+  // and value i; the scatter clears the marks it reads and workgroup 0
+  // stores the number of present items in *count_out.  key_in / val_in are
+  // not read.
+  unsigned char* marks = nullptr;
+  const long long* cand = nullptr;
+  unsigned top = 0;
+  int* count_out = nullptr;
 };
 
 __device__ __forceinline__ int sort_items(const SortPass& P) { return P.n_dev ? *P.n_dev : P.n; }
+
+// The kSortPer items of this thread in tile `base`: keys, values (when
+// want_val) and presence.  Every load of the tile is issued before the first
+// wait; in marks mode the candidate words are read for marked vertices only.
+__device__ __forceinline__ void sort_load(const SortPass& P, int n, long long base, bool want_val,
+                                          unsigned* key, int* val, bool* live) {
+  if (P.marks) {
+    unsigned char mk[kSortPer];
+#pragma unroll
+    for (int r = 0; r < kSortPer; ++r) {
+      const long long i = base + r * kBlock + threadIdx.x;
+      mk[r] = i < n ? P.marks[i] : 0;
+    }
+    long long x[kSortPer];
+#pragma unroll
+    for (int r = 0; r < kSortPer; ++r) {
+      const long long i = base + r * kBlock + threadIdx.x;
+      x[r] = mk[r] ? P.cand[i] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < kSortPer; ++r) {
+      live[r] = mk[r] != 0;
+      key[r] = P.top - (unsigned)(int)(x[r] >> 32);   // select gain, 0 <= gain <= top
+      if (want_val) val[r] = (int)(base + r * kBlock + threadIdx.x);
+    }
+    return;
+  }
+#pragma unroll
+  for (int r = 0; r < kSortPer; ++r) {
+    const long long i = base + r * kBlock + threadIdx.x;
+    live[r] = i < n;
+    key[r] = i < n ? P.key_in[i] : 0u;
+    if (want_val) val[r] = i < n ? P.val_in[i] : 0;
+  }
+}
 
 __device__ __forceinline__ unsigned digit_of(unsigned key, int shift) {
   return (key >> shift) & (kDigits - 1);
@@ -42,14 +86,11 @@ __global__ __launch_bounds__(kBlock) void k_sort_hist(SortPass P) {
   __syncthreads();
   const long long base = (long long)blockIdx.x * kSortTile;
   unsigned key[kSortPer];
-#pragma unroll
-  for (int r = 0; r < kSortPer; ++r) {
-    const long long i = base + r * kBlock + threadIdx.x;
-    key[r] = i < n ? P.key_in[i] : 0u;
-  }
+  bool live[kSortPer];
+  sort_load(P, n, base, false, key, nullptr, live);
 #pragma unroll
   for (int r = 0; r < kSortPer; ++r)
-    if (base + r * kBlock + threadIdx.x < n) atomicAdd(&s_h[digit_of(key[r], P.shift)], 1u);
+    if (live[r]) atomicAdd(&s_h[digit_of(key[r], P.shift)], 1u);
   __syncthreads();
   P.hist[(size_t)threadIdx.x * P.tiles + blockIdx.x] = s_h[threadIdx.x];
 }
@@ -82,18 +123,14 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(SortPass P) {
   __shared__ unsigned s_gofs[kDigits];    // output index of LDS slot 0 for each digit
   __shared__ unsigned s_wcnt[kBlock / kWave][kDigits];
   __shared__ long long s_tmp[kBlock / kWave];
+  __shared__ unsigned s_count;            // items present in this tile
   const long long base = (long long)blockIdx.x * kSortTile;
   const int n = sort_items(P);
   if (base >= n) return;                  // an empty tile (device-side count)
-  // every item of the tile requested before the first wait
   unsigned key[kSortPer];
   int val[kSortPer];
-#pragma unroll
-  for (int r = 0; r < kSortPer; ++r) {
-    const long long i = base + r * kBlock + threadIdx.x;
-    key[r] = i < n ? P.key_in[i] : 0u;
-    val[r] = i < n ? P.val_in[i] : 0;
-  }
+  bool item[kSortPer];
+  sort_load(P, n, base, true, key, val, item);
   {
     // digit d = threadIdx.x: its count in this tile is the difference of the
     // scanned per-tile offsets; its LDS run starts after the smaller digits'
@@ -103,7 +140,9 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(SortPass P) {
         (int)blockIdx.x + 1 < P.tiles ? P.hist[(size_t)d * P.tiles + blockIdx.x + 1] : P.dtot[d];
     long long tot;
     const long long below = block_excl_scan64(P.dtot[d], s_tmp, &tot);
+    if (P.count_out && blockIdx.x == 0 && d == 0) *P.count_out = (int)tot;
     const long long loff = block_excl_scan64(next - here, s_tmp, &tot);
+    if (d == 0) s_count = (unsigned)tot;
     s_run[d] = (unsigned)loff;
     s_gofs[d] = (unsigned)(below + here - loff);   // modulo 2^32; slot + this is in range
     for (int w = 0; w < kBlock / kWave; ++w) s_wcnt[w][d] = 0;
@@ -113,7 +152,8 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(SortPass P) {
   const unsigned long long lt = (1ull << lane) - 1ull;
 #pragma unroll
   for (int r = 0; r < kSortPer; ++r) {
-    const bool live = base + r * kBlock + threadIdx.x < n;
+    const bool live = item[r];
+    if (live && P.marks) P.marks[base + r * kBlock + threadIdx.x] = 0;
     const unsigned d = digit_of(key[r], P.shift);
     // lanes of this wave with the same digit
     unsigned long long peers = __ballot(live);
@@ -140,8 +180,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(SortPass P) {
     s_run[threadIdx.x] += add;
     __syncthreads();
   }
-  const long long left = (long long)n - base;
-  const int count = left < kSortTile ? (int)left : kSortTile;
+  const int count = (int)s_count;
   for (int j = threadIdx.x; j < count; j += kBlock) {
     const unsigned k = s_key[j];
     const unsigned pos = s_gofs[digit_of(k, P.shift)] + (unsigned)j;

@@ -102,6 +102,13 @@ def _cases():
     for k in (8, 32):
         yield ("band-k%d" % k, lambda k=k: synth.sparse_matrix(
             k, seed=40 + k, rows=40000, cols=40000, band=1500, rounds=4))
+    # average degree 12 and more (the select sweep's eight-wide gathers)
+    yield "vlsi-200x200-k16", lambda: synth.vlsi_grid(seed=11, side=200, height=200, m=42000,
+                                                      k=16, rounds=4)
+    yield "dense-k33-w", lambda: synth.random_power_law(77, 4000, 20000, 33, hi=40, unit=False,
+                                                        rounds=4)
+    yield "dense-k64-u", lambda: synth.random_power_law(78, 4000, 20000, 64, hi=40, unit=True,
+                                                        rounds=4)
     yield "hub-k4-u", lambda: _hub_instance(7, 6000, 5000, 4, 300, False)
     yield "hub-k16-w", lambda: _hub_instance(8, 6000, 5000, 16, 400, True)
     yield "hub-k70-w", lambda: _hub_instance(9, 5000, 4000, 70, 500, True)
