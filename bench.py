@@ -404,6 +404,11 @@ def served_leg(args, H, dev):
         lat = [x["done_ms"] - x["arrival_ms"] for x in infos]
         res = _lat_summary(lat, pin_rounds, start, max(x["done_ms"] for x in infos))
         res["server"] = H.hg_server_get_stats(srv)
+        small = [x for (r, h), x in zip(reqs, infos) if not r.big]
+        res["small_p50_parts_ms"] = {
+            "queued": percentile([x["admit_ms"] - x["arrival_ms"] for x in small], 50),
+            "load": percentile([x["loaded_ms"] - x["admit_ms"] for x in small], 50),
+            "rounds_and_copy": percentile([x["done_ms"] - x["loaded_ms"] for x in small], 50)}
         srv.free()
         return res, outs
 
@@ -412,14 +417,17 @@ def served_leg(args, H, dev):
         clock = lambda: time.perf_counter() * 1e3        # noqa: E731
         start = clock() + 20.0
         lat, t_last = [], start
+        parts = {"queued": [], "load": [], "rounds_and_copy": []}
         stats = torch.zeros(16 * H.STATS_WORDS, dtype=torch.int64, device=dev)
         for (r, h), out in zip(reqs, outs):
             due = start if burst else start + r.arrival_s * 1e3
             if not burst:
                 _sleep_until(clock, due)
             inst = h["inst"]
+            t_begin = clock()
             g = H.hg_load_csr(inst.n, h["eptr"], h["pins"], h["vwgt"], h["ewgt"], k_max=r.k,
                               device=dev)
+            t_loaded = clock()
             st = H.State(g, r.k, h["parts"][r.k])
             H.hg_refine(g, st, r.eps, r.rounds, stats, use_graph=False)
             out[0].copy_(st.part, non_blocking=True)
@@ -428,8 +436,14 @@ def served_leg(args, H, dev):
             torch.cuda.synchronize()
             t_last = clock()
             lat.append(t_last - due)
+            if not r.big:
+                parts["queued"].append(t_begin - due)
+                parts["load"].append(t_loaded - t_begin)
+                parts["rounds_and_copy"].append(t_last - t_loaded)
             g.free()
-        return _lat_summary(lat, pin_rounds, start, t_last), outs
+        res = _lat_summary(lat, pin_rounds, start, t_last)
+        res["small_p50_parts_ms"] = {x: percentile(v, 50) for x, v in parts.items()}
+        return res, outs
 
     res = {"rate_per_s": SERVED_RATE, "seconds": args.served_seconds, "requests": len(reqs),
            "big_requests": sum(r.big for r in trace), "pin_rounds": pin_rounds,
@@ -1032,6 +1046,22 @@ def headline(args, rec, workload, config_extra):
     return out
 
 
+def attach_traffic(roof, profile):
+    """Measured HBM-side bytes (committed counter summary) beside the
+    algorithmic ones: the select per launch, the approve and finalize phases
+    per round, and the whole round."""
+    roof["traffic"] = measured_traffic(profile, "select")
+    roof["traffic_unit"] = ("bytes per launch: L2-to-fabric read and write requests by size "
+                            "(32/64/128 B) from rocprofv3 counters, profiles/" + profile)
+    tot = roof["traffic"]
+    for p in ("approve", "finalize"):
+        t = measured_traffic(profile, p)
+        roof["phases"][p]["traffic"] = t
+        tot = None if tot is None or t is None else tot + t
+    roof["phases"]["select"]["traffic"] = roof["traffic"]
+    roof["round"]["traffic"] = tot
+
+
 def plain_legs(args, H, dev):
     """The plain workloads: the VLSI-like netlist (the headline), the
     sparse matrix and the tiny instance."""
@@ -1044,7 +1074,7 @@ def plain_legs(args, H, dev):
         sp = sparse_instance()
         srec = plain_workload(args, H, dev, sp, KS, ROUNDS, "sparse",
                               {8: ROUNDS, 64: args.cpu_rounds_k64})
-        srec["roofline"]["traffic"] = measured_traffic("plain_sparse_matrix_traffic.md", "select")
+        attach_traffic(srec["roofline"], "plain_sparse_matrix_traffic.md")
         srec["config"] = ("sparse-matrix row-net hypergraph 1M x 1M (%d pins), k = 8 and k = 64, "
                           "eps = 0.03, 10 synchronous LP rounds per k; one step = load + (pin "
                           "counts + 10 rounds + gains + km1) per k" % sp.P)
@@ -1065,9 +1095,7 @@ def vlsi_headline(args, H, dev):
     print("generating the VLSI-like netlist ...", file=sys.stderr, flush=True)
     vl = synth.vlsi_grid()
     rec = plain_workload(args, H, dev, vl, (vl.k,), ROUNDS, "vlsi", {vl.k: args.cpu_rounds})
-    rec["roofline"]["traffic"] = measured_traffic("plain_vlsi_traffic.md", "select")
-    rec["roofline"]["traffic_unit"] = ("bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated "
-                                       "by a plain copy; profiles/plain_vlsi_traffic.md)")
+    attach_traffic(rec["roofline"], "plain_vlsi_traffic.md")
     rec["roofline"]["copy_reference"] = copy_bandwidth(torch, dev)
     out = headline(args, rec, "VLSI-like netlist: 2000 x 2000 grid, n = %d cells, m = %d nets, "
                    "%d pins, k = %d, eps = 0.03, 10 synchronous LP rounds; one step = load + "

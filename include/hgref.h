@@ -352,7 +352,7 @@ typedef struct {
  * speed differs (hg_batch_autotune measures). */
 typedef struct {
   int32_t select_chunks;     /* 256-vertex chunks per select workgroup, 1..64    */
-  int32_t finalize_chunks;   /* 256-net chunks per finalize workgroup, 1..64     */
+  int32_t finalize_chunks;   /* 1024-net blocks per finalize workgroup, 1..64    */
   int32_t count_chunks;      /* 256-net chunks per pin-count workgroup, 1..64    */
   int32_t net_lanes;         /* lanes per net in the pin-count and finalize
                                 sweeps: 0 = the minimum for k (4 for k <= 4, 8
@@ -611,8 +611,10 @@ size_t hg_request_bytes(int32_t n, int32_t m, int64_t P, int32_t k, int32_t roun
  * lane (own stream and tables) for jobs of at least big_pins pins, so that
  * smaller jobs never wait for their rounds; 0 keeps one lane.  Each lane takes
  * half of the table region, split into two halves rebuilt alternately.
- * sched: HG_SIZE_CLASSES schedules or NULL (defaults).  The current device at
- * the call is the server's device. */
+ * sched: HG_SIZE_CLASSES schedules or NULL: then one unit per work item in
+ * every class (a server step usually holds a few jobs, so the most
+ * workgroups per job).  The current device at the call is the server's
+ * device. */
 hg_status hg_server_create(void* arena, size_t arena_bytes, size_t table_bytes,
                            int32_t max_active, int64_t big_pins, const hg_schedule* sched,
                            hg_server* out);

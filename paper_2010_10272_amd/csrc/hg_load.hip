@@ -217,17 +217,39 @@ __global__ void k_pin_pairs(int m, const long long* eptr, int* val) {
 
 // vptr[v] = the first sorted position with key >= v; vptr[n] = P.  A pair
 // equal to its predecessor (same pin, same net) is a vertex listed twice in
-// one net: the stable sort puts such pairs side by side.
-__global__ void k_row_starts(long long P, int n, const unsigned* key, const int* val,
+// one net: the stable sort puts such pairs side by side.  Four positions per
+// thread (16-byte loads of keys and values when both arrays are 16-byte
+// aligned, `vec`), each compared with the one before it.
+constexpr int kRowStartsPer = 4;
+
+__global__ void k_row_starts(long long P, int n, const unsigned* key, const int* val, int vec,
                              long long* vptr, LoadInfo* info) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= P) return;
-  const long long cur = key[i];
-  const long long prev = i == 0 ? -1 : (long long)key[i - 1];
-  if (cur == prev && val[i] == val[i - 1]) atomicOr(&info->err, kErrDuplicate);
-  for (long long v = prev + 1; v <= cur; ++v) vptr[v] = i;
-  if (i == P - 1)
-    for (long long v = cur + 1; v <= n; ++v) vptr[v] = P;
+  const long long i0 = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * kRowStartsPer;
+  if (i0 >= P) return;
+  long long k[kRowStartsPer + 1];
+  int v[kRowStartsPer + 1];
+  k[0] = i0 == 0 ? -1 : (long long)key[i0 - 1];
+  v[0] = i0 == 0 ? -1 : val[i0 - 1];
+  if (vec && i0 + kRowStartsPer <= P) {
+    const uint4 kq = *reinterpret_cast<const uint4*>(key + i0);
+    const int4 vq = *reinterpret_cast<const int4*>(val + i0);
+    k[1] = kq.x; k[2] = kq.y; k[3] = kq.z; k[4] = kq.w;
+    v[1] = vq.x; v[2] = vq.y; v[3] = vq.z; v[4] = vq.w;
+  } else {
+    for (int q = 0; q < kRowStartsPer; ++q) {
+      k[q + 1] = i0 + q < P ? (long long)key[i0 + q] : -1;
+      v[q + 1] = i0 + q < P ? val[i0 + q] : 0;
+    }
+  }
+  int err = 0;
+  for (int q = 0; q < kRowStartsPer && i0 + q < P; ++q) {
+    const long long i = i0 + q, cur = k[q + 1], prev = k[q];
+    if (cur == prev && v[q + 1] == v[q]) err = kErrDuplicate;
+    for (long long x = prev + 1; x <= cur; ++x) vptr[x] = i;
+    if (i == P - 1)
+      for (long long x = cur + 1; x <= n; ++x) vptr[x] = P;
+  }
+  if (err) atomicOr(&info->err, err);
 }
 
 // Per-vertex facts of the sorted rows: degree, w(I(v)), the heavy list.
@@ -362,9 +384,11 @@ hipError_t load_build(hg_graph_s* g, hipStream_t s) {
     sort_pass(SP, s);
     kin = SP.key_out;
   }
-  hipLaunchKernelGGL(k_row_starts, dim3((unsigned)((P + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                     s, P, g->n, (const unsigned*)key[passes & 1], (const int*)g->vnets, g->vptr,
-                     info);
+  const long long rs_threads = (P + kRowStartsPer - 1) / kRowStartsPer;
+  const unsigned* skey = key[passes & 1];
+  const int vec = (((uintptr_t)skey | (uintptr_t)g->vnets) & 15) == 0;
+  hipLaunchKernelGGL(k_row_starts, dim3((unsigned)((rs_threads + kBlock - 1) / kBlock)),
+                     dim3(kBlock), 0, s, P, g->n, skey, (const int*)g->vnets, vec, g->vptr, info);
   // all net weights 1 (the checks summed them to m): rows need no weights
   const int* ew = g->info.total_net_weight == (unsigned long long)g->m ? nullptr : g->ewgt;
   LoadPart* part = (LoadPart*)(g->ws + g->lay.lpart);

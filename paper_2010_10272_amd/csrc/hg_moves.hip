@@ -1005,9 +1005,7 @@ static hipError_t launch_rebalance_round(hg_graph_s* g, InstDesc d, char* ws, hi
     P.n = n;
     P.tiles = L.sort_tiles;
     P.shift = shift;
-    hipLaunchKernelGGL(k_sort_hist, dim3(L.sort_tiles), dim3(kBlock), 0, s, P);
-    hipLaunchKernelGGL(k_sort_scan, dim3(kDigits), dim3(kBlock), 0, s, P);
-    hipLaunchKernelGGL(k_sort_scatter, dim3(L.sort_tiles), dim3(kBlock), 0, s, P);
+    sort_pass(P, s);
     cur ^= 1;
   };
   // (gain desc, id asc): keys bias - gain lie in [0, 2 * bias]

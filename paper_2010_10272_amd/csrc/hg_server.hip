@@ -23,6 +23,7 @@
 // alternately; a half is rebuilt only after the last step that read it has
 // completed (its event).
 #include <string.h>
+#include <sys/prctl.h>
 
 #include <chrono>
 #include <condition_variable>
@@ -41,7 +42,12 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kMaxRounds = 1024;
-constexpr int kInFlightSteps = 2;   // steps queued ahead of the GPU
+// Steps of a lane queued ahead of the GPU: two while a job for the lane is
+// being loaded or waits to join (it joins at the next step the executor
+// enqueues), more when none is coming, so that the rounds of the running
+// jobs never wait for the executor thread to notice the previous one.
+constexpr int kInFlightSteps = 2;
+constexpr int kInFlightIdle = 8;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -187,6 +193,7 @@ struct hg_server_s {
   bool stop = false;
   std::vector<std::unique_ptr<hg::Job>> jobs;
   std::deque<hg::Job*> pending, to_load;
+  int loading_lane = -1;                // lane of the job the loader is loading
   int resident = 0;                     // admitted and not done
   hg_server_stats st{};
   hg_status fatal = HG_OK;
@@ -252,8 +259,13 @@ hg_status load_job(hg_server_s* s, Job* j) {
   return HG_OK;
 }
 
+// Short waits of the server threads: the kernel's default timer slack
+// (50 us) would stretch every 20 us poll several times over.
+void precise_waits() { (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0UL, 0UL, 0UL); }
+
 void load_loop(hg_server_s* s) {
   (void)hipSetDevice(s->device);
+  precise_waits();
   std::unique_lock<std::mutex> lk(s->mu);
   for (;;) {
     s->cv_load.wait(lk, [&] { return s->stop || !s->to_load.empty(); });
@@ -261,13 +273,19 @@ void load_loop(hg_server_s* s) {
       if (s->stop) break;
       continue;
     }
-    Job* j = s->to_load.front();
-    s->to_load.pop_front();
+    // small jobs first (in arrival order): a queued large load never delays them
+    auto it = s->to_load.begin();
+    while (it != s->to_load.end() && (*it)->lane != 0) ++it;
+    if (it == s->to_load.end()) it = s->to_load.begin();
+    Job* j = *it;
+    s->to_load.erase(it);
+    s->loading_lane = j->lane;
     lk.unlock();
     const hg_status st = load_job(s, j);
     char msg[160];
     snprintf(msg, sizeof(msg), "%s", st == HG_OK ? "" : hg_last_error());
     lk.lock();
+    s->loading_lane = -1;
     if (st == HG_OK) {
       j->loaded_ms = now_ms(s);
       s->lanes[j->lane].ready.push_back(j);
@@ -509,6 +527,7 @@ size_t gather_step(hg_server_s* s, Lane& ln, std::vector<Job*>& run) {
 
 void exec_loop(hg_server_s* s) {
   (void)hipSetDevice(s->device);
+  precise_waits();
   std::unique_lock<std::mutex> lk(s->mu);
   std::vector<Job*> run;
   for (;;) {
@@ -519,12 +538,15 @@ void exec_loop(hg_server_s* s) {
     bool stepped = false;
     for (int li = 0; li < s->nlanes; ++li) {
       Lane& ln = s->lanes[li];
-      // at most kInFlightSteps steps of a lane queued ahead of the GPU
+      // steps of this lane queued ahead of the GPU: few while a job for it
+      // is on its way (it joins at the next enqueued step)
       while (!ln.in_flight.empty() && hipEventQuery(ln.in_flight.front()) != hipErrorNotReady) {
         s->step_ev_pool.push_back(ln.in_flight.front());
         ln.in_flight.pop_front();
       }
-      if ((int)ln.in_flight.size() >= kInFlightSteps) continue;
+      bool incoming = !ln.ready.empty() || s->loading_lane == li;
+      for (const Job* j : s->to_load) incoming = incoming || j->lane == li;
+      if ((int)ln.in_flight.size() >= (incoming ? kInFlightSteps : kInFlightIdle)) continue;
       const bool wants_rebuild = ln.changed || !ln.ready.empty();
       if (wants_rebuild && !half_free(ln)) continue;
       const size_t nj = gather_step(s, ln, run);
@@ -627,7 +649,12 @@ hg_status hg_server_create(void* arena, size_t arena_bytes, size_t table_bytes,
   s->job_base = s->arena + table_bytes;
   s->mem.reset(new hg::RangeAlloc(arena_bytes - table_bytes));
   s->max_active = max_active;
-  memcpy(s->sched, sched ? sched : hg::kDefaultSchedule, sizeof(s->sched));
+  // without a schedule: one unit per work item (a step usually holds a few
+  // jobs, which then get the most workgroups; the batch defaults group units
+  // for batches of hundreds)
+  static const hg_schedule kServerSchedule[HG_SIZE_CLASSES] = {
+      {1, 1, 1, 0}, {1, 1, 1, 0}, {1, 1, 1, 0}, {1, 1, 1, 0}};
+  memcpy(s->sched, sched ? sched : kServerSchedule, sizeof(s->sched));
   s->t0 = hg::Clock::now();
   hipError_t e = hipGetDevice(&s->device);
   for (int li = 0; li < nlanes && e == hipSuccess; ++li) {

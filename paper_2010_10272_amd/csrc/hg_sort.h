@@ -1,7 +1,8 @@
 // hg_sort.h -- stable LSD radix sort of (uint32 key, int32 value) pairs,
 // 8 bits per pass, for the loader, the move-sequence, rebalancing and
-// contraction kernels.  A pass is three launches: per-tile digit counts, a
-// scan of each digit's counts over the tiles, and a stable scatter.
+// contraction kernels.  A pass is three launches (sort_pass): per-tile digit
+// counts, a scan of each digit's counts over the tiles, and a stable
+// scatter.
 // Included by each source file that sorts (the kernels have internal
 // linkage there).
 #pragma once
@@ -14,7 +15,18 @@ namespace {
 
 constexpr int kSortTile = 16 * kBlock;      // items per radix-sort workgroup (16 per thread)
 constexpr int kSortPer = kSortTile / kBlock;
+constexpr int kSortWaves = kBlock / kWave;
+constexpr int kSortPerWave = kSortTile / kSortWaves;   // each wave owns a contiguous quarter
 constexpr int kDigits = 256;                // 8-bit digits
+static_assert(kDigits == kBlock, "one thread per digit");
+
+// Item r of this thread in the tile at `base`: wave w holds items
+// [w * kSortPerWave, (w + 1) * kSortPerWave) of the tile, 64 consecutive per
+// round, so every load is coalesced and a wave's items are contiguous (the
+// scatter ranks them without workgroup barriers).
+__device__ __forceinline__ long long sort_item(long long base, int r) {
+  return base + (long long)(threadIdx.x / kWave) * kSortPerWave + r * kWave + lane_id();
+}
 
 struct SortPass {
   const unsigned* key_in;
@@ -49,26 +61,26 @@ __device__ __forceinline__ void sort_load(const SortPass& P, int n, long long ba
     unsigned char mk[kSortPer];
 #pragma unroll
     for (int r = 0; r < kSortPer; ++r) {
-      const long long i = base + r * kBlock + threadIdx.x;
+      const long long i = sort_item(base, r);
       mk[r] = i < n ? P.marks[i] : 0;
     }
     long long x[kSortPer];
 #pragma unroll
     for (int r = 0; r < kSortPer; ++r) {
-      const long long i = base + r * kBlock + threadIdx.x;
+      const long long i = sort_item(base, r);
       x[r] = mk[r] ? P.cand[i] : 0;
     }
 #pragma unroll
     for (int r = 0; r < kSortPer; ++r) {
       live[r] = mk[r] != 0;
       key[r] = P.top - (unsigned)(int)(x[r] >> 32);   // select gain, 0 <= gain <= top
-      if (want_val) val[r] = (int)(base + r * kBlock + threadIdx.x);
+      if (want_val) val[r] = (int)sort_item(base, r);
     }
     return;
   }
 #pragma unroll
   for (int r = 0; r < kSortPer; ++r) {
-    const long long i = base + r * kBlock + threadIdx.x;
+    const long long i = sort_item(base, r);
     live[r] = i < n;
     key[r] = i < n ? P.key_in[i] : 0u;
     if (want_val) val[r] = i < n ? P.val_in[i] : 0;
@@ -112,16 +124,20 @@ __global__ __launch_bounds__(kBlock) void k_sort_scan(SortPass P) {
 }
 
 // Stable scatter of one tile.  The tile is first ranked into LDS in digit
-// order (items r*kBlock + threadIdx.x for r = 0..kSortPer-1 in order; ranks
-// among equal digits by wave ballots, waves and rounds in order), then
-// written out slot by slot, so that each digit's run of the tile leaves as
-// consecutive addresses instead of every store touching many runs.
+// order, then written out slot by slot, so that each digit's run of the
+// tile leaves as consecutive addresses instead of every store touching many
+// runs.  Ranking: each wave walks its contiguous items 64 at a time; lanes
+// with equal digits find each other by ballots, and a wave-private LDS
+// counter per digit gives each item its offset among the wave's items of
+// that digit (no workgroup barrier inside the walk).  Offsets of the waves
+// before it and of the smaller digits complete the LDS slot, which keeps
+// item order within each digit.
 __global__ __launch_bounds__(kBlock) void k_sort_scatter(SortPass P) {
   __shared__ unsigned s_key[kSortTile];
   __shared__ int s_val[kSortTile];
-  __shared__ unsigned s_run[kDigits];     // next LDS slot of each digit
+  __shared__ unsigned s_run[kDigits];     // first LDS slot of each digit
   __shared__ unsigned s_gofs[kDigits];    // output index of LDS slot 0 for each digit
-  __shared__ unsigned s_wcnt[kBlock / kWave][kDigits];
+  __shared__ unsigned s_wcnt[kSortWaves][kDigits];
   __shared__ long long s_tmp[kBlock / kWave];
   __shared__ unsigned s_count;            // items present in this tile
   const long long base = (long long)blockIdx.x * kSortTile;
@@ -145,15 +161,16 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(SortPass P) {
     if (d == 0) s_count = (unsigned)tot;
     s_run[d] = (unsigned)loff;
     s_gofs[d] = (unsigned)(below + here - loff);   // modulo 2^32; slot + this is in range
-    for (int w = 0; w < kBlock / kWave; ++w) s_wcnt[w][d] = 0;
+    for (int w = 0; w < kSortWaves; ++w) s_wcnt[w][d] = 0;
   }
   __syncthreads();
   const int lane = lane_id(), wv = threadIdx.x / kWave;
   const unsigned long long lt = (1ull << lane) - 1ull;
+  unsigned off[kSortPer];   // offset among this wave's items of the same digit
 #pragma unroll
   for (int r = 0; r < kSortPer; ++r) {
     const bool live = item[r];
-    if (live && P.marks) P.marks[base + r * kBlock + threadIdx.x] = 0;
+    if (live && P.marks) P.marks[sort_item(base, r)] = 0;
     const unsigned d = digit_of(key[r], P.shift);
     // lanes of this wave with the same digit
     unsigned long long peers = __ballot(live);
@@ -163,23 +180,34 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(SortPass P) {
       peers &= ((d >> bit) & 1u) ? ones : ~ones;
     }
     const unsigned rank = (unsigned)__popcll(peers & lt);
-    if (live && rank == 0) s_wcnt[wv][d] = (unsigned)__popcll(peers);
-    __syncthreads();
-    if (live) {
-      unsigned slot = s_run[d] + rank;
-      for (int w = 0; w < wv; ++w) slot += s_wcnt[w][d];
+    const unsigned before = live ? s_wcnt[wv][d] : 0u;
+    wave_lds_sync();   // every lane has read its counter before the leaders add
+    off[r] = before + rank;
+    if (live && rank == 0) s_wcnt[wv][d] = before + (unsigned)__popcll(peers);
+    wave_lds_sync();
+  }
+  __syncthreads();
+  {
+    // per digit: counts of the waves before each wave
+    const int d = threadIdx.x;
+    unsigned acc = 0;
+    for (int w = 0; w < kSortWaves; ++w) {
+      const unsigned c = s_wcnt[w][d];
+      s_wcnt[w][d] = acc;
+      acc += c;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortPer; ++r) {
+    if (item[r]) {
+      const unsigned d = digit_of(key[r], P.shift);
+      const unsigned slot = s_run[d] + s_wcnt[wv][d] + off[r];
       s_key[slot] = key[r];
       s_val[slot] = val[r];
     }
-    __syncthreads();
-    unsigned add = 0;
-    for (int w = 0; w < kBlock / kWave; ++w) {
-      add += s_wcnt[w][threadIdx.x];
-      s_wcnt[w][threadIdx.x] = 0;
-    }
-    s_run[threadIdx.x] += add;
-    __syncthreads();
   }
+  __syncthreads();
   const int count = (int)s_count;
   for (int j = threadIdx.x; j < count; j += kBlock) {
     const unsigned k = s_key[j];

@@ -183,6 +183,27 @@ def test_lp_rounds_bit_exact(H, name, make):
     H.hg_sync_status(g)
 
 
+@pytest.mark.parametrize("shift", [1, 2, 3])
+def test_load_into_unaligned_incidence_buffer(H, shift):
+    """A caller's incidence array that is 4-byte but not 16-byte aligned: the
+    row starts then read it word by word; same rows as the oracle's."""
+    import torch
+    inst = synth.sparse_matrix(8, seed=70 + shift, rows=20000, cols=20000, band=800, rounds=2)
+    h = _oracle_hg(inst)
+    vptr = torch.empty(inst.n + 1, dtype=torch.int64, device="cuda")
+    vnets_big = torch.empty(inst.P + 4, dtype=torch.int32, device="cuda")
+    vnets = vnets_big[shift:shift + inst.P]
+    assert vnets.data_ptr() % 16 != 0
+    ws = torch.empty(H.hg_workspace_size(inst.n, inst.m, inst.P, 8), dtype=torch.uint8,
+                     device="cuda")
+    g = H.hg_load_csr(inst.n, inst.eptr, inst.pins, inst.c, inst.w, k_max=8,
+                      out=(vptr, vnets, ws))
+    vptr_o, vnets_o = O.incidence(h)
+    assert np.array_equal(vptr.cpu().numpy(), vptr_o)
+    assert np.array_equal(vnets.cpu().numpy(), vnets_o)
+    H.hg_sync_status(g)
+
+
 @pytest.mark.parametrize("use_graph", [False, True])
 def test_refine_matches_oracle_and_replays(H, use_graph):
     import torch
