@@ -372,7 +372,11 @@ hipError_t load_build(hg_graph_s* g, hipStream_t s) {
   SP.hist = (unsigned*)(g->ws + g->lay.lhist);
   SP.dtot = (unsigned*)(g->ws + g->lay.ldtot);
   SP.n = (int)P;
-  SP.tiles = sort_tiles(P);
+  // long sorts in 8192-item tiles (fuller digit runs per tile; the netlist's
+  // 56.5M pairs sort 11% faster), shorter ones in 4096-item tiles (more
+  // workgroups: 7% faster on 10M pairs)
+  const bool long_sort = P >= (1LL << 24);
+  SP.tiles = long_sort ? sort_tiles<kSortPerLong>(P) : sort_tiles(P);
   // the first pass reads the (validated, non-negative) pins as its keys
   const unsigned* kin = (const unsigned*)g->pins;
   for (int q = 0; q < passes; ++q) {
@@ -381,7 +385,10 @@ hipError_t load_build(hg_graph_s* g, hipStream_t s) {
     SP.key_out = key[(q & 1) ^ 1];
     SP.val_out = val[(q & 1) ^ 1];
     SP.shift = 8 * q;
-    sort_pass(SP, s);
+    if (long_sort)
+      sort_pass<kSortPerLong>(SP, s);
+    else
+      sort_pass(SP, s);
     kin = SP.key_out;
   }
   const long long rs_threads = (P + kRowStartsPer - 1) / kRowStartsPer;

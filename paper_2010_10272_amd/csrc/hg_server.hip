@@ -388,10 +388,28 @@ bool half_free(const Lane& ln) {
 }
 
 // Enqueue one step of lane `ln` for the members in `run` (joiners last, `nj`
-// of them); rebuild the tables when the lane's membership changed.
+// of them); rebuild the tables when the lane's membership changed.  A step
+// of one member launches the single-instance plans instead (the kernels of
+// hg_refine, no table), which spares a lone job the table rebuilds.
 hipError_t enqueue_step(hg_server_s* s, Lane& ln, const std::vector<Job*>& run, size_t nj) {
   hipStream_t cs = ln.stream;
   hipError_t e = hipSuccess;
+  if (run.size() == 1) {
+    const BatchMember M = member_of(s, run[0]);
+    InstDesc d = make_desc(M.g, M.k, M.lmax, M.part, M.phi, M.netstate, M.block_w, M.eligible,
+                           nullptr, M.km1, M.stats);
+    d.round_base = M.round_base;
+    if (nj > 0) {
+      CountPlan cp;
+      single_count_plan(d, cp);
+      e = launch_counts(cp, true, true, cs);
+      if (e != hipSuccess) return e;
+    }
+    RoundPlan rp;
+    single_round_plan(d, rp);
+    ln.changed = true;   // the tables (if any) describe another membership
+    return launch_round(rp, (int)ln.step, cs, nullptr);
+  }
   if (ln.changed) {
     const int h = ln.half ^ 1;   // free: checked by the caller (half_free)
     std::vector<BatchMember> mem;

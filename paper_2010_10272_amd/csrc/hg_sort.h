@@ -13,19 +13,22 @@
 namespace hg {
 namespace {
 
-constexpr int kSortTile = 16 * kBlock;      // items per radix-sort workgroup (16 per thread)
-constexpr int kSortPer = kSortTile / kBlock;
+// Items per thread of a radix-sort tile: 16 (4096-item tiles) by default,
+// 32 for long sorts (fewer, fuller digit runs per tile; half the occupancy).
+constexpr int kSortPer = 16;
+constexpr int kSortPerLong = 32;
+constexpr int kSortTile = kSortPer * kBlock;
 constexpr int kSortWaves = kBlock / kWave;
-constexpr int kSortPerWave = kSortTile / kSortWaves;   // each wave owns a contiguous quarter
 constexpr int kDigits = 256;                // 8-bit digits
 static_assert(kDigits == kBlock, "one thread per digit");
 
-// Item r of this thread in the tile at `base`: wave w holds items
-// [w * kSortPerWave, (w + 1) * kSortPerWave) of the tile, 64 consecutive per
-// round, so every load is coalesced and a wave's items are contiguous (the
-// scatter ranks them without workgroup barriers).
+// Item r of this thread in the tile at `base`: wave w holds the tile's items
+// [w * PER * 64, (w + 1) * PER * 64), 64 consecutive per round, so every
+// load is coalesced and a wave's items are contiguous (the scatter ranks them
+// without workgroup barriers).
+template <int PER>
 __device__ __forceinline__ long long sort_item(long long base, int r) {
-  return base + (long long)(threadIdx.x / kWave) * kSortPerWave + r * kWave + lane_id();
+  return base + (long long)(threadIdx.x / kWave) * (PER * kWave) + r * kWave + lane_id();
 }
 
 struct SortPass {
@@ -52,35 +55,36 @@ struct SortPass {
 
 __device__ __forceinline__ int sort_items(const SortPass& P) { return P.n_dev ? *P.n_dev : P.n; }
 
-// The kSortPer items of this thread in tile `base`: keys, values (when
-// want_val) and presence.  Every load of the tile is issued before the first
-// wait; in marks mode the candidate words are read for marked vertices only.
+// The PER items of this thread in tile `base`: keys, values (when want_val)
+// and presence.  Every load of the tile is issued before the first wait; in
+// marks mode the candidate words are read for marked vertices only.
+template <int PER>
 __device__ __forceinline__ void sort_load(const SortPass& P, int n, long long base, bool want_val,
                                           unsigned* key, int* val, bool* live) {
   if (P.marks) {
-    unsigned char mk[kSortPer];
+    unsigned char mk[PER];
 #pragma unroll
-    for (int r = 0; r < kSortPer; ++r) {
-      const long long i = sort_item(base, r);
+    for (int r = 0; r < PER; ++r) {
+      const long long i = sort_item<PER>(base, r);
       mk[r] = i < n ? P.marks[i] : 0;
     }
-    long long x[kSortPer];
+    long long x[PER];
 #pragma unroll
-    for (int r = 0; r < kSortPer; ++r) {
-      const long long i = sort_item(base, r);
+    for (int r = 0; r < PER; ++r) {
+      const long long i = sort_item<PER>(base, r);
       x[r] = mk[r] ? P.cand[i] : 0;
     }
 #pragma unroll
-    for (int r = 0; r < kSortPer; ++r) {
+    for (int r = 0; r < PER; ++r) {
       live[r] = mk[r] != 0;
       key[r] = P.top - (unsigned)(int)(x[r] >> 32);   // select gain, 0 <= gain <= top
-      if (want_val) val[r] = (int)sort_item(base, r);
+      if (want_val) val[r] = (int)sort_item<PER>(base, r);
     }
     return;
   }
 #pragma unroll
-  for (int r = 0; r < kSortPer; ++r) {
-    const long long i = sort_item(base, r);
+  for (int r = 0; r < PER; ++r) {
+    const long long i = sort_item<PER>(base, r);
     live[r] = i < n;
     key[r] = i < n ? P.key_in[i] : 0u;
     if (want_val) val[r] = i < n ? P.val_in[i] : 0;
@@ -91,17 +95,18 @@ __device__ __forceinline__ unsigned digit_of(unsigned key, int shift) {
   return (key >> shift) & (kDigits - 1);
 }
 
+template <int PER>
 __global__ __launch_bounds__(kBlock) void k_sort_hist(SortPass P) {
   __shared__ unsigned s_h[kDigits];
   const int n = sort_items(P);
   s_h[threadIdx.x] = 0;
   __syncthreads();
-  const long long base = (long long)blockIdx.x * kSortTile;
-  unsigned key[kSortPer];
-  bool live[kSortPer];
-  sort_load(P, n, base, false, key, nullptr, live);
+  const long long base = (long long)blockIdx.x * (PER * kBlock);
+  unsigned key[PER];
+  bool live[PER];
+  sort_load<PER>(P, n, base, false, key, nullptr, live);
 #pragma unroll
-  for (int r = 0; r < kSortPer; ++r)
+  for (int r = 0; r < PER; ++r)
     if (live[r]) atomicAdd(&s_h[digit_of(key[r], P.shift)], 1u);
   __syncthreads();
   P.hist[(size_t)threadIdx.x * P.tiles + blockIdx.x] = s_h[threadIdx.x];
@@ -132,21 +137,23 @@ __global__ __launch_bounds__(kBlock) void k_sort_scan(SortPass P) {
 // that digit (no workgroup barrier inside the walk).  Offsets of the waves
 // before it and of the smaller digits complete the LDS slot, which keeps
 // item order within each digit.
+template <int PER>
 __global__ __launch_bounds__(kBlock) void k_sort_scatter(SortPass P) {
-  __shared__ unsigned s_key[kSortTile];
-  __shared__ int s_val[kSortTile];
+  constexpr int kTile = PER * kBlock;
+  __shared__ unsigned s_key[kTile];
+  __shared__ int s_val[kTile];
   __shared__ unsigned s_run[kDigits];     // first LDS slot of each digit
   __shared__ unsigned s_gofs[kDigits];    // output index of LDS slot 0 for each digit
   __shared__ unsigned s_wcnt[kSortWaves][kDigits];
   __shared__ long long s_tmp[kBlock / kWave];
   __shared__ unsigned s_count;            // items present in this tile
-  const long long base = (long long)blockIdx.x * kSortTile;
+  const long long base = (long long)blockIdx.x * kTile;
   const int n = sort_items(P);
   if (base >= n) return;                  // an empty tile (device-side count)
-  unsigned key[kSortPer];
-  int val[kSortPer];
-  bool item[kSortPer];
-  sort_load(P, n, base, true, key, val, item);
+  unsigned key[PER];
+  int val[PER];
+  bool item[PER];
+  sort_load<PER>(P, n, base, true, key, val, item);
   {
     // digit d = threadIdx.x: its count in this tile is the difference of the
     // scanned per-tile offsets; its LDS run starts after the smaller digits'
@@ -166,11 +173,11 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(SortPass P) {
   __syncthreads();
   const int lane = lane_id(), wv = threadIdx.x / kWave;
   const unsigned long long lt = (1ull << lane) - 1ull;
-  unsigned off[kSortPer];   // offset among this wave's items of the same digit
+  unsigned off[PER];   // offset among this wave's items of the same digit
 #pragma unroll
-  for (int r = 0; r < kSortPer; ++r) {
+  for (int r = 0; r < PER; ++r) {
     const bool live = item[r];
-    if (live && P.marks) P.marks[sort_item(base, r)] = 0;
+    if (live && P.marks) P.marks[sort_item<PER>(base, r)] = 0;
     const unsigned d = digit_of(key[r], P.shift);
     // lanes of this wave with the same digit
     unsigned long long peers = __ballot(live);
@@ -199,7 +206,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(SortPass P) {
   }
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < kSortPer; ++r) {
+  for (int r = 0; r < PER; ++r) {
     if (item[r]) {
       const unsigned d = digit_of(key[r], P.shift);
       const unsigned slot = s_run[d] + s_wcnt[wv][d] + off[r];
@@ -218,13 +225,16 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(SortPass P) {
 }
 
 // One pass on stream s: items [0, P.n), digit (key >> P.shift) & 255.
+// P.tiles must be sort_tiles<PER>(P.n).
+template <int PER = kSortPer>
 inline void sort_pass(const SortPass& P, hipStream_t s) {
-  hipLaunchKernelGGL(k_sort_hist, dim3(P.tiles), dim3(kBlock), 0, s, P);
+  hipLaunchKernelGGL(k_sort_hist<PER>, dim3(P.tiles), dim3(kBlock), 0, s, P);
   hipLaunchKernelGGL(k_sort_scan, dim3(kDigits), dim3(kBlock), 0, s, P);
-  hipLaunchKernelGGL(k_sort_scatter, dim3(P.tiles), dim3(kBlock), 0, s, P);
+  hipLaunchKernelGGL(k_sort_scatter<PER>, dim3(P.tiles), dim3(kBlock), 0, s, P);
 }
 
-inline int sort_tiles(long long n) { return (int)((n + kSortTile - 1) / kSortTile); }
+template <int PER = kSortPer>
+inline int sort_tiles(long long n) { return (int)((n + PER * kBlock - 1) / (PER * kBlock)); }
 
 // Ascending bitonic sort of len int32 items by one workgroup (indices past
 // the end act as +infinity and never move); get/put address LDS or global
