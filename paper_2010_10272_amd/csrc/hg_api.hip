@@ -143,6 +143,7 @@ WsLayout ws_layout(int n, int m, long long P, int k_max) {
   L.flags = take(256);
   L.red = take(sizeof(unsigned long long) * kSlots);
   L.bw_slots = take(sizeof(long long) * kSlots * (size_t)k_max);
+  L.part8 = take((size_t)n);
   L.lkey[0] = take(sizeof(unsigned) * (size_t)P);
   L.lkey[1] = take(sizeof(unsigned) * (size_t)P);
   L.lval = take(sizeof(int) * (size_t)P);
@@ -199,6 +200,7 @@ InstDesc make_desc(hg_graph_s* g, int k, long long lmax, int* part, int* phi,
   d.err_flags = (int*)(ws + g->lay.flags);
   d.red = (unsigned long long*)(ws + g->lay.red);
   d.bw_slots = (long long*)(ws + g->lay.bw_slots);
+  d.part8 = (unsigned char*)(ws + g->lay.part8);
   return d;
 }
 

@@ -141,6 +141,7 @@ struct InstDesc {
   int* err_flags;
   unsigned long long* red;
   long long* bw_slots;           // kSlots x k block-weight deltas of a round's moves
+  unsigned char* part8;          // byte copy of part written by the block-weight sweep
   unsigned char* appr;           // monotone rounds: approve marks moves here instead of applying
   int4* seq_cell;                // monotone rounds: per (net, block) cells the marking sets empty
   int* cache;                    // gain cache (b[n], w(I)[n], p[n*k]); null: none
@@ -211,6 +212,7 @@ struct WsLayout {
   size_t cand, touched, heavy, big, hist, overflow, thr, tilesum, ctr, info, scan, flags;
   size_t red;   // kSlots partial sums for whole-array reductions (km1)
   size_t bw_slots;   // kSlots x k_max block-weight deltas (apply), folded in by the round record
+  size_t part8;      // n bytes: the partition as block ids of one byte (pin-count gathers)
   size_t lkey[2], lval, lhist, ldtot;   // load only: radix-sort buffers of the transpose
   size_t lpart;      // load only: per-workgroup partial facts (LoadPart[kLoadGrid])
   size_t total;

@@ -34,6 +34,9 @@ __device__ __forceinline__ WorkItem contiguous_units(long long units) {
 // Pin slots per lane and pass: the pin loads of kCountSlots * G pins, then
 // their block-id loads, are in flight together (the sweep is bound by their
 // latency); slots past the net's end repeat its first pin and are masked.
+// Block ids are gathered from the byte copy part8 that the block-weight
+// sweep writes just before (a quarter of the bytes of part: on a 4M-vertex
+// netlist 4 MB, which an XCD's L2 mostly holds, instead of 16 MB).
 constexpr int kCountSlots = 4;
 
 // Unit: kBlock/G consecutive nets (one per group).  G lanes per net (G
@@ -54,7 +57,6 @@ __global__ __launch_bounds__(kBlock) void k_pincounts(Launch L) {
   // Phi rows leave as 16-byte streaming stores when rows are 16-byte aligned
   const bool vec_phi = (k & 3) == 0 && ((uintptr_t)D.phi & 15) == 0;
   long long km1_local = 0;
-  int err = 0;
   for (int it = 0; it < wi.count; ++it) {
     const long long e = ((long long)wi.first + (long long)it * wi.stride) * kGroups + grp;
     long long b = 0, t = 0;
@@ -69,13 +71,11 @@ __global__ __launch_bounds__(kBlock) void k_pincounts(Launch L) {
 #pragma unroll
       for (int q = 0; q < kCountSlots; ++q) v[q] = D.pins[p0 + q * G < t ? p0 + q * G : p0];
 #pragma unroll
-      for (int q = 0; q < kCountSlots; ++q) v[q] = D.part[v[q]];
+      for (int q = 0; q < kCountSlots; ++q) v[q] = D.part8[v[q]];
 #pragma unroll
       for (int q = 0; q < kCountSlots; ++q) {
-        if (p0 + q * G < t) {
-          if ((unsigned)v[q] < (unsigned)k) atomicAdd(&cnt[v[q]], 1);
-          else err = kErrPart;
-        }
+        // part itself was checked by the block-weight sweep
+        if (p0 + q * G < t && (unsigned)v[q] < (unsigned)k) atomicAdd(&cnt[v[q]], 1);
       }
     }
     wave_lds_sync();
@@ -101,14 +101,14 @@ __global__ __launch_bounds__(kBlock) void k_pincounts(Launch L) {
     }
     wave_lds_sync();
   }
-  if (err) atomicOr(D.err_flags, err);
   const long long tot = block_sum64(km1_local, s_tmp);
   if (threadIdx.x == 0 && tot)
     atomicAdd(&D.red[blockIdx.x % kSlots], (unsigned long long)tot);
 }
 
 // Unit: one instance.  Sum its km1 slots into *km1 (or just clear them) and
-// clear the block weights for the sweep that follows.
+// fold the block-weight slot rows of the sweep before into block_w (clearing
+// them for the rounds).
 __global__ __launch_bounds__(kBlock) void k_count_epilogue(Launch L, int want_km1) {
   const WorkItem wi = work_item(L, WorkItem{0, 0, 1, 1});
   const InstDesc D = inst_desc(L, wi.inst);
@@ -119,12 +119,28 @@ __global__ __launch_bounds__(kBlock) void k_count_epilogue(Launch L, int want_km
     v = wave_sum(v);
     if (lane == 0 && want_km1) *D.km1 = v;
   }
-  for (int i = threadIdx.x; i < D.k; i += kBlock) D.block_w[i] = 0;
+  const size_t ks = (size_t)D.k;
+  for (int i = threadIdx.x; i < D.k; i += kBlock) {
+    long long* col = D.bw_slots + i;
+    long long w = 0;
+    for (int s0 = 0; s0 < kSlots; s0 += 16) {      // 16 loads in flight, then the clears
+      long long cells[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) cells[q] = col[(s0 + q) * ks];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) w += cells[q];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) col[(s0 + q) * ks] = 0;
+    }
+    D.block_w[i] = w;
+  }
 }
 
 // Unit: kBwChunk consecutive vertices.  LDS partial sums per workgroup, then
-// one atomic per block.  With mark_eligible every vertex is also made
-// eligible (the start of a refinement).
+// one atomic per block into the workgroup's slot row (the epilogue folds the
+// rows into block_w).  Every vertex's block also goes to part8 (one byte).
+// With mark_eligible every vertex is also made eligible (the start of a
+// refinement).
 __global__ __launch_bounds__(kBlock) void k_block_weights(Launch L, int mark_eligible) {
   __shared__ unsigned long long s_w[HG_MAX_K];
   const WorkItem wi = work_item(L, contiguous_units((L.one.n + kBwChunk - 1) / kBwChunk));
@@ -150,6 +166,7 @@ __global__ __launch_bounds__(kBlock) void k_block_weights(Launch L, int mark_eli
       const long long v = base + (long long)j * kBlock + threadIdx.x;
       if (v < n) {
         if (mark_eligible) D.eligible[v] = 1;
+        D.part8[v] = (unsigned char)blk[j];
         if ((unsigned)blk[j] < (unsigned)k)
           atomicAdd(&s_w[blk[j]], (unsigned long long)cw[j]);
         else
@@ -159,8 +176,9 @@ __global__ __launch_bounds__(kBlock) void k_block_weights(Launch L, int mark_eli
   }
   if (err) atomicOr(D.err_flags, err);
   __syncthreads();
+  long long* my_w = D.bw_slots + (size_t)(blockIdx.x % kSlots) * k;
   for (int i = threadIdx.x; i < k; i += kBlock)
-    if (s_w[i]) atomicAdd((unsigned long long*)&D.block_w[i], s_w[i]);
+    if (s_w[i]) atomicAdd((unsigned long long*)&my_w[i], s_w[i]);
 }
 
 // km1 partial sums from the net-state records (single instance only).
@@ -231,14 +249,15 @@ void single_count_plan(const InstDesc& d, CountPlan& plan) {
   plan.vertices.L = L;
 }
 
-// Pin counts, then km1 / block-weight reset / view zeroing, then block weights.
+// Block weights (and the byte partition), then pin counts, then km1 and the
+// block-weight fold.
 hipError_t launch_counts(const CountPlan& plan, bool want_km1, bool mark_eligible, hipStream_t s) {
+  hipLaunchKernelGGL(k_block_weights, dim3(plan.vertices.grid), dim3(kBlock), 0, s,
+                     plan.vertices.L, mark_eligible ? 1 : 0);
   for (const PlanLaunch& pl : plan.pincounts)
     hipLaunchKernelGGL((GroupKernel)pl.kernel, dim3(pl.grid), dim3(kBlock), pl.lds, s, pl.L);
   hipLaunchKernelGGL(k_count_epilogue, dim3(plan.instances.grid), dim3(kBlock), 0, s,
                      plan.instances.L, want_km1 ? 1 : 0);
-  hipLaunchKernelGGL(k_block_weights, dim3(plan.vertices.grid), dim3(kBlock), 0, s,
-                     plan.vertices.L, mark_eligible ? 1 : 0);
   return hipGetLastError();
 }
 
