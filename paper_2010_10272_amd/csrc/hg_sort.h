@@ -113,7 +113,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_hist(SortPass P) {
 }
 
 // One workgroup per digit: exclusive scan of its per-tile counts; total.
-__global__ __launch_bounds__(kBlock) void k_sort_scan(SortPass P) {
+__global__ __launch_bounds__(kBlock) __attribute__((unused)) void k_sort_scan(SortPass P) {
   __shared__ long long s_tmp[kBlock / kWave];
   unsigned* row = P.hist + (size_t)blockIdx.x * P.tiles;
   long long carry = 0;
