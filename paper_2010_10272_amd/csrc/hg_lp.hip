@@ -1212,14 +1212,19 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Launch L) {
   const int grp = threadIdx.x / G, gl = threadIdx.x % G;
   const int k = D.k, wk = bit_words(k), rw = D.rw;
   long long dcheck = 0, ntouched = 0, tpins = 0;
+  // four flags per thread in one load (the flag array is padded to whole
+  // blocks and zero past m; the workspace keeps it 4-byte aligned); the next
+  // block's flags are loaded while this block is finalized
+  unsigned next_f4 = *reinterpret_cast<const unsigned*>(
+      D.touched + (long long)wi.first * kFinalChunk + (long long)threadIdx.x * kFlags);
   for (int it = 0; it < wi.count; ++it) {
     const long long c = (long long)wi.first + (long long)it * wi.stride;
     if (threadIdx.x == 0) s_cnt = 0;
     __syncthreads();
-    // four flags per thread in one load (the flag array is padded to whole
-    // blocks and zero past m; the workspace keeps it 4-byte aligned)
     const long long e0 = c * kFinalChunk + (long long)threadIdx.x * kFlags;
-    const unsigned f4 = *reinterpret_cast<const unsigned*>(D.touched + e0);
+    const unsigned f4 = next_f4;
+    if (it + 1 < wi.count)
+      next_f4 = *reinterpret_cast<const unsigned*>(D.touched + e0 + (long long)wi.stride * kFinalChunk);
     int mine = 0;
 #pragma unroll
     for (int q = 0; q < kFlags; ++q) mine += ((f4 >> (8 * q)) & 0xffu) != 0;

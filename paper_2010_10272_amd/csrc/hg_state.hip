@@ -57,15 +57,30 @@ __global__ __launch_bounds__(kBlock) void k_pincounts(Launch L) {
   // Phi rows leave as 16-byte streaming stores when rows are 16-byte aligned
   const bool vec_phi = (k & 3) == 0 && ((uintptr_t)D.phi & 15) == 0;
   long long km1_local = 0;
+  // the next net's pin range is loaded while this net's pins are counted
+  // (one dependent load fewer per net)
+  long long nb = 0, nt = 0;
+  {
+    const long long e0 = (long long)wi.first * kGroups + grp;
+    if (e0 < m) {
+      nb = D.eptr[e0];
+      nt = D.eptr[e0 + 1];
+    }
+  }
   for (int it = 0; it < wi.count; ++it) {
     const long long e = ((long long)wi.first + (long long)it * wi.stride) * kGroups + grp;
-    long long b = 0, t = 0;
-    if (e < m) {
-      b = D.eptr[e];
-      t = D.eptr[e + 1];
+    const long long b = nb, t = nt;
+    if (e < m)
       for (int i = gl; i < k; i += G) cnt[i] = 0;
-    }
     wave_lds_sync();
+    if (it + 1 < wi.count) {
+      const long long en = e + (long long)wi.stride * kGroups;
+      nb = nt = 0;
+      if (en < m) {
+        nb = D.eptr[en];
+        nt = D.eptr[en + 1];
+      }
+    }
     for (long long p0 = b + gl; p0 < t; p0 += kCountSlots * G) {
       int v[kCountSlots];
 #pragma unroll
