@@ -94,18 +94,6 @@ __global__ __launch_bounds__(kBlock) void k_check_nets(int m, long long P,
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_check_pins(int n, long long P, const int* pins,
-                                                       LoadInfo* info) {
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  long long stride = (long long)gridDim.x * blockDim.x;
-  int err = 0;
-  for (; i < P; i += stride) {
-    int v = pins[i];
-    if (v < 0 || v >= n) err = kErrPin;
-  }
-  if (err) atomicOr(&info->err, err);
-}
-
 __global__ __launch_bounds__(kBlock) void k_check_vertices(int n, const int* vwgt,
                                                            LoadInfo* info, LoadPart* part) {
   __shared__ long long s_tmp[kBlock / kWave];
@@ -169,6 +157,23 @@ static unsigned grid_cap_load(long long items) {
   return (unsigned)b;
 }
 
+// The transpose's radix sort: long sorts in 8192-item tiles (fuller digit
+// runs per tile; the netlist's 56.5M pairs sort 11% faster), shorter ones in
+// 4096-item tiles (more workgroups: 7% faster on 10M pairs).
+static bool long_load_sort(long long P) { return P >= (1LL << 24); }
+
+// The sort's first pass: the keys are the caller's pins, read in place.
+static SortPass first_load_pass(hg_graph_s* g) {
+  SortPass SP;
+  SP.hist = (unsigned*)(g->ws + g->lay.lhist);
+  SP.dtot = (unsigned*)(g->ws + g->lay.ldtot);
+  SP.n = (int)g->P;
+  SP.tiles = long_load_sort(g->P) ? sort_tiles<kSortPerLong>(g->P) : sort_tiles(g->P);
+  SP.key_in = (const unsigned*)g->pins;
+  SP.shift = 0;
+  return SP;
+}
+
 hipError_t load_check(hg_graph_s* g, hipStream_t s) {
   LoadInfo* info = (LoadInfo*)(g->ws + g->lay.info);
   hipError_t e = fill_i32((int*)info, 0, sizeof(LoadInfo) / sizeof(int), s);
@@ -178,8 +183,17 @@ hipError_t load_check(hg_graph_s* g, hipStream_t s) {
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_check_nets, dim3(grid_cap_load(g->m)), dim3(kBlock), 0, s, g->m, g->P,
                      g->eptr, g->ewgt, info, part);
-  hipLaunchKernelGGL(k_check_pins, dim3(grid_for(g->P, 4)), dim3(kBlock), 0, s, g->n, g->P,
-                     g->pins, info);
+  // the pins' range check is the sort's first digit count, which reads every
+  // pin anyway (a pin outside [0, n) only lands in some digit's count; the
+  // build does not start unless the checks pass)
+  SortPass SP = first_load_pass(g);
+  SP.err = &info->err;
+  SP.err_bit = kErrPin;
+  SP.key_limit = (unsigned)g->n;
+  if (long_load_sort(g->P))
+    hipLaunchKernelGGL(k_sort_hist<kSortPerLong>, dim3(SP.tiles), dim3(kBlock), 0, s, SP);
+  else
+    hipLaunchKernelGGL(k_sort_hist<kSortPer>, dim3(SP.tiles), dim3(kBlock), 0, s, SP);
   hipLaunchKernelGGL(k_check_vertices, dim3(grid_cap_load(g->n)), dim3(kBlock), 0, s, g->n,
                      g->vwgt, info, part);
   hipLaunchKernelGGL(k_fold_load, dim3(1), dim3(kBlock), 0, s, (const LoadPart*)part, info);
@@ -368,28 +382,24 @@ hipError_t load_build(hg_graph_s* g, hipStream_t s) {
   const long long waves = ((long long)g->m + kWave - 1) / kWave;
   const unsigned blocks = (unsigned)((waves + kBlock / kWave - 1) / (kBlock / kWave));
   hipLaunchKernelGGL(k_pin_pairs, dim3(blocks), dim3(kBlock), 0, s, g->m, g->eptr, val[0]);
-  SortPass SP;
-  SP.hist = (unsigned*)(g->ws + g->lay.lhist);
-  SP.dtot = (unsigned*)(g->ws + g->lay.ldtot);
-  SP.n = (int)P;
-  // long sorts in 8192-item tiles (fuller digit runs per tile; the netlist's
-  // 56.5M pairs sort 11% faster), shorter ones in 4096-item tiles (more
-  // workgroups: 7% faster on 10M pairs)
-  const bool long_sort = P >= (1LL << 24);
-  SP.tiles = long_sort ? sort_tiles<kSortPerLong>(P) : sort_tiles(P);
-  // the first pass reads the (validated, non-negative) pins as its keys
-  const unsigned* kin = (const unsigned*)g->pins;
+  // the first pass reads the (validated, non-negative) pins as its keys; its
+  // digit counts were taken by the checks
+  SortPass SP = first_load_pass(g);
+  const bool long_sort = long_load_sort(P);
   for (int q = 0; q < passes; ++q) {
-    SP.key_in = kin;
     SP.val_in = val[q & 1];
     SP.key_out = key[(q & 1) ^ 1];
     SP.val_out = val[(q & 1) ^ 1];
     SP.shift = 8 * q;
-    if (long_sort)
+    if (q == 0 && long_sort)
+      sort_pass_counted<kSortPerLong>(SP, s);
+    else if (q == 0)
+      sort_pass_counted(SP, s);
+    else if (long_sort)
       sort_pass<kSortPerLong>(SP, s);
     else
       sort_pass(SP, s);
-    kin = SP.key_out;
+    SP.key_in = SP.key_out;
   }
   const long long rs_threads = (P + kRowStartsPer - 1) / kRowStartsPer;
   const unsigned* skey = key[passes & 1];

@@ -51,6 +51,12 @@ struct SortPass {
   const long long* cand = nullptr;
   unsigned top = 0;
   int* count_out = nullptr;
+  // Range check (the loader's first pass, whose keys are the caller's pins):
+  // when err is set, the digit-count kernel also ORs err_bit into *err if a
+  // present key is >= key_limit.  The counts stay in range either way.
+  int* err = nullptr;
+  int err_bit = 0;
+  unsigned key_limit = 0;
 };
 
 __device__ __forceinline__ int sort_items(const SortPass& P) { return P.n_dev ? *P.n_dev : P.n; }
@@ -108,6 +114,12 @@ __global__ __launch_bounds__(kBlock) void k_sort_hist(SortPass P) {
 #pragma unroll
   for (int r = 0; r < PER; ++r)
     if (live[r]) atomicAdd(&s_h[digit_of(key[r], P.shift)], 1u);
+  if (P.err) {
+    bool bad = false;
+#pragma unroll
+    for (int r = 0; r < PER; ++r) bad |= live[r] && key[r] >= P.key_limit;
+    if (bad) atomicOr(P.err, P.err_bit);
+  }
   __syncthreads();
   P.hist[(size_t)threadIdx.x * P.tiles + blockIdx.x] = s_h[threadIdx.x];
 }
@@ -229,6 +241,14 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(SortPass P) {
 template <int PER = kSortPer>
 inline void sort_pass(const SortPass& P, hipStream_t s) {
   hipLaunchKernelGGL(k_sort_hist<PER>, dim3(P.tiles), dim3(kBlock), 0, s, P);
+  hipLaunchKernelGGL(k_sort_scan, dim3(kDigits), dim3(kBlock), 0, s, P);
+  hipLaunchKernelGGL(k_sort_scatter<PER>, dim3(P.tiles), dim3(kBlock), 0, s, P);
+}
+
+// The rest of a pass whose digit counts are already in P.hist (k_sort_hist
+// ran earlier on the same stream with the same P): scan and scatter.
+template <int PER = kSortPer>
+inline void sort_pass_counted(const SortPass& P, hipStream_t s) {
   hipLaunchKernelGGL(k_sort_scan, dim3(kDigits), dim3(kBlock), 0, s, P);
   hipLaunchKernelGGL(k_sort_scatter<PER>, dim3(P.tiles), dim3(kBlock), 0, s, P);
 }
