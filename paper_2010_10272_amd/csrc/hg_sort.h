@@ -125,16 +125,29 @@ __global__ __launch_bounds__(kBlock) void k_sort_hist(SortPass P) {
 }
 
 // One workgroup per digit: exclusive scan of its per-tile counts; total.
+// Each thread takes kSortScanPer consecutive counts per step (all loaded before
+// the first wait), so a 7,000-tile row is four workgroup scans, not 28.
+constexpr int kSortScanPer = 8;
+
 __global__ __launch_bounds__(kBlock) __attribute__((unused)) void k_sort_scan(SortPass P) {
   __shared__ long long s_tmp[kBlock / kWave];
   unsigned* row = P.hist + (size_t)blockIdx.x * P.tiles;
   long long carry = 0;
-  for (int b = 0; b < P.tiles; b += kBlock) {
-    const int i = b + threadIdx.x;
-    const long long v = i < P.tiles ? row[i] : 0;
+  for (int b = 0; b < P.tiles; b += kBlock * kSortScanPer) {
+    const int i0 = b + threadIdx.x * kSortScanPer;
+    unsigned c[kSortScanPer];
+#pragma unroll
+    for (int q = 0; q < kSortScanPer; ++q) c[q] = i0 + q < P.tiles ? row[i0 + q] : 0u;
+    long long sum = 0;
+#pragma unroll
+    for (int q = 0; q < kSortScanPer; ++q) sum += c[q];
     long long tot;
-    const long long ex = block_excl_scan64(v, s_tmp, &tot);
-    if (i < P.tiles) row[i] = (unsigned)(carry + ex);
+    long long run = carry + block_excl_scan64(sum, s_tmp, &tot);
+#pragma unroll
+    for (int q = 0; q < kSortScanPer; ++q) {
+      if (i0 + q < P.tiles) row[i0 + q] = (unsigned)run;
+      run += c[q];
+    }
     carry += tot;
   }
   if (threadIdx.x == 0) P.dtot[blockIdx.x] = (unsigned)carry;
