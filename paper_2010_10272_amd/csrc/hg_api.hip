@@ -278,17 +278,15 @@ hg_status hg_load_csr(int32_t n, int32_t m, int64_t P, const int64_t* eptr, cons
   if (e != hipSuccess) return bail(hip_fail(e, "incidence build"));
   // zero the round state kept in the workspace
   char* ws = g->ws;
-  e = hg::fill_u8((unsigned char*)(ws + lay.touched), 0, (long long)hg::touched_bytes(m), s);
-  if (e == hipSuccess)
-    e = hg::fill_i64((long long*)(ws + lay.hist), 0,
-                     (long long)hg::kHistReplicas * k_max * hg::kBuckets, s);
-  if (e == hipSuccess) e = hg::fill_i32((int*)(ws + lay.overflow), 0, k_max, s);
-  if (e == hipSuccess)
-    e = hg::fill_i32((int*)(ws + lay.ctr), 0, sizeof(hg::RoundCounters) / sizeof(int), s);
-  if (e == hipSuccess) e = hg::fill_i32((int*)(ws + lay.flags), 0, 64, s);
-  if (e == hipSuccess) e = hg::fill_i64((long long*)(ws + lay.red), 0, hg::kSlots, s);
-  if (e == hipSuccess)
-    e = hg::fill_i64((long long*)(ws + lay.bw_slots), 0, (long long)hg::kSlots * k_max, s);
+  hg::ZeroRanges Z;
+  Z.add(ws + lay.touched, (long long)hg::touched_bytes(m));
+  Z.add(ws + lay.hist, (long long)sizeof(long long) * hg::kHistReplicas * k_max * hg::kBuckets);
+  Z.add(ws + lay.overflow, (long long)sizeof(int) * k_max);
+  Z.add(ws + lay.ctr, (long long)sizeof(hg::RoundCounters));
+  Z.add(ws + lay.flags, (long long)sizeof(int) * 64);
+  Z.add(ws + lay.red, (long long)sizeof(long long) * hg::kSlots);
+  Z.add(ws + lay.bw_slots, (long long)sizeof(long long) * hg::kSlots * k_max);
+  e = hg::zero_ranges(Z, s);
   if (e != hipSuccess) return bail(hip_fail(e, "workspace init"));
   st = read_info(g, s);
   if (st != HG_OK) return bail(st);

@@ -495,8 +495,11 @@ static hipError_t launch_contract(hg_graph_s* g, const int* cluster, int* map, i
   const long long n = g->n, m = g->m;
 
   // 1-2. renumbering, map, coarse weights
-  hipError_t e = fill_u8(C.used, 0, n, s);
-  if (e == hipSuccess) e = fill_i64((long long*)C.cw, 0, n, s);
+  ZeroRanges Z;
+  Z.add(C.used, n);
+  Z.add((void*)C.cw, (long long)sizeof(long long) * n);
+  Z.add(C.big_count, (long long)sizeof(int));
+  hipError_t e = zero_ranges(Z, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_ct_mark, dim3(blocks_of(n)), dim3(kBlock), 0, s, C);
   exclusive_scan(UsedF{C.used}, n, C.rank, &sizes[0], B, s);
@@ -504,8 +507,6 @@ static hipError_t launch_contract(hg_graph_s* g, const int* cluster, int* map, i
   hipLaunchKernelGGL(k_ct_vweights, dim3(blocks_of(n)), dim3(kBlock), 0, s, C);
 
   // 3-4. per net: mapped, sorted, deduplicated pins, size, fingerprint
-  e = fill_i32(C.big_count, 0, 1, s);
-  if (e != hipSuccess) return e;
   const long long tiles = (g->P + kNetTile - 1) / kNetTile;
   hipLaunchKernelGGL(k_ct_tiles, dim3(blocks_of(m + 1)), dim3(kBlock), 0, s, C, tiles);
   long long sg = tiles < 8192 ? tiles : 8192;

@@ -312,6 +312,17 @@ hg_status check_k(hg_graph_s* g, int k);
   } while (0)
 
 // ---- launch helpers implemented in the .hip files (return hipError_t) ----
+// Up to kZeroRanges byte ranges of device memory, cleared by one launch of
+// zero_ranges (add() ignores empty ranges; more than kZeroRanges is a bug).
+constexpr int kZeroRanges = 8;
+struct ZeroRanges {
+  unsigned char* p[kZeroRanges];
+  long long bytes[kZeroRanges];
+  int count = 0;
+  void add(void* ptr, long long nbytes);
+};
+hipError_t zero_ranges(const ZeroRanges& R, hipStream_t s);
+
 hipError_t fill_i64(long long* p, long long v, long long count, hipStream_t s);
 hipError_t fill_u8(unsigned char* p, unsigned char v, long long count, hipStream_t s);
 hipError_t fill_i32(int* p, int v, long long count, hipStream_t s);

@@ -29,6 +29,27 @@ __global__ void k_fill_u8(unsigned char* p, unsigned char v, long long count) {
   for (; i < count; i += stride) p[i] = v;
 }
 
+// Byte ranges cleared by one launch: each range's unaligned head and tail
+// byte by byte, its middle in 16-byte stores.  One launch instead of one per
+// range matters where a call clears many small arrays (a few microseconds
+// of launch each).
+__global__ void k_zero_ranges(ZeroRanges R) {
+  const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (int r = 0; r < R.count; ++r) {
+    unsigned char* p = R.p[r];
+    const long long bytes = R.bytes[r];
+    long long head = (long long)((16 - ((uintptr_t)p & 15)) & 15);
+    if (head > bytes) head = bytes;
+    const long long words = (bytes - head) / 16;
+    const long long tail = head + words * 16;
+    for (long long i = tid; i < head; i += stride) p[i] = 0;
+    int4* w = reinterpret_cast<int4*>(p + head);
+    for (long long i = tid; i < words; i += stride) w[i] = make_int4(0, 0, 0, 0);
+    for (long long i = tail + tid; i < bytes; i += stride) p[i] = 0;
+  }
+}
+
 static unsigned grid_for(long long count, int per_thread = 1) {
   long long blocks = (count + (long long)kBlock * per_thread - 1) / ((long long)kBlock * per_thread);
   if (blocks < 1) blocks = 1;
@@ -46,6 +67,22 @@ hipError_t fill_i32(int* p, int v, long long count, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(count)), dim3(kBlock), 0, s, p, v, count);
   return hipGetLastError();
 }
+void ZeroRanges::add(void* ptr, long long nbytes) {
+  if (nbytes <= 0) return;
+  if (count == kZeroRanges) __builtin_trap();   // a caller listed too many ranges
+  p[count] = (unsigned char*)ptr;
+  bytes[count] = nbytes;
+  ++count;
+}
+
+hipError_t zero_ranges(const ZeroRanges& R, hipStream_t s) {
+  long long most = 0;
+  for (int r = 0; r < R.count; ++r) most = R.bytes[r] > most ? R.bytes[r] : most;
+  if (most == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_ranges, dim3(grid_for(most, 16)), dim3(kBlock), 0, s, R);
+  return hipGetLastError();
+}
+
 hipError_t fill_u8(unsigned char* p, unsigned char v, long long count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(count)), dim3(kBlock), 0, s, p, v, count);
@@ -176,10 +213,11 @@ static SortPass first_load_pass(hg_graph_s* g) {
 
 hipError_t load_check(hg_graph_s* g, hipStream_t s) {
   LoadInfo* info = (LoadInfo*)(g->ws + g->lay.info);
-  hipError_t e = fill_i32((int*)info, 0, sizeof(LoadInfo) / sizeof(int), s);
-  if (e != hipSuccess) return e;
   LoadPart* part = (LoadPart*)(g->ws + g->lay.lpart);
-  e = fill_i32((int*)part, 0, (long long)(sizeof(LoadPart) / sizeof(int)) * kLoadGrid, s);
+  ZeroRanges Z;
+  Z.add(info, sizeof(LoadInfo));
+  Z.add(part, (long long)sizeof(LoadPart) * kLoadGrid);
+  hipError_t e = zero_ranges(Z, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_check_nets, dim3(grid_cap_load(g->m)), dim3(kBlock), 0, s, g->m, g->P,
                      g->eptr, g->ewgt, info, part);

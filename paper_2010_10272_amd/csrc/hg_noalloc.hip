@@ -117,15 +117,15 @@ hg_status hg_lp_round_noalloc(hg_graph g, int32_t k, int64_t max_block_w, int32_
   hipStream_t s = (hipStream_t)stream;
   // The round kernels expect these zero on entry (and leave them zero); the
   // array keeps whatever the previous call on this GPU left, so clear them.
-  // Fill kernels rather than hipMemsetAsync, so a captured graph holds no
+  // One fill kernel rather than hipMemsetAsync, so a captured graph holds no
   // memset nodes.
-  hipError_t e = hg::fill_u8(d.touched, 0, (long long)hg::touched_bytes(g->m), s);
-  if (e == hipSuccess)
-    e = hg::fill_i64((long long*)d.hist, 0, (long long)hg::kHistReplicas * k * hg::kBuckets, s);
-  if (e == hipSuccess) e = hg::fill_i32(d.overflow, 0, k, s);
-  if (e == hipSuccess)
-    e = hg::fill_i32((int*)d.ctr, 0, (long long)(sizeof(hg::RoundCounters) / sizeof(int)), s);
-  if (e == hipSuccess) e = hg::fill_i64(d.bw_slots, 0, (long long)hg::kSlots * k, s);
+  hg::ZeroRanges Z;
+  Z.add(d.touched, (long long)hg::touched_bytes(g->m));
+  Z.add((void*)d.hist, (long long)sizeof(long long) * hg::kHistReplicas * k * hg::kBuckets);
+  Z.add(d.overflow, (long long)sizeof(int) * k);
+  Z.add(d.ctr, (long long)sizeof(hg::RoundCounters));
+  Z.add(d.bw_slots, (long long)sizeof(long long) * hg::kSlots * k);
+  hipError_t e = hg::zero_ranges(Z, s);
   if (e != hipSuccess) return hg::hip_fail(e, "scratch clear");
   hg::RoundPlan plan;
   hg::single_round_plan(d, plan);
