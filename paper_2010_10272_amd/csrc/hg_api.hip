@@ -106,8 +106,10 @@ hg_status timing_marks(hg_graph_s* g, hipStream_t s, hipEvent_t** marks) {
     g->timing_state = t;
   }
   while (t->events.size() < t->used + 4) {
+    // timing only: without the system-scope fence, recording a mark costs no
+    // cache writeback and invalidation between the phases it separates
     hipEvent_t e;
-    HG_TRY(hipEventCreate(&e), "hipEventCreate");
+    HG_TRY(hipEventCreateWithFlags(&e, hipEventDisableSystemFence), "hipEventCreateWithFlags");
     t->events.push_back(e);
   }
   *marks = t->events.data() + t->used;
