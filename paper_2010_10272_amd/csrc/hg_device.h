@@ -110,38 +110,6 @@ __device__ __forceinline__ int wave_append(unsigned int* counter, bool pred) {
   return pred ? base + __popcll(mask & (((unsigned long long)1 << lane_id()) - 1)) : -1;
 }
 
-// Load-balanced iteration over the union of up to 64 item ranges, one range
-// per lane ([begin, begin+len)).  Calls f(active, owner_lane, item) with all
-// lanes converged in every step, so f may use wave-wide operations.
-// s_excl / s_begin: 64 LDS slots private to this wave.
-template <typename F>
-__device__ __forceinline__ void wave_expand(long long begin, int len, int* s_excl,
-                                            long long* s_begin, F f) {
-  int lane = lane_id();
-  int incl = wave_incl_scan(len);
-  int total = __shfl(incl, kWave - 1);
-  s_excl[lane] = incl - len;
-  s_begin[lane] = begin;
-  wave_lds_sync();
-  for (int base = 0; base < total; base += kWave) {
-    int j = base + lane;
-    bool act = j < total;
-    int s = 0;
-    if (act) {
-      // largest s with s_excl[s] <= j
-      int lo = 0, hi = kWave - 1;
-      while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (s_excl[mid] <= j) lo = mid; else hi = mid - 1;
-      }
-      s = lo;
-    }
-    long long item = act ? s_begin[s] + (j - s_excl[s]) : 0;
-    f(act, s, item);
-  }
-  wave_lds_sync();
-}
-
 // A select candidate: gain in the high word, target block in the low word.
 __device__ __forceinline__ long long pack_cand(int gain, int target) {
   return ((long long)gain << 32) | (unsigned)target;

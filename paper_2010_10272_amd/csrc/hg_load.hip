@@ -246,12 +246,15 @@ constexpr int kBigRowGrid = 256;   // workgroups striding over the long rows
 // atomics anywhere (so nothing depends on timing).  Row starts come from
 // where the sorted keys change.
 
-// Each wave expands the pins of 64 consecutive nets, load-balanced, into the
-// net id of every pin position: the pairs' values (their keys are the pins
-// themselves, which the first sort pass reads in place).
+// Each wave expands the pins of 64 consecutive nets into the net id of every
+// pin position: the pairs' values (their keys are the pins themselves, which
+// the first sort pass reads in place).  The nets' pins form one contiguous
+// run; it is written 64 positions per step, and a position's net is the
+// count of nets starting at or before it: each net flags its first position
+// of the step in LDS and one ballot gives every lane the count (nets are
+// non-empty, so their starts are distinct).
 __global__ void k_pin_pairs(int m, const long long* eptr, int* val) {
-  __shared__ int s_excl[kBlock / kWave][kWave];
-  __shared__ long long s_begin[kBlock / kWave][kWave];
+  __shared__ unsigned char s_start[kBlock / kWave][kWave];
   const int w = threadIdx.x / kWave, lane = lane_id();
   const long long wave_global = (long long)blockIdx.x * (kBlock / kWave) + w;
   const long long e = wave_global * kWave + lane;
@@ -261,10 +264,25 @@ __global__ void k_pin_pairs(int m, const long long* eptr, int* val) {
     b = eptr[e];
     len = (int)(eptr[e + 1] - b);
   }
+  const int incl = wave_incl_scan(len);
+  const int total = __shfl(incl, kWave - 1);
+  const int first = incl - len;                  // this net's offset in the run
+  const long long run = __shfl(b, 0);            // the run starts at the wave's first net
   const int first_net = (int)(wave_global * kWave);
-  wave_expand(b, len, s_excl[w], s_begin[w], [&](bool act, int owner, long long p) {
-    if (act) val[p] = first_net + owner;
-  });
+  const unsigned long long upto = ~0ull >> (kWave - 1 - lane);   // lanes 0 .. this one
+  s_start[w][lane] = 0;
+  wave_lds_sync();
+  int before = 0;                                // nets starting before this step
+  for (int base = 0; base < total; base += kWave) {
+    if (len > 0 && first >= base && first < base + kWave) s_start[w][first - base] = 1;
+    wave_lds_sync();
+    const unsigned long long starts = __ballot(s_start[w][lane] != 0);
+    s_start[w][lane] = 0;
+    wave_lds_sync();
+    if (base + lane < total)
+      val[run + base + lane] = first_net + before + __popcll(starts & upto) - 1;
+    before += __popcll(starts);
+  }
 }
 
 // vptr[v] = the first sorted position with key >= v; vptr[n] = P.  A pair
