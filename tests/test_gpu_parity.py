@@ -298,6 +298,29 @@ def test_determinism_repeat(H):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("nets,bad_at,bad", [
+    (2, 3, -1),                   # negative pin, one tile
+    (30000, 59999, 60000),        # pin = n in the last of 15 tiles
+    (30000, 12345, -7),           # negative pin in a middle tile
+    ((1 << 23) + 3, -1, 1 << 30),  # 2^24 + 6 pins: the long-sort tiles
+])
+def test_pin_range_check(H, nets, bad_at, bad):
+    """The pins' range check rides on the first radix pass's digit count:
+    a single bad pin anywhere, in either tile size, rejects the load."""
+    eptr = np.arange(0, 2 * nets + 1, 2, dtype=np.int64)
+    n = 2 * nets
+    pins = np.arange(n, dtype=np.int32)
+    good = pins[bad_at]
+    pins[bad_at] = bad
+    with pytest.raises(H.HgError) as ei:
+        H.hg_load_csr(n, eptr, pins, k_max=2)
+    assert ei.value.code == H.HG_ERR_INVALID
+    assert "outside [0, n)" in str(ei.value)
+    pins[bad_at] = good                               # the same load, valid: accepted
+    g = H.hg_load_csr(n, eptr, pins, k_max=2)
+    g.free()
+
+
 def test_invalid_inputs_raise(H):
     import torch
     eptr = np.array([0, 2, 4], np.int64)
