@@ -299,8 +299,10 @@ hg_status hg_refine_cached(hg_graph g, int32_t k, double eps, int32_t rounds, in
 
 /* Per-phase timing of label-propagation rounds, off by default.  While on,
  * every round enqueued outside a stream capture (hg_lp_round, and hg_refine
- * with use_graph = 0) records four HIP events on its own stream around the
- * three phases; a recorded hipGraph is never timed. */
+ * with use_graph = 0) records HIP events on its own stream around the three
+ * phases (four per round; inside one refine call a round starts at the
+ * previous round's end event, so three); a recorded hipGraph is never
+ * timed. */
 hg_status hg_timing_enable(hg_graph g, int32_t enable);
 
 /* Wait for the recorded events, add each phase's total duration in

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <new>
+#include <array>
 #include <vector>
 
 #include "hg_internal.h"
@@ -76,24 +77,31 @@ hg_status read_info(hg_graph_s* g, hipStream_t s) {
   return HG_OK;
 }
 
-// Events of timed rounds: groups of four (round start, after select, after
-// approve/apply, round end), recorded in order; `used` groups are pending.
+// Events of timed rounds.  Each round has four marks (round start, after
+// select, after approve/apply, round end); `spans` keeps them for the
+// elapsed times, `marks` the handles the launch records (the start left null
+// when it is the previous round's end, which the launch then need not
+// record again: each recorded mark costs a few microseconds of idle GPU).
+// `pool` holds the events, reused after every collect.
 struct TimingState {
-  std::vector<hipEvent_t> events;
-  size_t used = 0;
+  std::vector<hipEvent_t> pool;
+  size_t next = 0;
+  std::vector<std::array<hipEvent_t, 4>> marks, spans;
 };
 
 void release_timing(hg_graph_s* g) {
   TimingState* t = (TimingState*)g->timing_state;
   if (!t) return;
-  for (hipEvent_t e : t->events) (void)hipEventDestroy(e);
+  for (hipEvent_t e : t->pool) (void)hipEventDestroy(e);
   delete t;
   g->timing_state = nullptr;
 }
 
-// Four events for the next round, or *marks = nullptr when timing is off or
-// the stream is being captured.
-hg_status timing_marks(hg_graph_s* g, hipStream_t s, hipEvent_t** marks) {
+// The marks of the next round, or *marks = nullptr when timing is off or the
+// stream is being captured.  With chain, the caller has enqueued nothing on
+// the stream since the previous round's end mark, which then also starts
+// this round.
+hg_status timing_marks(hg_graph_s* g, hipStream_t s, hipEvent_t** marks, bool chain = false) {
   *marks = nullptr;
   if (!g->timing) return HG_OK;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -105,15 +113,24 @@ hg_status timing_marks(hg_graph_s* g, hipStream_t s, hipEvent_t** marks) {
     if (!t) return fail(HG_ERR_INVALID, "out of host memory");
     g->timing_state = t;
   }
-  while (t->events.size() < t->used + 4) {
+  const bool shared = chain && !t->spans.empty();
+  const size_t take = shared ? 3 : 4;
+  while (t->pool.size() < t->next + take) {
     // timing only: without the system-scope fence, recording a mark costs no
     // cache writeback and invalidation between the phases it separates
     hipEvent_t e;
     HG_TRY(hipEventCreateWithFlags(&e, hipEventDisableSystemFence), "hipEventCreateWithFlags");
-    t->events.push_back(e);
+    t->pool.push_back(e);
   }
-  *marks = t->events.data() + t->used;
-  t->used += 4;
+  std::array<hipEvent_t, 4> rec, span;
+  for (int i = 0; i < 4; ++i) rec[i] = nullptr;
+  for (size_t i = 0; i < take; ++i) rec[4 - take + i] = t->pool[t->next + i];
+  span = rec;
+  if (shared) span[0] = t->spans.back()[3];
+  t->next += take;
+  t->marks.push_back(rec);
+  t->spans.push_back(span);
+  *marks = t->marks.back().data();
   return HG_OK;
 }
 
@@ -397,7 +414,7 @@ static hipError_t enqueue_refine(hg_graph g, int k, long long lmax, int rounds, 
   hg::RoundPlan plan;
   for (int r = 0; r < rounds && e == hipSuccess; ++r) {
     hipEvent_t* marks = nullptr;
-    if (timing_marks(g, s, &marks) != HG_OK) return hipErrorUnknown;
+    if (timing_marks(g, s, &marks, r > 0) != HG_OK) return hipErrorUnknown;
     d.stats = stats + r;
     hg::single_round_plan(d, plan);
     e = hg::launch_round(plan, 0, s, marks);
@@ -529,7 +546,7 @@ hg_status hg_refine_cached(hg_graph g, int32_t k, double eps, int32_t rounds, in
   hg::RoundPlan plan;
   for (int r = 0; r < rounds; ++r) {
     hipEvent_t* marks = nullptr;
-    st = timing_marks(g, s, &marks);
+    st = timing_marks(g, s, &marks, r > 0);
     if (st != HG_OK) return st;
     d.stats = stats + r;
     hg::cached_round_plan(d, plan);
@@ -547,18 +564,19 @@ hg_status hg_timing_enable(hg_graph g, int32_t enable) {
 hg_status hg_timing_collect(hg_graph g, double* ms, int64_t* rounds) {
   if (!g || !ms || !rounds) return fail(HG_ERR_INVALID, "graph handle, ms and rounds must be non-NULL");
   TimingState* t = (TimingState*)g->timing_state;
-  if (!t || t->used == 0) return HG_OK;
-  for (size_t i = 0; i < t->used; i += 4) {
-    HG_TRY(hipEventSynchronize(t->events[i + 3]), "hipEventSynchronize");
+  if (!t || t->spans.empty()) return HG_OK;
+  for (const auto& span : t->spans) {
+    HG_TRY(hipEventSynchronize(span[3]), "hipEventSynchronize");
     for (int p = 0; p < HG_NUM_PHASES; ++p) {
       float x = 0.0f;
-      HG_TRY(hipEventElapsedTime(&x, t->events[i + p], t->events[i + p + 1]),
-             "hipEventElapsedTime");
+      HG_TRY(hipEventElapsedTime(&x, span[p], span[p + 1]), "hipEventElapsedTime");
       ms[p] += x;
     }
     *rounds += 1;
   }
-  t->used = 0;
+  t->marks.clear();
+  t->spans.clear();
+  t->next = 0;
   return HG_OK;
 }
 

@@ -1442,7 +1442,8 @@ hipError_t launch_round(const RoundPlan& plan, int round, hipStream_t s, hipEven
 // Select, thresholds, tiles and approve (+ apply unless the descriptor asks
 // for marks only).
 hipError_t launch_round_front(const RoundPlan& plan, hipStream_t s, hipEvent_t* marks) {
-  if (marks) (void)hipEventRecord(marks[0], s);
+  // a null start mark: the previous round's end mark starts this round
+  if (marks && marks[0]) (void)hipEventRecord(marks[0], s);
   for (const PlanLaunch& pl : plan.select)
     hipLaunchKernelGGL((SelectKernel)pl.kernel, dim3(pl.grid), dim3(kBlock), 0, s, pl.L);
   for (const PlanLaunch& pl : plan.heavy)
