@@ -19,7 +19,7 @@ matrix, about 10M pins, k = 8 and 64) and on the tiny instance (n = m =
 rebalancing and contraction legs.  For each plain workload: the select
 kernel's and the whole round's algorithmic bandwidth against the 8 TB/s HBM
 peak (round records over the library's per-phase HIP events, recorded on the
-kernels' stream during the timed steps), per-round latency p50/p99, the
+kernels' stream during the last timed step), per-round latency p50/p99, the
 recorded-hipGraph refine time, and the CPU oracle on a bounded sample of the
 same rounds, whose records and partitions must equal the timed run's.
 
@@ -859,13 +859,17 @@ def plain_workload(args, H, dev, inst, ks, rounds, label, cpu_plan, roofline=Tru
     phase_ms = {p: 0.0 for p in H.HG_PHASES}
     timed_rounds = [0]
 
-    def step():
+    def step(marks):
         # the step's graph handle is returned, not freed: reading its phase
         # marks and freeing it wait for the GPU, which the timed loop leaves
         # to after its last step (the next load reuses the same buffers in
-        # stream order)
+        # stream order).  Phase marks (HIP events around the select, the
+        # approval and the finalize of every round) are recorded when asked:
+        # on the last timed step, a sample of the same work, so that the
+        # marks' own cost (a few microseconds of idle GPU each) stays out of
+        # the other steps
         g = H.hg_load_csr(n, eptr, pins, c, w, k_max=kmax, device=dev, out=bufs)
-        H.hg_timing_enable(g, True)
+        H.hg_timing_enable(g, marks)
         for k in ks:
             st = states[k]
             st.part.copy_(parts[k])
@@ -884,13 +888,13 @@ def plain_workload(args, H, dev, inst, ks, rounds, label, cpu_plan, roofline=Tru
 
     print("%s: warmup ..." % label, file=sys.stderr, flush=True)
     for _ in range(args.warmup):
-        retire(step(), False)
+        retire(step(True), False)
     torch.cuda.synchronize()
     print("%s: timing %d steps ..." % (label, args.steps), file=sys.stderr, flush=True)
     e0, e1 = _events(torch)
     t0 = time.perf_counter()
     e0.record()
-    done = [step() for _ in range(args.steps)]
+    done = [step(i == args.steps - 1) for i in range(args.steps)]
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -908,7 +912,7 @@ def plain_workload(args, H, dev, inst, ks, rounds, label, cpu_plan, roofline=Tru
 
     # rooflines: bytes of the step's rounds (records) over the phase times
     launches = len(ks) * rounds
-    assert timed_rounds[0] == launches * args.steps, "phase timing lost rounds"
+    assert timed_rounds[0] == launches, "phase timing lost rounds"
     phase_bytes = {p: sum(f(s, n, k) for k in ks for s in per_k[k]) / launches
                    for p, f in PHASE_BYTES.items()}
     phase_avg = {p: phase_ms[p] / timed_rounds[0] for p in H.HG_PHASES}
