@@ -1146,6 +1146,9 @@ def main():
                     help="also run one plain device-to-device copy of MIB MiB (a known "
                          "byte count for scaling HBM traffic counters)")
     args = ap.parse_args()
+    if args.steps < 1 or args.warmup < 0:
+        print("bench.py needs --steps >= 1 and --warmup >= 0", file=sys.stderr)
+        sys.exit(2)
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)

@@ -22,6 +22,12 @@ def test_more_than_one_gpu_is_refused():
     assert r.stdout == ""
 
 
+def test_no_timed_steps_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "0"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "--steps" in r.stderr
+
+
 def test_phase_bytes_by_hand():
     st = {"boundary": 2, "active_pins": 5, "candidates": 1, "approved": 1, "moved_pins": 3,
           "touched_nets": 4, "touched_pins": 9}
